@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of restarted sGMRES (k-truncated Arnoldi, sparse sign sketch) on one MI355X.
+
+One step = one complete solve from x0 = 0 to relative residual 1e-10 of the
+full-size workload: 2D convection-diffusion on a 1024 x 1024 grid
+(n = 1,048,576, nnz = 5,238,784, beta = (50, 20)), b ~ N(0, 1) (seed 0),
+d = 200, k = 4, s = 400, zeta = 8, FP64 throughout.  Inputs are resident in HBM
+before the timed region.
+
+Prints ONE JSON line with the metric plus:
+  roofline      basis kernel (the dominant kernel): algorithmic HBM bytes per
+                launch / average launch time, measured with HIP events on the
+                solve's stream inside the timed region
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload on
+                this host, scaled to solves/s
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sGMRES solves/s at rel. residual 1e-10 (n=1M, d=200); HBM GB/s vs peak"
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def basis_launch_bytes(n: int, nnz: int, dc: float) -> float:
+    """Compulsory HBM bytes of one basis-kernel launch building dc columns.
+
+    Per column: CSR arrays (12 B per nonzero + 4 B per row pointer), the gathered
+    input column b_j (8n); per new column the written b_{j+1} (8n); at start the
+    residual read and b_1 written (16n).  The truncation window, m_j, w and the
+    sketch pattern stay on chip; block partial sums (a few kB per step) are not
+    counted."""
+    per_step = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n
+    return dc * per_step + 8.0 * n * (dc - 1) + 16.0 * n
+
+
+def cpu_baseline(A, f, p, cycles_per_solve: float, sample_cols: int) -> dict:
+    """Time the oracle on one bounded sample of a cycle and scale to solves/s."""
+    import numpy as np
+
+    import oracle
+
+    n = A.n
+    d, k, s, zeta = p["d"], p["k"], p["s"], p["zeta"]
+    t0 = time.perf_counter()
+    r, _ = oracle.residual(A, f, np.zeros(n))
+    t_res = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cyc = oracle.arnoldi_cycle(A, r, sample_cols, k, s, zeta, p["seed"], 0)
+    t_basis = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    C = cyc["SAB"][:, :sample_cols]
+    C = np.column_stack([C] + [rng.standard_normal((s, 1)) for _ in range(d - sample_cols)])
+    t0 = time.perf_counter()
+    oracle.sketched_lsq(C, cyc["g"])
+    t_lsq = time.perf_counter() - t0
+    Bd = rng.standard_normal((d, n))  # row q = basis column q (column-major n x d)
+    y = rng.standard_normal(d)
+    x = np.zeros(n)
+    L = oracle.lib()
+    t0 = time.perf_counter()
+    L.oracle_basis_combine(n, d, Bd, y, x)
+    t_comb = time.perf_counter() - t0
+    per_cycle = t_res + t_basis * (d / sample_cols) + t_lsq + t_comb
+    per_solve = per_cycle * cycles_per_solve + t_res
+    return {
+        "value": 1.0 / per_solve,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one residual, {sample_cols} of {d} basis columns of cycle 0, one {s}x{d} sketched "
+                   f"least-squares solve and one {n}x{d} combine at full size; basis time scaled by "
+                   f"{d}/{sample_cols}, cycle time by {cycles_per_solve:.1f} cycles per solve (measured "
+                   f"on the GPU run); {per_solve:.1f} s per solve, sample took "
+                   f"{t_res + t_basis + t_lsq + t_comb:.1f} s"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
+    ap.add_argument("--workload", default="cd1024")
+    ap.add_argument("--cpu-sample-cols", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--rows-per-thread", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the row-block sharding design is described in DESIGN.md).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2111_00113_amd as sg
+    import synth
+
+    log(f"building workload {args.workload}")
+    A, f, p = synth.workload(args.workload)
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    dA = sg.DeviceCSR.from_host(A, dev)
+    fb = torch.as_tensor(f, dtype=torch.float64, device=dev)
+    x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    d, k, s = p["d"], p["k"], p["s"]
+
+    def solve(profile: bool) -> dict:
+        x.zero_()
+        rc, info = sg.sgmres_solve(dA, fb, x, d, k, s, p["seed"], p["tol"], p["restarts"], zeta=p["zeta"],
+                                   profile=profile, block_size=args.block_size,
+                                   rows_per_thread=args.rows_per_thread)
+        if rc != sg.OK:
+            raise RuntimeError(f"solve did not converge: {info}")
+        return info
+
+    for w in range(args.warmup):
+        info = solve(False)
+        log(f"warmup {w}: cycles={info['cycles']} relres={info['relres']:.3e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(solve(True))
+        log(f"step {i}: cycles={infos[-1]['cycles']} relres={infos[-1]['relres']:.3e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    cycles = sum(i["cycles"] for i in infos)
+    steps = sum(i["steps"] for i in infos)
+    t_basis = sum(i["t_basis_ms"] for i in infos)
+    t_lsq = sum(i["t_lsq_ms"] for i in infos)
+    t_comb = sum(i["t_combine_ms"] for i in infos)
+    t_res = sum(i["t_residual_ms"] for i in infos)
+    dc_avg = steps / cycles
+    launch_ms = t_basis / cycles
+    launch_bytes = basis_launch_bytes(A.n, A.nnz, dc_avg)
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    # x after the last timed solve: confirm the residual with an independent host SpMV
+    xr = x.cpu().numpy()
+    relres_host = float(np.linalg.norm(f - A.to_scipy() @ xr) / np.linalg.norm(f))
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: 2D convection-diffusion 5-point, n={A.n}, nnz={A.nnz}, "
+                         f"d={d}, k={k}, s={s}, zeta={p['zeta']}, tol={p['tol']:g}, b~N(0,1) seed 0, x0=0"),
+            "n": A.n,
+            "nnz": A.nnz,
+            "d": d,
+            "k": k,
+            "s": s,
+            "zeta": p["zeta"],
+            "tol": p["tol"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "kernel": "arnoldi_kernel (spmv_truncarnoldi)",
+            "bytes_per_launch": launch_bytes,
+            "avg_launch_ms": launch_ms,
+        },
+        "cycles_per_solve": cycles / args.steps,
+        "relres_final": infos[-1]["relres"],
+        "relres_host_check": relres_host,
+        "gpu_ms_per_solve": {
+            "basis": t_basis / args.steps,
+            "lsq": t_lsq / args.steps,
+            "combine": t_comb / args.steps,
+            "residual": t_res / args.steps,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(A, f, p, cycles / args.steps, args.cpu_sample_cols)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,190 @@
+/*
+ * sgmres.h -- C ABI of the MI355X (gfx950) sketched GMRES library.
+ *
+ * Method: Y. Nakatsukasa and J. A. Tropp, "Fast & accurate randomized
+ * algorithms for linear systems and eigenvalue problems", arXiv:2111.00113,
+ * Algorithm 1 (sGMRES + k-truncated Arnoldi) with restarting (Section 3.5).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (HIP) unless stated otherwise and are
+ *     owned by the caller; the library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is enqueued on it.  Entry points that return host-side
+ *     results (status codes, info structs, host scalars) synchronise `stream`
+ *     before returning.
+ *   - Dense matrices are column-major with the stated leading dimension.
+ *   - Indices are int32 (n < 2^31, nnz < 2^31).  CSR column indices need not
+ *     be sorted within a row.
+ *   - Internal workspace is allocated by the library on first use on each
+ *     device and cached (grow-only) until sgmres_release_workspace().
+ *     Concurrent calls on one device from several host threads are not
+ *     supported.
+ *   - Return codes: SGMRES_OK (0) on success, SGMRES_NOT_CONVERGED (1) when a
+ *     solve ran out of restarts (x then holds the last iterate), or a negative
+ *     SGMRES_E* code.  Nothing is written to outputs on SGMRES_EINVAL.
+ *
+ * Readings of points the paper leaves open (listed with the library design):
+ *   sketch columns scaled by 1/sqrt(zeta); real +-1 signs; zeta distinct rows
+ *   per column drawn by rejection from Philox4x32-10; classical Gram-Schmidt
+ *   twice against the window; unpivoted Householder QR of S A B; the longest
+ *   prefix with max|T_ii|/min|T_ii| <= kappa_max is used; x <- x + B y.
+ */
+#ifndef SGMRES_H
+#define SGMRES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGMRES_OK 0
+#define SGMRES_NOT_CONVERGED 1
+#define SGMRES_EINVAL (-1)     /* bad argument (null pointer, size out of range) */
+#define SGMRES_ECSR (-2)       /* malformed CSR (row_ptr not monotone, column out of range) */
+#define SGMRES_ENOMEM (-3)     /* device or pinned-host allocation failed */
+#define SGMRES_EHIP (-4)       /* a HIP runtime call failed */
+#define SGMRES_ENONFINITE (-5) /* NaN/Inf met in b, x0, A or a residual norm */
+#define SGMRES_ETIMEOUT (-6)   /* an in-kernel grid barrier exceeded its wait limit */
+
+#define SGMRES_FLAG_KAPPA_TRUNC 1 /* a cycle used a prefix of its basis (kappa guard) */
+#define SGMRES_FLAG_BREAKDOWN 2   /* a cycle's basis ended early (invariant subspace) */
+
+/* Square sparse matrix in CSR form; all arrays on the device. */
+typedef struct {
+    int64_t n;              /* order, 1 <= n < 2^31 */
+    int64_t nnz;            /* row_ptr[n] */
+    const int32_t *row_ptr; /* n + 1 entries, row_ptr[0] = 0, nondecreasing */
+    const int32_t *col_idx; /* nnz entries in [0, n) */
+    const double *val;      /* nnz entries */
+} sgmres_csr_t;
+
+/* Host-side solve report (pointer may be NULL). */
+typedef struct {
+    int32_t cycles;     /* basis cycles run (restarts + 1 at most) */
+    int32_t steps;      /* basis columns built, summed over cycles */
+    int32_t d_eff_last; /* columns used by the last cycle's least-squares solve */
+    int32_t flags;      /* OR of SGMRES_FLAG_* over all cycles */
+    double relres;      /* final true relative residual |b - A x| / |b| */
+    double rest_est;    /* last cycle's sketched residual estimate / |b| (Section 3.2) */
+    double kappa_est;   /* last cycle's max|T_ii| / min|T_ii| over the used prefix */
+    /* GPU time per kernel class, summed over the solve, measured with HIP events
+     * on `stream`; filled only when sgmres_options_t.profile is nonzero. */
+    double t_residual_ms; /* residual r = b - A x and its norm */
+    double t_basis_ms;    /* basis + sketch kernel (one launch per cycle) */
+    double t_lsq_ms;      /* sketched least squares */
+    double t_combine_ms;  /* x <- x + B y */
+} sgmres_info_t;
+
+/* Options of sgmres_solve_ex; zero-initialise for the defaults. */
+typedef struct {
+    int32_t zeta;       /* nonzeros per sketch column; 0 -> 8; must be <= s and <= 32 */
+    double kappa_max;   /* condition guard on T (Sections 3.4, 5.3); 0 -> 1e14 */
+    int32_t transposed; /* nonzero: solve A^T x = b */
+    int32_t block_size; /* basis-kernel workgroup size, 256 / 512 / 1024; 0 -> auto */
+    int32_t rows_per_thread; /* basis-kernel rows per thread, 1 / 2 / 4 / 8; 0 -> auto */
+    int32_t profile;    /* nonzero: fill the t_*_ms fields of sgmres_info_t */
+    int32_t reserved[2];
+} sgmres_options_t;
+
+/*
+ * Restarted sGMRES with k-truncated Arnoldi (Algorithm 1; restarts Section 3.5).
+ * Solves A x = b.
+ *   A        CSR matrix (struct on the host, arrays on the device)
+ *   b        n right-hand side
+ *   x        n; in: initial guess x0, out: approximate solution
+ *   d        basis columns per cycle, 1 <= d <= min(n, 1024)
+ *   k        truncation window (previous columns orthogonalised against), k >= 1;
+ *            k >= d-1 gives full Arnoldi
+ *   s        sketch rows, d + 1 <= s <= 4096 (the paper recommends s = 2(d+1))
+ *   seed     sketch key; cycle c uses Philox counter word 2 = c
+ *   tol      stop when |b - A x|_2 / |b|_2 <= tol (true residual), tol >= 0
+ *   restarts maximum additional cycles (total cycles <= restarts + 1), >= 0
+ *   info     host pointer, may be NULL
+ * Returns SGMRES_OK, SGMRES_NOT_CONVERGED or an SGMRES_E* code.  b = 0 gives
+ * x = 0 and SGMRES_OK.
+ */
+int sgmres_solve(const sgmres_csr_t *A, const double *b, double *x, int d, int k, int s,
+                 uint64_t seed, double tol, int restarts, sgmres_info_t *info, void *stream);
+
+/* As sgmres_solve, for the transposed system A^T x = b.  CSR(A^T) is built on
+ * the device (sgmres_csr_transpose) into library workspace on each call. */
+int sgmres_solve_transposed(const sgmres_csr_t *A, const double *b, double *x, int d, int k,
+                            int s, uint64_t seed, double tol, int restarts,
+                            sgmres_info_t *info, void *stream);
+
+/* As sgmres_solve with options (NULL = defaults). */
+int sgmres_solve_ex(const sgmres_csr_t *A, const double *b, double *x, int d, int k, int s,
+                    uint64_t seed, double tol, int restarts, const sgmres_options_t *opts,
+                    sgmres_info_t *info, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Hot-path steps, callable one by one (they compose into sgmres_solve).
+ * ------------------------------------------------------------------------- */
+
+/* Sparse sign embedding pattern (Section 2.3.2).  For columns i = i0 .. i0+count-1
+ * writes rows[(i-i0)*zeta + t] in [0, s) (distinct within a column) and
+ * signs[(i-i0)*zeta + t] in {-1, +1}, t in acceptance order.  Column i uses
+ * Philox4x32-10 with key (lo32(seed), hi32(seed)) and counters
+ * (lo32(i), hi32(i), cycle, t), t = 0, 1, ...; each 32-bit output word u, in
+ * order, proposes row floor(u*s/2^32) with sign -1 iff u is odd; proposals
+ * repeating an accepted row are discarded.  1 <= zeta <= min(s, 32). */
+int sgmres_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s,
+                          int zeta, int32_t *rows, int8_t *signs, void *stream);
+
+/* g = S v (Section 2.3.2, scale 1/sqrt(zeta)): v has n entries, g has s. */
+int sgmres_sketch_apply(int64_t n, const double *v, uint64_t seed, uint32_t cycle, int s,
+                        int zeta, double *g, void *stream);
+
+/* r = f - A x and its 2-norm (Algorithm 1, residual step).  r has n entries
+ * (device); *norm (host) receives |r|_2. */
+int sgmres_residual(const sgmres_csr_t *A, const double *f, const double *x, double *r,
+                    double *norm, void *stream);
+
+/* One cycle of basis generation and sketching (Algorithm 1, basis loop;
+ * truncated-Arnoldi recurrence of Section 1.2.2 with two classical
+ * Gram-Schmidt passes).  From the residual r (n, nonzero):
+ *   B   n x d, leading dim ldb >= n: columns b_1 .. b_dc (b_1 = r/|r|)
+ *   SB  s x d (ld s):  S b_j          SAB s x d (ld s):  S A b_j
+ *   H   (k+1) x d (ld k+1): column j holds the summed Gram-Schmidt coefficients
+ *       against the window, newest column first, then |w| in row k
+ *   g   s: S r
+ * *dc (host) receives the number of columns built (< d after breakdown) and
+ * *flags (host) ORs in SGMRES_FLAG_BREAKDOWN.  Requires 1 <= d <= 1024,
+ * 1 <= k <= 1024, 1 <= s <= 4096, 1 <= zeta <= min(s, 32).  H is cleared first;
+ * column d-1 (and columns past a breakdown) stay zero. */
+int sgmres_arnoldi_cycle(const sgmres_csr_t *A, const double *r, int d, int k, int s, int zeta,
+                         uint64_t seed, uint32_t cycle, double *B, int64_t ldb, double *SB,
+                         double *SAB, double *H, double *g, int *dc, int *flags, void *stream);
+
+/* Sketched least squares (Algorithm 1 solve step; Section 3.3).  C (s x dc,
+ * ld s) is overwritten by its Householder factorisation (T in the upper
+ * triangle), g (s) by Q^T g.  y (d_eff entries) solves
+ * T[:d_eff,:d_eff] y = (Q^T g)[:d_eff], where d_eff is the longest prefix with
+ * max|T_ii|/min|T_ii| <= kappa_max.  Host outputs: *d_eff, *rest = |(Q^T g)[d_eff:]|,
+ * *kappa = the ratio at d_eff; *flags ORs in SGMRES_FLAG_KAPPA_TRUNC when
+ * d_eff < dc.  0 <= dc <= min(s, 1024), s <= 32767. */
+int sgmres_sketched_lsq(int s, int dc, double *C, double *g, double kappa_max, double *y,
+                        int *d_eff, double *rest, double *kappa, int *flags, void *stream);
+
+/* x <- x + B[:, :d_eff] y (Section 3.3, solution step).  B n x d_eff, ld ldb. */
+int sgmres_basis_combine(int64_t n, int d_eff, const double *B, int64_t ldb, const double *y,
+                         double *x, void *stream);
+
+/* CSR(A^T) on the device: t_row_ptr (n+1), t_col_idx (nnz), t_val (nnz) are
+ * caller-allocated device arrays; each output row lists its columns in
+ * ascending order. */
+int sgmres_csr_transpose(const sgmres_csr_t *A, int32_t *t_row_ptr, int32_t *t_col_idx,
+                         double *t_val, void *stream);
+
+/* Frees the cached workspace of every device. */
+void sgmres_release_workspace(void);
+
+/* Library version string (static storage). */
+const char *sgmres_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGMRES_H */

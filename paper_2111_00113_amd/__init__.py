@@ -1,0 +1,29 @@
+"""Sketched GMRES (sGMRES) for AMD MI355X (gfx950).
+
+Nakatsukasa & Tropp, "Fast & accurate randomized algorithms for linear systems
+and eigenvalue problems" (arXiv:2111.00113), Algorithm 1 with restarting, as
+hand-written HIP kernels behind a C ABI (include/sgmres.h).  This package is the
+Python binding; the library is loaded lazily on first use.
+"""
+
+from .sgmres import (  # noqa: F401
+    DeviceCSR,
+    SGMRESError,
+    OK,
+    NOT_CONVERGED,
+    FLAG_BREAKDOWN,
+    FLAG_KAPPA_TRUNC,
+    LIB_PATH,
+    lib,
+    sgmres_solve,
+    sgmres_solve_transposed,
+    sgmres_sketch_pattern,
+    sgmres_sketch_apply,
+    sgmres_residual,
+    sgmres_arnoldi_cycle,
+    sgmres_sketched_lsq,
+    sgmres_basis_combine,
+    sgmres_csr_transpose,
+    sgmres_release_workspace,
+    sgmres_version,
+)

@@ -1,0 +1,560 @@
+// Host driver and C ABI of the sGMRES library (see include/sgmres.h).
+//
+// One solve = repeated cycles of (arXiv:2111.00113 Algorithm 1; Section 3.5):
+//   residual r = b - A x and |r|     -> one 64-byte device->host read per cycle
+//   persistent basis + sketch kernel (b_1 .. b_d, S B, S A B, g = S r)
+//   sketched least squares (Householder QR, kappa guard, back substitution)
+//   x <- x + B y
+// All coefficients stay on the device; the host reads the residual norm (stop
+// test) and the previous cycle's counters once per cycle.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+
+#include "../../include/sgmres.h"
+#include "internal.hpp"
+
+namespace sg {
+namespace {
+
+constexpr uint64_t kSpinLimitTicks = 200000000ull;  // 2 s of the 100 MHz real-time counter
+constexpr int kMaxD = kLsqMaxCols;
+constexpr int kMaxS = 4096;
+
+// Scalars the kernels leave on the device; read back in one copy per cycle.
+struct DevScalars {
+    double beta;   // |r| of the current residual
+    double rho;    // |r| / |b|
+    double nf;     // |b|
+    double rest;   // last sketched residual estimate
+    double kappa;  // last diagonal ratio of T
+    double pad0[3];
+    int dc;         // columns built by the last basis cycle
+    int flags;      // OR of breakdown flags
+    int d_eff;      // columns used by the last least-squares solve
+    int lsq_flags;  // OR of kappa-truncation flags
+    int abort;      // grid-barrier wait limit hit
+    int csr_bad;    // CSR validation failed
+    int pad1[2];
+};
+
+struct Workspace {
+    double* r = nullptr;
+    size_t r_cap = 0;
+    double* B = nullptr;
+    size_t B_cap = 0;
+    double* SB = nullptr;
+    size_t SB_cap = 0;
+    double* SAB = nullptr;
+    size_t SAB_cap = 0;
+    double* H = nullptr;
+    size_t H_cap = 0;
+    double* g = nullptr;
+    size_t g_cap = 0;
+    double* y = nullptr;
+    size_t y_cap = 0;
+    double* part_a = nullptr;
+    size_t part_a_cap = 0;
+    double* part_b = nullptr;
+    size_t part_b_cap = 0;
+    double* part_sk = nullptr;
+    size_t part_sk_cap = 0;
+    double* part_vec = nullptr;
+    size_t part_vec_cap = 0;
+    unsigned* bar = nullptr;
+    DevScalars* sc = nullptr;
+    DevScalars* host_sc = nullptr;  // pinned
+    int32_t* t_rp = nullptr;
+    size_t t_rp_cap = 0;
+    int32_t* t_ci = nullptr;
+    size_t t_ci_cap = 0;
+    double* t_val = nullptr;
+    size_t t_val_cap = 0;
+    int32_t* t_scratch = nullptr;
+    size_t t_scratch_cap = 0;
+};
+
+std::mutex g_mutex;
+std::unordered_map<int, Workspace> g_ws;
+
+template <typename T>
+hipError_t ensure(T*& p, size_t& cap, size_t need) {
+    if (need == 0) need = 1;
+    if (p && cap >= need) return hipSuccess;
+    if (p) {
+        hipError_t e = hipFree(p);
+        if (e != hipSuccess) return e;
+        p = nullptr;
+        cap = 0;
+    }
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), sizeof(T) * need);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = need;
+    return hipSuccess;
+}
+
+int to_code(hipError_t e) {
+    if (e == hipSuccess) return SGMRES_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SGMRES_ENOMEM;
+    return SGMRES_EHIP;
+}
+
+#define SG_TRY(expr)                                  \
+    do {                                              \
+        hipError_t sg_e_ = (expr);                    \
+        if (sg_e_ != hipSuccess) return to_code(sg_e_); \
+    } while (0)
+
+int workspace(Workspace** out) {
+    int dev = 0;
+    SG_TRY(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    if (!ws.sc) {
+        SG_TRY(hipMalloc(reinterpret_cast<void**>(&ws.sc), sizeof(DevScalars)));
+        SG_TRY(hipMemset(ws.sc, 0, sizeof(DevScalars)));
+        SG_TRY(hipMalloc(reinterpret_cast<void**>(&ws.bar), 64));
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ws.host_sc), sizeof(DevScalars),
+                                     hipHostMallocDefault);
+        if (e != hipSuccess) return SGMRES_ENOMEM;
+        std::memset(ws.host_sc, 0, sizeof(DevScalars));
+    }
+    *out = &ws;
+    return SGMRES_OK;
+}
+
+bool csr_ok(const sgmres_csr_t* A) {
+    return A && A->n >= 1 && A->n < (int64_t(1) << 31) - 1 && A->nnz >= 0 && A->nnz < (int64_t(1) << 31) &&
+           A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val));
+}
+
+bool bad_sizes(int64_t n, int d, int k, int s, int zeta) {
+    return d < 1 || d > n || d > kMaxD || k < 1 || s < d + 1 || s > kMaxS || zeta < 1 || zeta > s ||
+           zeta > kMaxZeta;
+}
+
+struct SolveArgs {
+    sgmres_csr_t A;
+    const double* b;
+    double* x;
+    int d, k, s, zeta;
+    uint64_t seed;
+    double tol;
+    int restarts;
+    double kappa_max;
+    int block, rows_per_thread;
+    int profile;
+    hipStream_t stream;
+};
+
+// HIP events bracketing the kernels of one cycle (profiling only).
+struct CycleEvents {
+    hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr, l1 = nullptr, c1 = nullptr;
+    bool on = false;
+    hipError_t create() {
+        hipEvent_t* all[] = {&r0, &r1, &b0, &b1, &l1, &c1};
+        for (hipEvent_t* e : all) {
+            hipError_t err = hipEventCreate(e);
+            if (err != hipSuccess) return err;
+        }
+        on = true;
+        return hipSuccess;
+    }
+    ~CycleEvents() {
+        hipEvent_t all[] = {r0, r1, b0, b1, l1, c1};
+        for (hipEvent_t e : all)
+            if (e) (void)hipEventDestroy(e);
+    }
+    static double ms(hipEvent_t a, hipEvent_t b) {
+        float t = 0.0f;
+        return hipEventElapsedTime(&t, a, b) == hipSuccess ? static_cast<double>(t) : 0.0;
+    }
+};
+
+int copy_scalars(Workspace& ws, hipStream_t stream) {
+    SG_TRY(hipMemcpyAsync(ws.host_sc, ws.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, stream));
+    SG_TRY(hipStreamSynchronize(stream));
+    return SGMRES_OK;
+}
+
+// One basis cycle on the residual in ws.r (norm already in ws.sc->beta).
+int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zeta, uint64_t seed,
+              uint32_t cycle, const ArnoldiLaunch& L, double* B, int64_t ldb, double* SB, double* SAB,
+              double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr) {
+    SG_TRY(launch_fill_u32(ws.bar, 1, 0u, stream));
+    if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
+    ArnoldiParams p{};
+    p.n = A.n;
+    p.rp = A.row_ptr;
+    p.ci = A.col_idx;
+    p.val = A.val;
+    p.r = ws.r;
+    p.beta = &ws.sc->beta;
+    p.B = B;
+    p.ldb = ldb;
+    p.SB = SB;
+    p.SAB = SAB;
+    p.H = H;
+    p.g = g;
+    p.d = d;
+    p.k = k;
+    p.s = s;
+    p.zeta = zeta;
+    p.seed = seed;
+    p.cycle = cycle;
+    p.part_a = ws.part_a;
+    p.part_b = ws.part_b;
+    p.part_sk = ws.part_sk;
+    p.bar_count = ws.bar;
+    p.abort = &ws.sc->abort;
+    p.status = &ws.sc->dc;
+    p.spin_limit = kSpinLimitTicks;
+    SG_TRY(arnoldi_launch(L, p, stream));
+    return SGMRES_OK;
+}
+
+// Validates the CSR arrays on the device (one pass over row_ptr and col_idx).
+int check_csr(Workspace& ws, const sgmres_csr_t& A, hipStream_t st) {
+    SG_TRY(hipMemsetAsync(&ws.sc->csr_bad, 0, sizeof(int), st));
+    SG_TRY(launch_csr_check(A.n, A.nnz, A.row_ptr, A.col_idx, &ws.sc->csr_bad, st));
+    int rc = copy_scalars(ws, st);
+    if (rc) return rc;
+    return ws.host_sc->csr_bad ? SGMRES_ECSR : SGMRES_OK;
+}
+
+int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int block, int rpt,
+                    ArnoldiLaunch* L) {
+    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0};
+    if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
+    SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(k + 1) * L->grid));
+    SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
+    SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(3 * s) * L->grid));
+    return SGMRES_OK;
+}
+
+int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* wsp = nullptr;
+    int rc = workspace(&wsp);
+    if (rc) return rc;
+    Workspace& ws = *wsp;
+    const int64_t n = a.A.n;
+    const int kk = (a.k > a.d - 1) ? (a.d > 1 ? a.d - 1 : 1) : a.k;
+    hipStream_t st = a.stream;
+
+    SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
+    SG_TRY(ensure(ws.B, ws.B_cap, static_cast<size_t>(n) * a.d));
+    SG_TRY(ensure(ws.SB, ws.SB_cap, static_cast<size_t>(a.s) * a.d));
+    SG_TRY(ensure(ws.SAB, ws.SAB_cap, static_cast<size_t>(a.s) * a.d));
+    SG_TRY(ensure(ws.H, ws.H_cap, static_cast<size_t>(kk + 1) * a.d));
+    SG_TRY(ensure(ws.g, ws.g_cap, static_cast<size_t>(a.s)));
+    SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(a.d)));
+    SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    ArnoldiLaunch L{};
+    rc = prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L);
+    if (rc) return rc;
+    rc = check_csr(ws, a.A, st);
+    if (rc) return rc;
+
+    // |b|, and clear the per-solve counters
+    SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
+    SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, a.b, nullptr, ws.r, ws.part_vec, st));
+    SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(n), &ws.sc->nf, nullptr, st));
+    rc = copy_scalars(ws, st);
+    if (rc) return rc;
+    const double nf = ws.host_sc->nf;
+    sgmres_info_t rep{};
+    if (!std::isfinite(nf)) return SGMRES_ENONFINITE;
+    if (nf == 0.0) {
+        SG_TRY(launch_fill(a.x, n, 0.0, st));
+        SG_TRY(hipStreamSynchronize(st));
+        if (info) *info = rep;
+        return SGMRES_OK;
+    }
+
+    int cycles = 0;
+    int status = SGMRES_OK;
+    CycleEvents ev;
+    if (a.profile) SG_TRY(ev.create());
+    for (;;) {
+        if (ev.on) SG_TRY(hipEventRecord(ev.r0, st));
+        SG_TRY(launch_residual(n, a.A.row_ptr, a.A.col_idx, a.A.val, a.b, a.x, ws.r, ws.part_vec, st));
+        SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(n), &ws.sc->beta, &ws.sc->nf, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.r1, st));
+        rc = copy_scalars(ws, st);
+        if (rc) return rc;
+        const DevScalars& h = *ws.host_sc;
+        if (ev.on) rep.t_residual_ms += CycleEvents::ms(ev.r0, ev.r1);
+        if (cycles > 0) {
+            rep.steps += h.dc;
+            rep.d_eff_last = h.d_eff;
+            rep.rest_est = h.rest / nf;
+            rep.kappa_est = h.kappa;
+            if (ev.on) {
+                rep.t_basis_ms += CycleEvents::ms(ev.b0, ev.b1);
+                rep.t_lsq_ms += CycleEvents::ms(ev.b1, ev.l1);
+                rep.t_combine_ms += CycleEvents::ms(ev.l1, ev.c1);
+            }
+        }
+        rep.flags = h.flags | h.lsq_flags;
+        rep.relres = h.rho;
+        if (h.abort) {
+            status = SGMRES_ETIMEOUT;
+            break;
+        }
+        if (!std::isfinite(h.rho)) {
+            status = SGMRES_ENONFINITE;
+            break;
+        }
+        if (h.rho <= a.tol) {
+            status = SGMRES_OK;
+            break;
+        }
+        if (cycles > a.restarts) {
+            status = SGMRES_NOT_CONVERGED;
+            break;
+        }
+        rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
+                       ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr);
+        if (rc) return rc;
+        if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
+        SG_TRY(launch_lsq(a.s, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, &ws.sc->rest, &ws.sc->d_eff, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.l1, st));
+        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.c1, st));
+        ++cycles;
+    }
+    rep.cycles = cycles;
+    if (info) *info = rep;
+    return status;
+}
+
+int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s, uint64_t seed,
+                double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream) {
+    if (!csr_ok(A) || !b || !x) return SGMRES_EINVAL;
+    const int zeta = (opts && opts->zeta) ? opts->zeta : 8;
+    const double kappa_max = (opts && opts->kappa_max > 0) ? opts->kappa_max : 1e14;
+    if (bad_sizes(A->n, d, k, s, zeta) || !(tol >= 0.0) || restarts < 0) return SGMRES_EINVAL;
+    SolveArgs a{};
+    a.A = *A;
+    a.b = b;
+    a.x = x;
+    a.d = d;
+    a.k = k;
+    a.s = s;
+    a.zeta = zeta;
+    a.seed = seed;
+    a.tol = tol;
+    a.restarts = restarts;
+    a.kappa_max = kappa_max;
+    a.block = opts ? opts->block_size : 0;
+    a.rows_per_thread = opts ? opts->rows_per_thread : 0;
+    a.profile = opts ? opts->profile : 0;
+    a.stream = static_cast<hipStream_t>(stream);
+    if (opts && opts->transposed) {
+        Workspace* wsp = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(g_mutex);
+            int rc = workspace(&wsp);
+            if (rc) return rc;
+            const int64_t n = A->n;
+            SG_TRY(ensure(wsp->t_rp, wsp->t_rp_cap, static_cast<size_t>(n + 1)));
+            SG_TRY(ensure(wsp->t_ci, wsp->t_ci_cap, static_cast<size_t>(A->nnz)));
+            SG_TRY(ensure(wsp->t_val, wsp->t_val_cap, static_cast<size_t>(A->nnz)));
+            SG_TRY(ensure(wsp->t_scratch, wsp->t_scratch_cap, static_cast<size_t>(transpose_scratch_ints(n))));
+            rc = check_csr(*wsp, *A, a.stream);
+            if (rc) return rc;
+            SG_TRY(launch_csr_transpose(n, A->nnz, A->row_ptr, A->col_idx, A->val, wsp->t_rp, wsp->t_ci,
+                                        wsp->t_val, wsp->t_scratch, a.stream));
+        }
+        a.A.row_ptr = wsp->t_rp;
+        a.A.col_idx = wsp->t_ci;
+        a.A.val = wsp->t_val;
+    }
+    return solve_impl(a, info);
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int sgmres_solve(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s, uint64_t seed,
+                 double tol, int restarts, sgmres_info_t* info, void* stream) {
+    return solve_entry(A, b, x, d, k, s, seed, tol, restarts, nullptr, info, stream);
+}
+
+int sgmres_solve_transposed(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s,
+                            uint64_t seed, double tol, int restarts, sgmres_info_t* info, void* stream) {
+    sgmres_options_t o{};
+    o.transposed = 1;
+    return solve_entry(A, b, x, d, k, s, seed, tol, restarts, &o, info, stream);
+}
+
+int sgmres_solve_ex(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s, uint64_t seed,
+                    double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream) {
+    return solve_entry(A, b, x, d, k, s, seed, tol, restarts, opts, info, stream);
+}
+
+int sgmres_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s, int zeta,
+                          int32_t* rows, int8_t* signs, void* stream) {
+    if (count < 0 || i0 < 0 || s < 1 || s > 32767 || zeta < 1 || zeta > s || zeta > kMaxZeta ||
+        (count > 0 && (!rows || !signs)))
+        return SGMRES_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SG_TRY(launch_sketch_pattern(seed, cycle, i0, count, s, zeta, rows, signs, st));
+    SG_TRY(hipStreamSynchronize(st));
+    return SGMRES_OK;
+}
+
+int sgmres_sketch_apply(int64_t n, const double* v, uint64_t seed, uint32_t cycle, int s, int zeta, double* g,
+                        void* stream) {
+    if (n < 0 || (n > 0 && !v) || !g || s < 1 || s > 32767 || zeta < 1 || zeta > s || zeta > kMaxZeta)
+        return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SG_TRY(ensure(ws->part_sk, ws->part_sk_cap, static_cast<size_t>(s) * sketch_grid(n)));
+    SG_TRY(launch_sketch_apply(n, v, seed, cycle, s, zeta, ws->part_sk, g, st));
+    SG_TRY(hipStreamSynchronize(st));
+    return SGMRES_OK;
+}
+
+int sgmres_residual(const sgmres_csr_t* A, const double* f, const double* x, double* r, double* norm,
+                    void* stream) {
+    if (!csr_ok(A) || !f || !x || !r) return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SG_TRY(ensure(ws->part_vec, ws->part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    SG_TRY(launch_residual(A->n, A->row_ptr, A->col_idx, A->val, f, x, r, ws->part_vec, st));
+    SG_TRY(launch_norm_finish(ws->part_vec, vec_grid(A->n), &ws->sc->beta, nullptr, st));
+    rc = copy_scalars(*ws, st);
+    if (rc) return rc;
+    if (norm) *norm = ws->host_sc->beta;
+    return SGMRES_OK;
+}
+
+int sgmres_arnoldi_cycle(const sgmres_csr_t* A, const double* r, int d, int k, int s, int zeta, uint64_t seed,
+                         uint32_t cycle, double* B, int64_t ldb, double* SB, double* SAB, double* H, double* g,
+                         int* dc, int* flags, void* stream) {
+    if (!csr_ok(A) || !r || !B || !SB || !SAB || !H || !g || ldb < A->n) return SGMRES_EINVAL;
+    if (d < 1 || d > kMaxD || k < 1 || k > 1024 || s < 1 || s > kMaxS || zeta < 1 || zeta > s || zeta > kMaxZeta)
+        return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = A->n;
+    SG_TRY(ensure(ws->r, ws->r_cap, static_cast<size_t>(n)));
+    SG_TRY(ensure(ws->part_vec, ws->part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    ArnoldiLaunch L{};
+    rc = prepare_arnoldi(*ws, n, d, k, s, zeta, 0, 0, &L);
+    if (rc) return rc;
+    rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    // |r| into the scalar block, r copied into the workspace residual
+    SG_TRY(hipMemsetAsync(&ws->sc->dc, 0, 5 * sizeof(int), st));
+    SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, r, nullptr, ws->r, ws->part_vec, st));
+    SG_TRY(launch_norm_finish(ws->part_vec, vec_grid(n), &ws->sc->beta, nullptr, st));
+    SG_TRY(launch_fill(H, static_cast<int64_t>(k + 1) * d, 0.0, st));
+    rc = run_cycle(*ws, *A, d, k, s, zeta, seed, cycle, L, B, ldb, SB, SAB, H, g, st);
+    if (rc) return rc;
+    rc = copy_scalars(*ws, st);
+    if (rc) return rc;
+    if (ws->host_sc->abort) return SGMRES_ETIMEOUT;
+    if (dc) *dc = ws->host_sc->dc;
+    if (flags) *flags |= ws->host_sc->flags;
+    return SGMRES_OK;
+}
+
+int sgmres_sketched_lsq(int s, int dc, double* C, double* g, double kappa_max, double* y, int* d_eff,
+                        double* rest, double* kappa, int* flags, void* stream) {
+    if (s < 1 || s > 32767 || dc < 0 || dc > s || dc > kLsqMaxCols || !C || !g || (dc > 0 && !y) ||
+        !(kappa_max > 0))
+        return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SG_TRY(hipMemsetAsync(&ws->sc->d_eff, 0, 2 * sizeof(int), st));
+    SG_TRY(launch_lsq(s, nullptr, dc, C, g, kappa_max, y, &ws->sc->rest, &ws->sc->d_eff, st));
+    rc = copy_scalars(*ws, st);
+    if (rc) return rc;
+    if (d_eff) *d_eff = ws->host_sc->d_eff;
+    if (rest) *rest = ws->host_sc->rest;
+    if (kappa) *kappa = ws->host_sc->kappa;
+    if (flags) *flags |= ws->host_sc->lsq_flags;
+    return SGMRES_OK;
+}
+
+int sgmres_basis_combine(int64_t n, int d_eff, const double* B, int64_t ldb, const double* y, double* x,
+                         void* stream) {
+    if (n < 1 || d_eff < 0 || d_eff > kMaxD || ldb < n || !x || (d_eff > 0 && (!B || !y))) return SGMRES_EINVAL;
+    if (d_eff == 0) return SGMRES_OK;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ws->host_sc->d_eff = d_eff;
+    SG_TRY(hipMemcpyAsync(&ws->sc->d_eff, &ws->host_sc->d_eff, sizeof(int), hipMemcpyHostToDevice, st));
+    SG_TRY(launch_combine(n, &ws->sc->d_eff, d_eff, B, ldb, y, x, st));
+    SG_TRY(hipStreamSynchronize(st));
+    return SGMRES_OK;
+}
+
+int sgmres_csr_transpose(const sgmres_csr_t* A, int32_t* t_row_ptr, int32_t* t_col_idx, double* t_val,
+                         void* stream) {
+    if (!csr_ok(A) || !t_row_ptr || (A->nnz > 0 && (!t_col_idx || !t_val))) return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SG_TRY(ensure(ws->t_scratch, ws->t_scratch_cap, static_cast<size_t>(transpose_scratch_ints(A->n))));
+    rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    SG_TRY(launch_csr_transpose(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, t_row_ptr, t_col_idx, t_val,
+                                ws->t_scratch, st));
+    SG_TRY(hipStreamSynchronize(st));
+    return SGMRES_OK;
+}
+
+void sgmres_release_workspace(void) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_ws) {
+        (void)hipSetDevice(kv.first);
+        Workspace& w = kv.second;
+        void* ptrs[] = {w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.part_a, w.part_b, w.part_sk, w.part_vec,
+                        w.bar, w.sc, w.t_rp, w.t_ci, w.t_val, w.t_scratch};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+        if (w.host_sc) (void)hipHostFree(w.host_sc);
+    }
+    g_ws.clear();
+    (void)hipSetDevice(cur);
+}
+
+const char* sgmres_version(void) { return "sgmres-gfx950 0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal interfaces between the host driver and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sg {
+
+constexpr int kMaxZeta = 32;  // largest sketch column sparsity supported
+
+// ---- persistent basis kernel (arnoldi.hip) --------------------------------
+struct ArnoldiParams {
+    int64_t n;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+    const double* r;     // cycle residual, n
+    const double* beta;  // device scalar |r|
+    double* B;           // n x d, leading dim ldb
+    int64_t ldb;
+    double* SB;   // s x d
+    double* SAB;  // s x d
+    double* H;    // (k+1) x d
+    double* g;    // s
+    int d, k, s, zeta;
+    uint64_t seed;
+    uint32_t cycle;
+    double* part_a;   // (k+1) x G
+    double* part_b;   // (k+1) x G
+    double* part_sk;  // 3s x G
+    unsigned* bar_count;
+    int* abort;
+    int* status;  // [0] columns built, [1] flags (OR)
+    uint64_t spin_limit;
+};
+
+struct ArnoldiShape {
+    int64_t n;
+    int d, k, s, zeta;
+    int block;            // 0 = auto
+    int rows_per_thread;  // 0 = auto
+    int force_global_window;
+};
+
+struct ArnoldiLaunch {
+    const void* fn;
+    int block, R, KW, grid;
+    size_t lds;
+};
+
+size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta);
+hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
+hipError_t arnoldi_launch(const ArnoldiLaunch& L, ArnoldiParams params, hipStream_t stream);
+
+// ---- vector kernels (vec.hip) ----------------------------------------------
+constexpr int kVecBlock = 256;
+int vec_grid(int64_t n);  // blocks used by the partial-sum kernels (<= kMaxVecGrid)
+constexpr int kMaxVecGrid = 1024;
+
+// r = f - A x (x may be null: r = f); partial |r|^2 per block into part[G]
+hipError_t launch_residual(int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                           const double* f, const double* x, double* r, double* part,
+                           hipStream_t stream);
+// out[0] = sqrt(sum part[0..G)); if nf != null also out[1] = out[0] / *nf
+hipError_t launch_norm_finish(const double* part, int G, double* out, const double* nf,
+                              hipStream_t stream);
+// bad[0] |= 1 when the CSR arrays are malformed
+hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int* bad,
+                            hipStream_t stream);
+// x[i] = v  for i < n
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t stream);
+hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t stream);
+// x += B[:, :*d_eff] y
+hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const double* B, int64_t ldb,
+                          const double* y, double* x, hipStream_t stream);
+
+// ---- sketch kernels (sketch.hip) -------------------------------------------
+hipError_t launch_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s,
+                                 int zeta, int32_t* rows, int8_t* signs, hipStream_t stream);
+// g = S v using part (s x G workspace, G = sketch_grid(n))
+int sketch_grid(int64_t n);
+hipError_t launch_sketch_apply(int64_t n, const double* v, uint64_t seed, uint32_t cycle, int s,
+                               int zeta, double* part, double* g, hipStream_t stream);
+
+// ---- sketched least squares (lsq.hip) --------------------------------------
+// dc read from *dc_dev (device) when dc_dev != null, else dc_host.
+// dout: [0] rest, [1] kappa; iout: [0] d_eff, [1] flags (OR)
+hipError_t launch_lsq(int s, const int* dc_dev, int dc_host, double* C, double* g,
+                      double kappa_max, double* y, double* dout, int* iout, hipStream_t stream);
+constexpr int kLsqMaxCols = 1024;
+
+// ---- CSR transpose (transpose.hip) -----------------------------------------
+// scratch: transpose_scratch_ints(n) int32 (counts, fill counters, scan tile sums)
+int64_t transpose_scratch_ints(int64_t n);
+hipError_t launch_csr_transpose(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                                const double* val, int32_t* trp, int32_t* tci, double* tval,
+                                int32_t* scratch, hipStream_t stream);
+
+}  // namespace sg

@@ -1,0 +1,156 @@
+// Bandwidth-bound vector kernels of the sGMRES cycle (arXiv:2111.00113):
+//   residual r = f - A x with partial |r|^2   (Algorithm 1, residual step)
+//   norm finish (fixed-order sum of block partials)
+//   basis combine x <- x + B y                (Section 3.3, solution step)
+//   fills (graph-capture-safe clears)
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace sg {
+
+int vec_grid(int64_t n) {
+    const int64_t g = (n + kVecBlock - 1) / kVecBlock;
+    return static_cast<int>(g < 1 ? 1 : (g > kMaxVecGrid ? kMaxVecGrid : g));
+}
+
+namespace {
+
+__global__ __launch_bounds__(kVecBlock) void residual_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ ci,
+                                                             const double* __restrict__ val,
+                                                             const double* __restrict__ f,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ r,
+                                                             double* __restrict__ part) {
+    __shared__ double tmp[kVecBlock / kWave];
+    __shared__ double out[1];
+    double acc = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kVecBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kVecBlock + threadIdx.x; i < n; i += stride) {
+        double ax = 0.0;
+        if (x) {
+            const int q1 = rp[i + 1];
+            for (int q = rp[i]; q < q1; ++q) ax += val[q] * x[ci[q]];
+        }
+        const double ri = f[i] - ax;
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double v[1] = {acc};
+    block_sum<1>(v, 1, tmp, out);
+    if (threadIdx.x == 0) part[blockIdx.x] = out[0];
+}
+
+__global__ __launch_bounds__(kVecBlock) void norm_finish_kernel(const double* __restrict__ part, int G,
+                                                                double* __restrict__ out,
+                                                                const double* __restrict__ nf) {
+    __shared__ double res[1];
+    grid_sum(part, G, 1, res);
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(res[0]);
+        out[0] = nrm;
+        if (nf) out[1] = nrm / *nf;
+    }
+}
+
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+__global__ void fill_u32_kernel(unsigned* x, int64_t n, unsigned v) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+// x[i] += sum_{c < d_eff} B[c*ldb + i] y[c]; y staged in LDS; eight columns in
+// flight per thread.
+constexpr int kCombineBlock = 256;
+__global__ __launch_bounds__(kCombineBlock) void combine_kernel(int64_t n, const int* __restrict__ d_eff_p,
+                                                                const double* __restrict__ B, int64_t ldb,
+                                                                const double* __restrict__ y,
+                                                                double* __restrict__ x) {
+    extern __shared__ double ys[];
+    const int d_eff = *d_eff_p;
+    for (int c = threadIdx.x; c < d_eff; c += kCombineBlock) ys[c] = y[c];
+    __syncthreads();
+    if (d_eff <= 0) return;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kCombineBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kCombineBlock + threadIdx.x; i < n; i += stride) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int c = 0;
+        for (; c + 8 <= d_eff; c += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += B[static_cast<int64_t>(c + u) * ldb + i] * ys[c + u];
+        }
+        for (; c < d_eff; ++c) acc[0] += B[static_cast<int64_t>(c) * ldb + i] * ys[c];
+        const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        x[i] += sum;
+    }
+}
+
+// bad[0] = 1 if row_ptr is not a valid prefix array for nnz entries or a
+// column index falls outside [0, n)
+__global__ void csr_check_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                                 const int32_t* __restrict__ ci, int* __restrict__ bad) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool err = false;
+    for (int64_t i = tid; i < n; i += stride) err |= rp[i] > rp[i + 1];
+    if (tid == 0) err |= rp[0] != 0 || static_cast<int64_t>(rp[n]) != nnz;
+    for (int64_t q = tid; q < nnz; q += stride) err |= ci[q] < 0 || static_cast<int64_t>(ci[q]) >= n;
+    if (err) atomicOr(bad, 1);
+}
+
+}  // namespace
+
+hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int* bad,
+                            hipStream_t stream) {
+    int64_t g = (n + nnz + 255) / 256;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    csr_check_kernel<<<static_cast<int>(g), 256, 0, stream>>>(n, nnz, rp, ci, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                           const double* f, const double* x, double* r, double* part,
+                           hipStream_t stream) {
+    const int G = vec_grid(n);
+    residual_kernel<<<G, kVecBlock, 0, stream>>>(n, rp, ci, val, f, x, r, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finish(const double* part, int G, double* out, const double* nf,
+                              hipStream_t stream) {
+    norm_finish_kernel<<<1, kVecBlock, 0, stream>>>(part, G, out, nf);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    fill_kernel<<<static_cast<int>(g), 256, 0, stream>>>(x, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    fill_u32_kernel<<<static_cast<int>(g), 256, 0, stream>>>(x, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const double* B, int64_t ldb,
+                          const double* y, double* x, hipStream_t stream) {
+    int64_t g = (n + kCombineBlock - 1) / kCombineBlock;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    combine_kernel<<<static_cast<int>(g), kCombineBlock, sizeof(double) * (d_max > 0 ? d_max : 1), stream>>>(
+        n, d_eff, B, ldb, y, x);
+    return hipGetLastError();
+}
+
+}  // namespace sg

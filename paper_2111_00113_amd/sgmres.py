@@ -1,0 +1,309 @@
+"""ctypes binding of libsgmres.so (the gfx950 sketched GMRES library).
+
+Argument marshalling only: every computation runs in the HIP kernels behind
+the C ABI declared in include/sgmres.h.  PyTorch supplies device memory and the
+current HIP stream.  There is no CPU fallback: if the library is missing or a
+tensor is not on the GPU, the call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgmres.so")
+
+OK = 0
+NOT_CONVERGED = 1
+FLAG_KAPPA_TRUNC = 1
+FLAG_BREAKDOWN = 2
+ERRORS = {
+    -1: "SGMRES_EINVAL (bad argument)",
+    -2: "SGMRES_ECSR (malformed CSR)",
+    -3: "SGMRES_ENOMEM (allocation failed)",
+    -4: "SGMRES_EHIP (HIP runtime error)",
+    -5: "SGMRES_ENONFINITE (NaN/Inf encountered)",
+    -6: "SGMRES_ETIMEOUT (grid barrier wait limit)",
+}
+
+
+class SGMRESError(RuntimeError):
+    def __init__(self, fn: str, rc: int):
+        super().__init__(f"{fn} failed: {ERRORS.get(rc, rc)}")
+        self.rc = rc
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("d_eff_last", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("relres", ctypes.c_double),
+        ("rest_est", ctypes.c_double),
+        ("kappa_est", ctypes.c_double),
+        ("t_residual_ms", ctypes.c_double),
+        ("t_basis_ms", ctypes.c_double),
+        ("t_lsq_ms", ctypes.c_double),
+        ("t_combine_ms", ctypes.c_double),
+    ]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("zeta", ctypes.c_int32),
+        ("kappa_max", ctypes.c_double),
+        ("transposed", ctypes.c_int32),
+        ("block_size", ctypes.c_int32),
+        ("rows_per_thread", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libsgmres.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double)
+    P = ctypes.POINTER
+    L.sgmres_solve.argtypes = [P(_CSR), vp, vp, i32, i32, i32, u64, dbl, i32, P(_Info), vp]
+    L.sgmres_solve_transposed.argtypes = L.sgmres_solve.argtypes
+    L.sgmres_solve_ex.argtypes = [P(_CSR), vp, vp, i32, i32, i32, u64, dbl, i32, P(_Options), P(_Info), vp]
+    L.sgmres_sketch_pattern.argtypes = [u64, u32, i64, i64, i32, i32, vp, vp, vp]
+    L.sgmres_sketch_apply.argtypes = [i64, vp, u64, u32, i32, i32, vp, vp]
+    L.sgmres_residual.argtypes = [P(_CSR), vp, vp, vp, P(dbl), vp]
+    L.sgmres_arnoldi_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, i32, u64, u32, vp, i64, vp, vp, vp, vp,
+                                       P(i32), P(i32), vp]
+    L.sgmres_sketched_lsq.argtypes = [i32, i32, vp, vp, dbl, vp, P(i32), P(dbl), P(dbl), P(i32), vp]
+    L.sgmres_basis_combine.argtypes = [i64, i32, vp, i64, vp, vp, vp]
+    L.sgmres_csr_transpose.argtypes = [P(_CSR), vp, vp, vp, vp]
+    L.sgmres_release_workspace.argtypes = []
+    L.sgmres_release_workspace.restype = None
+    L.sgmres_version.argtypes = []
+    L.sgmres_version.restype = ctypes.c_char_p
+    for name in ("sgmres_solve", "sgmres_solve_transposed", "sgmres_solve_ex", "sgmres_sketch_pattern",
+                 "sgmres_sketch_apply", "sgmres_residual", "sgmres_arnoldi_cycle", "sgmres_sketched_lsq",
+                 "sgmres_basis_combine", "sgmres_csr_transpose"):
+        getattr(L, name).restype = ctypes.c_int
+    _LIB = L
+    return L
+
+
+@dataclasses.dataclass
+class DeviceCSR:
+    """CSR matrix whose arrays are torch tensors on a GPU."""
+
+    n: int
+    row_ptr: torch.Tensor  # int32[n+1]
+    col_idx: torch.Tensor  # int32[nnz]
+    val: torch.Tensor  # float64[nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @classmethod
+    def from_host(cls, A, device="cuda") -> "DeviceCSR":
+        """Upload a host CSR (anything with n, row_ptr, col_idx, val arrays)."""
+        return cls(
+            n=int(A.n),
+            row_ptr=torch.as_tensor(A.row_ptr, dtype=torch.int32).to(device),
+            col_idx=torch.as_tensor(A.col_idx, dtype=torch.int32).to(device),
+            val=torch.as_tensor(A.val, dtype=torch.float64).to(device),
+        )
+
+    def _c(self) -> _CSR:
+        for t in (self.row_ptr, self.col_idx, self.val):
+            _check_dev(t)
+        if self.row_ptr.dtype != torch.int32 or self.col_idx.dtype != torch.int32:
+            raise TypeError("row_ptr / col_idx must be int32")
+        if self.val.dtype != torch.float64:
+            raise TypeError("val must be float64")
+        if self.row_ptr.numel() != self.n + 1:
+            raise ValueError("row_ptr must have n+1 entries")
+        return _CSR(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.val.data_ptr())
+
+
+def _check_dev(t: torch.Tensor, dtype=None, numel=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"tensor has {t.numel()} entries, needs {numel}")
+    return t
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _info(i: _Info) -> dict:
+    return dict(cycles=i.cycles, steps=i.steps, d_eff_last=i.d_eff_last, flags=i.flags, relres=i.relres,
+                rest_est=i.rest_est, kappa_est=i.kappa_est, t_residual_ms=i.t_residual_ms,
+                t_basis_ms=i.t_basis_ms, t_lsq_ms=i.t_lsq_ms, t_combine_ms=i.t_combine_ms)
+
+
+def _raise(fn, rc):
+    if rc < 0:
+        raise SGMRESError(fn, rc)
+    return rc
+
+
+def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
+                 transposed=False, block_size=0, rows_per_thread=0, profile=False, stream=None):
+    """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
+
+    Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED (1);
+    raises SGMRESError on the negative error codes."""
+    _check_dev(b, torch.float64, A.n)
+    _check_dev(x, torch.float64, A.n)
+    info = _Info()
+    opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0)
+    rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
+                               ctypes.byref(opts), ctypes.byref(info), _stream(stream))
+    return _raise("sgmres_solve", rc), _info(info)
+
+
+def sgmres_solve_transposed(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, stream=None):
+    """Restarted sGMRES on A^T x = b through the dedicated entry point."""
+    _check_dev(b, torch.float64, A.n)
+    _check_dev(x, torch.float64, A.n)
+    info = _Info()
+    rc = lib().sgmres_solve_transposed(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol,
+                                       restarts, ctypes.byref(info), _stream(stream))
+    return _raise("sgmres_solve_transposed", rc), _info(info)
+
+
+def sgmres_sketch_pattern(seed, cycle, i0, count, s, zeta, device="cuda", stream=None):
+    """Rows (int32[count, zeta]) and signs (int8[count, zeta]) of sketch columns i0.. on the GPU."""
+    rows = torch.empty((max(count, 1), zeta), dtype=torch.int32, device=device)
+    signs = torch.empty((max(count, 1), zeta), dtype=torch.int8, device=device)
+    rc = lib().sgmres_sketch_pattern(seed, cycle, i0, count, s, zeta, rows.data_ptr(), signs.data_ptr(),
+                                     _stream(stream))
+    _raise("sgmres_sketch_pattern", rc)
+    return rows[:count], signs[:count]
+
+
+def sgmres_sketch_apply(v, seed, cycle, s, zeta, stream=None):
+    """g = S v on the GPU."""
+    _check_dev(v, torch.float64)
+    g = torch.empty(s, dtype=torch.float64, device=v.device)
+    rc = lib().sgmres_sketch_apply(v.numel(), v.data_ptr(), seed, cycle, s, zeta, g.data_ptr(), _stream(stream))
+    _raise("sgmres_sketch_apply", rc)
+    return g
+
+
+def sgmres_residual(A: DeviceCSR, f, x, stream=None):
+    """(r, |r|) with r = f - A x on the GPU."""
+    _check_dev(f, torch.float64, A.n)
+    _check_dev(x, torch.float64, A.n)
+    r = torch.empty(A.n, dtype=torch.float64, device=f.device)
+    nrm = ctypes.c_double(0)
+    rc = lib().sgmres_residual(ctypes.byref(A._c()), f.data_ptr(), x.data_ptr(), r.data_ptr(), ctypes.byref(nrm),
+                               _stream(stream))
+    _raise("sgmres_residual", rc)
+    return r, nrm.value
+
+
+def sgmres_arnoldi_cycle(A: DeviceCSR, r, d, k, s, zeta=8, seed=0, cycle=0, stream=None):
+    """One basis + sketch cycle; returns dict of GPU tensors (B n x d, SB, SAB s x d,
+    H (k+1) x d, g) plus dc and flags."""
+    _check_dev(r, torch.float64, A.n)
+    dev = r.device
+    B = torch.empty((d, A.n), dtype=torch.float64, device=dev)  # column-major n x d
+    SB = torch.zeros((d, s), dtype=torch.float64, device=dev)
+    SAB = torch.zeros((d, s), dtype=torch.float64, device=dev)
+    H = torch.zeros((d, k + 1), dtype=torch.float64, device=dev)
+    g = torch.empty(s, dtype=torch.float64, device=dev)
+    dc = ctypes.c_int(0)
+    flags = ctypes.c_int(0)
+    rc = lib().sgmres_arnoldi_cycle(ctypes.byref(A._c()), r.data_ptr(), d, k, s, zeta, seed, cycle, B.data_ptr(),
+                                    A.n, SB.data_ptr(), SAB.data_ptr(), H.data_ptr(), g.data_ptr(),
+                                    ctypes.byref(dc), ctypes.byref(flags), _stream(stream))
+    _raise("sgmres_arnoldi_cycle", rc)
+    return dict(B=B.T, SB=SB.T, SAB=SAB.T, H=H.T, g=g, dc=dc.value, flags=flags.value)
+
+
+def sgmres_sketched_lsq(SAB, g, kappa_max=1e14, stream=None):
+    """Sketched LS on the GPU.  SAB: (s, dc) tensor (any layout), g: (s,).  Returns a dict."""
+    s, dc = SAB.shape
+    C = SAB.T.contiguous().clone()  # column-major storage, overwritten by the factorisation
+    gg = g.contiguous().clone()
+    _check_dev(C, torch.float64)
+    _check_dev(gg, torch.float64, s)
+    y = torch.zeros(max(dc, 1), dtype=torch.float64, device=C.device)
+    d_eff = ctypes.c_int(0)
+    rest = ctypes.c_double(0)
+    kap = ctypes.c_double(0)
+    flags = ctypes.c_int(0)
+    rc = lib().sgmres_sketched_lsq(s, dc, C.data_ptr(), gg.data_ptr(), kappa_max, y.data_ptr(), ctypes.byref(d_eff),
+                                   ctypes.byref(rest), ctypes.byref(kap), ctypes.byref(flags), _stream(stream))
+    _raise("sgmres_sketched_lsq", rc)
+    de = d_eff.value
+    return dict(y=y[:de], d_eff=de, rest=rest.value, kappa=kap.value, flags=flags.value,
+                T=torch.triu(C.T[:dc, :dc]), QTg=gg)
+
+
+def sgmres_basis_combine(B, y, x, stream=None):
+    """x <- x + B[:, :len(y)] y in place; B is an (n, d) tensor with column-major storage."""
+    n = x.numel()
+    _check_dev(x, torch.float64)
+    d_eff = int(y.numel())
+    Bc = B.T  # (d, n) row-major view of a column-major (n, d)
+    if not Bc.is_contiguous():
+        Bc = Bc.contiguous()
+    yy = y.contiguous()
+    rc = lib().sgmres_basis_combine(n, d_eff, Bc.data_ptr(), n, yy.data_ptr() if d_eff else None, x.data_ptr(),
+                                    _stream(stream))
+    _raise("sgmres_basis_combine", rc)
+    return x
+
+
+def sgmres_csr_transpose(A: DeviceCSR, stream=None) -> DeviceCSR:
+    """CSR of A^T built on the GPU."""
+    dev = A.val.device
+    trp = torch.empty(A.n + 1, dtype=torch.int32, device=dev)
+    tci = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    tv = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev)
+    rc = lib().sgmres_csr_transpose(ctypes.byref(A._c()), trp.data_ptr(), tci.data_ptr(), tv.data_ptr(),
+                                    _stream(stream))
+    _raise("sgmres_csr_transpose", rc)
+    return DeviceCSR(A.n, trp, tci[: A.nnz], tv[: A.nnz])
+
+
+def sgmres_release_workspace():
+    lib().sgmres_release_workspace()
+
+
+def sgmres_version() -> str:
+    return lib().sgmres_version().decode()
