@@ -99,7 +99,22 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
+    ap.add_argument("--spmv-mode", type=int, default=0, help="0 row per thread, 1 CSR-stream")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}), flush=True)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -126,7 +141,7 @@ def main() -> int:
         x.zero_()
         rc, info = sg.sgmres_solve(dA, fb, x, d, k, s, p["seed"], p["tol"], p["restarts"], zeta=p["zeta"],
                                    profile=profile, block_size=args.block_size,
-                                   rows_per_thread=args.rows_per_thread)
+                                   rows_per_thread=args.rows_per_thread, spmv_mode=args.spmv_mode)
         if rc != sg.OK:
             raise RuntimeError(f"solve did not converge: {info}")
         return info
@@ -195,6 +210,8 @@ def main() -> int:
         "cycles_per_solve": cycles / args.steps,
         "relres_final": infos[-1]["relres"],
         "relres_host_check": relres_host,
+        "basis_phase_us_per_step": [round(sum(i["phase_us"][q] for i in infos) / max(steps, 1), 3)
+                                    for q in range(8)],
         "gpu_ms_per_solve": {
             "basis": t_basis / args.steps,
             "lsq": t_lsq / args.steps,
@@ -206,8 +223,13 @@ def main() -> int:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(A, f, p, cycles / args.steps, args.cpu_sample_cols)
     print(json.dumps(out), flush=True)
+    del dA, fb, x
+    torch.cuda.synchronize()
+    sg.sgmres_release_workspace()
     return 0
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    _rc = main()
+    if _rc:
+        sys.exit(_rc)

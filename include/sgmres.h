@@ -74,6 +74,12 @@ typedef struct {
     double t_basis_ms;    /* basis + sketch kernel (one launch per cycle) */
     double t_lsq_ms;      /* sketched least squares */
     double t_combine_ms;  /* x <- x + B y */
+    /* Basis kernel, workgroup 0's wall time per phase summed over all steps
+     * (microseconds; profile only): [0] SpMV + dots, [1] sketch scatter,
+     * [2] wait after phase 1, [3] first Gram-Schmidt update + dots,
+     * [4] barrier after phase 2, [5] second update + new column,
+     * [6] sketch column sums, [7] wait after phase 3. */
+    double phase_us[8];
 } sgmres_info_t;
 
 /* Options of sgmres_solve_ex; zero-initialise for the defaults. */
@@ -84,7 +90,12 @@ typedef struct {
     int32_t block_size; /* basis-kernel workgroup size, 256 / 512 / 1024; 0 -> auto */
     int32_t rows_per_thread; /* basis-kernel rows per thread, 1 / 2 / 4 / 8; 0 -> auto */
     int32_t profile;    /* nonzero: fill the t_*_ms fields of sgmres_info_t */
-    int32_t reserved[2];
+    int32_t barrier_mode; /* basis-kernel grid barrier: 0 one L2 write-back per XCD
+                             (default), 1 one per workgroup (reference protocol;
+                             results are bit-identical) */
+    int32_t spmv_mode;  /* basis-kernel SpMV: 0 one row per thread (default), 1
+                           nonzeros streamed through LDS in BLOCK-row chunks; both
+                           sum each row in nonzero order */
 } sgmres_options_t;
 
 /*

@@ -5,21 +5,31 @@
 //
 // Work decomposition.  Logical block b owns rows [b*R*BLOCK, (b+1)*R*BLOCK);
 // thread t of it owns rows b*R*BLOCK + r*BLOCK + t, r < R (coalesced across
-// lanes).  Everything a row needs between steps stays on chip: the last KW
-// basis entries of its rows (registers), m_j = A b_j and w (registers) and the
-// row's sketch column (LDS, generated once per cycle).  Per step the kernel
-// moves A, the gathered b_j and the written b_{j+1} through HBM, plus a few
-// kilobytes of per-block partial sums.
+// lanes).  What a row needs between steps stays on chip for the whole cycle:
+// its row-pointer range and the last KW basis entries (registers), m_j = A b_j
+// and w (registers).  The SpMV streams each BLOCK-row chunk's nonzeros with
+// coalesced loads into an LDS product buffer and every thread then sums its
+// row in nonzero order.  Per step the kernel moves the CSR column indices and
+// values, the gathered b_j and the written b_{j+1} through HBM, plus per-block
+// partial sums.
 //
-// Per step j (three grid barriers, each carrying a reduction):
-//   phase 1  m = A b_j; scatter S b_j, S m into LDS; partial <m,m>, W^T m
-//            -- barrier --
-//   phase 2  h = W^T m (grid sum); w = m - W h; partial <w,w>, W^T w;
-//            column j of SB / SAB (and g at j = 0) summed from block partials
-//            -- barrier --
+// Sketch.  The pattern of S restricted to the block's rows is generated once
+// per cycle and sorted by sketch row into LDS lists.  Each step stages b_j and
+// m_j of the block's rows in LDS and forms the block's share of S b_j and
+// S m_j as fixed-order sums over those lists (no atomics, so the result is
+// bitwise reproducible).  The block partials of all steps are kept and summed
+// across blocks once, at the end of the cycle.
+//
+// Per step j (three split-phase grid barriers, the first two carrying a
+// reduction; a third of the block's sketch work fills each barrier wait):
+//   phase 1  m = A b_j; partial <m,m>, W^T m           -- arrive --
+//            stage b_j, m in LDS; sketch rows [0, s/3)   -- wait --
+//   phase 2  h = W^T m (grid sum); w = m - W h; partial <w,w>, W^T w
+//                                                        -- arrive --
+//            sketch rows [s/3, 2s/3)                     -- wait --
 //   phase 3  h2 = W^T w; |w - W h2|^2 = <w,w> - |h2|^2 (window orthonormal to
-//            rounding); b_{j+1} = (w - W h2)/nu; H column j
-//            -- barrier --
+//            rounding); b_{j+1} = (w - W h2)/nu; H column j  -- arrive --
+//            sketch rows [2s/3, s)                       -- wait --
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -29,66 +39,180 @@ namespace {
 
 constexpr int kChunk = 8;     // reduction values per block_sum pass (global window)
 constexpr int kRedSlots = 9;  // max values per block_sum: window of 8 plus a norm
+constexpr int kSketchParts = 4;  // each sketch-row list is summed in this many pieces
 
 template <int R, int KW, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
+    constexpr int RB = R * BLOCK;  // rows per block
     const int s = p.s;
     const int zeta = p.zeta;
     const int64_t n = p.n;
-    double* acc = smem;                         // 2s: SB / SAB accumulators (g at init)
-    double* red_tmp = acc + 2 * s;              // NW * kRedSlots
-    double* red_out = red_tmp + NW * kRedSlots; // kRedSlots
-    double* coef = red_out + kRedSlots;         // [0] <m,m>, [1..k] h ; [k+1] <w,w>, [k+2..2k+1] h2
-    uint16_t* pat = reinterpret_cast<uint16_t*>(coef + 2 * p.k + 2);  // zeta x (R*BLOCK)
-    const int pstride = R * BLOCK;
+    // LDS: vals (2 RB doubles; the raw pattern at init) | reduction scratch |
+    //      coefficients | list starts (s+1) | counters (s) | lists (zeta RB)
+    double* vals = smem;
+    double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
+    double* red_out = red_tmp + NW * kRedSlots;
+    double* coef = red_out + kRedSlots;  // [0] <m,m>, [1..k] h ; [k+1] <w,w>, [k+2..2k+1] h2
+    double* sk_tmp = coef + 2 * p.k + 2;  // 2s x kSketchParts partial sums
+    int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
+    int* lcount = lstart + (s + 1);
+    uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
+    __shared__ unsigned sync_lds[2];
 
     const int G = gridDim.x;
     const int blk = xcd_logical_block(blockIdx.x, G);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
-    const int64_t base = static_cast<int64_t>(blk) * R * BLOCK + tid;
-    GridBarrier bar{p.bar_count, p.abort, static_cast<unsigned>(G), 0u, p.spin_limit};
+    const int64_t base = static_cast<int64_t>(blk) * RB + tid;
     const double scale = 1.0 / sqrt(static_cast<double>(zeta));
+    const int64_t slab = static_cast<int64_t>(2 * s) * G;  // sketch partials of one step
 
-    // ---- init: sketch pattern of own rows, b_1 = r/|r|, g partial ----------
-    for (int e = tid; e < 2 * s; e += BLOCK) acc[e] = 0.0;
+    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
+                 p.per_block_release != 0};
+    bar.setup(sync_lds);
+
+    // ---- per-row CSR structure, held for the cycle ---------------------------
+    // rbeg/rlen of own rows in registers; chunk r of the block (rows
+    // [b*RB + r*BLOCK, +BLOCK)) spans nonzeros [cq[r], cq[r+1]).
+    int rbeg[R], rlen[R];
+    __shared__ int cq[R + 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-        if (row < n) sketch_column(p.seed, p.cycle, row, s, zeta, pat + r * BLOCK + tid, pstride);
+        rbeg[r] = 0;
+        rlen[r] = 0;
+        if (row < n) {
+            rbeg[r] = p.rp[row];
+            rlen[r] = p.rp[row + 1] - rbeg[r];
+        }
+    }
+    if (tid <= R) {
+        int64_t row = static_cast<int64_t>(blk) * RB + static_cast<int64_t>(tid) * BLOCK;
+        if (row > n) row = n;
+        cq[tid] = p.rp[row];
     }
     __syncthreads();
 
+    // ---- sketch lists of the block's rows, sorted by sketch row --------------
+    {
+        uint16_t* raw = reinterpret_cast<uint16_t*>(vals);  // zeta x RB packed (row << 1 | neg)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+            if (row < n) sketch_column(p.seed, p.cycle, row, s, zeta, raw + r * BLOCK + tid, RB);
+        }
+        for (int e = tid; e < s; e += BLOCK) lcount[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+            if (row < n)
+                for (int t = 0; t < zeta; ++t) atomicAdd(&lcount[raw[t * RB + r * BLOCK + tid] >> 1], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int run = 0;
+            for (int e = 0; e < s; ++e) {
+                lstart[e] = run;
+                run += lcount[e];
+                lcount[e] = 0;
+            }
+            lstart[s] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+            if (row < n) {
+                const int local = r * BLOCK + tid;
+                for (int t = 0; t < zeta; ++t) {
+                    const unsigned e = raw[t * RB + local];
+                    const int pos = lstart[e >> 1] + atomicAdd(&lcount[e >> 1], 1);
+                    lists[pos] = static_cast<uint16_t>((local << 1) | (e & 1u));
+                }
+            }
+        }
+        __syncthreads();
+        // fixed order inside each list: ascending local row
+        for (int e = tid; e < s; e += BLOCK) {
+            const int q0 = lstart[e], q1 = lstart[e + 1];
+            for (int q = q0 + 1; q < q1; ++q) {
+                const uint16_t key = lists[q];
+                int z = q - 1;
+                while (z >= q0 && lists[z] > key) {
+                    lists[z + 1] = lists[z];
+                    --z;
+                }
+                lists[z + 1] = key;
+            }
+        }
+        __syncthreads();
+    }
+
+    // Block partial of S v over sketch rows [r0, r1) for nvec (1 or 2) vectors
+    // staged in vals[v*RB + local]: entry e = v*s + row goes to dst[e*G + blk].
+    // Each list is cut into kSketchParts pieces summed by separate threads,
+    // and the pieces are added in a fixed order: the result is reproducible.
+    auto block_sketch = [&](int nvec, int r0, int r1, double* dst) {
+        const int nrow = r1 - r0;
+        const int tasks = nvec * nrow * kSketchParts;
+        for (int t = tid; t < tasks; t += BLOCK) {
+            const int part = t % kSketchParts;
+            const int e = t / kSketchParts;
+            const int v = e / nrow;
+            const int row = r0 + (e - v * nrow);
+            const int q0 = lstart[row];
+            const int len = lstart[row + 1] - q0;
+            const int a0 = q0 + (len * part) / kSketchParts;
+            const int a1 = q0 + (len * (part + 1)) / kSketchParts;
+            const double* vv = vals + v * RB;
+            double a = 0.0;
+            for (int q = a0; q < a1; ++q) {
+                const unsigned u = lists[q];
+                const double x = vv[u >> 1];
+                a += (u & 1u) ? -x : x;
+            }
+            sk_tmp[t] = a;
+        }
+        __syncthreads();
+        for (int e = tid; e < nvec * nrow; e += BLOCK) {
+            double a = 0.0;
+#pragma unroll
+            for (int part = 0; part < kSketchParts; ++part) a += sk_tmp[e * kSketchParts + part];
+            const int v = e / nrow;
+            const int row = r0 + (e - v * nrow);
+            dst[static_cast<int64_t>(v * s + row) * G + blk] = a;
+        }
+    };
+    // the sketch of one step is spread over the three barrier windows
+    const int sk_cut1 = s / 3;
+    const int sk_cut2 = (2 * s) / 3;
+
+    // ---- init: g partial (S r), b_1 = r/|r| ----------------------------------
     const double beta = *p.beta;
     double win[KW > 0 ? KW : 1][R];
 #pragma unroll
     for (int a = 0; a < (KW > 0 ? KW : 1); ++a)
 #pragma unroll
         for (int r = 0; r < R; ++r) win[a][r] = 0.0;
-
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        double rv = 0.0;
         if (row < n) {
-            const double rv = p.r[row];
+            rv = p.r[row];
             const double b1 = rv / beta;
             p.B[row] = b1;
             win[0][r] = b1;
-            for (int t = 0; t < zeta; ++t) {
-                const unsigned e = pat[t * pstride + r * BLOCK + tid];
-                atomicAdd(&acc[e >> 1], (e & 1u) ? -rv : rv);
-            }
         }
+        vals[r * BLOCK + tid] = rv;
     }
     __syncthreads();
-    for (int e = tid; e < s; e += BLOCK) {
-        p.part_sk[static_cast<int64_t>(2 * s + e) * G + blk] = acc[e];
-        acc[e] = 0.0;
-    }
-    bar.sync();
+    block_sketch(1, 0, s, p.part_sk + static_cast<int64_t>(p.d) * slab);  // g partials after the d step slabs
+    bar.sync();  // B[:,0] and the g partials are complete
 
     // window entry a (0 = newest) of own row r at step j
     auto Wg = [&](int j, int a, int r) -> double {
@@ -137,68 +261,78 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         }
     };
 
+    // profiling: block 0 accumulates the real-time ticks spent in each phase
+    const bool timing = p.phase_ticks != nullptr && blk == 0 && tid == 0;
+    uint64_t t_last = timing ? __builtin_amdgcn_s_memrealtime() : 0;
+    auto tick = [&](int k) {
+        if (timing) {
+            const uint64_t t = __builtin_amdgcn_s_memrealtime();
+            p.phase_ticks[k] += t - t_last;
+            t_last = t;
+        }
+    };
+
     int dc = p.d;
     int flags = 0;
     for (int j = 0; j < p.d; ++j) {
         const double* bj = p.B + static_cast<int64_t>(j) * p.ldb;
         const int kw = min(j + 1, p.k);
 
-        // ---- phase 1: m = A b_j, sketch b_j and m, partial dots ------------
+        // ---- phase 1: m = A b_j and partial dots ---------------------------
         double m[R];
+        if (p.spmv_mode == 1) {
+            // CSR-stream: the chunk's products val[q] * b_j[col[q]] go to LDS with
+            // coalesced loads, then each thread sums its row in nonzero order.
+            double* prod = vals;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-            double am = 0.0;
-            if (row < n) {
-                const int q1 = p.rp[row + 1];
-                for (int q = p.rp[row]; q < q1; ++q) am += p.val[q] * bj[p.ci[q]];
-            }
-            m[r] = am;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-            if (row < n) {
-                double bv;
-                if constexpr (KW > 0) bv = win[0][r];
-                else bv = bj[row];
-                const double mv = m[r];
-                for (int t = 0; t < zeta; ++t) {
-                    const unsigned e = pat[t * pstride + r * BLOCK + tid];
-                    const bool neg = e & 1u;
-                    atomicAdd(&acc[e >> 1], neg ? -bv : bv);
-                    atomicAdd(&acc[s + (e >> 1)], neg ? -mv : mv);
+            for (int r = 0; r < R; ++r) {
+                const int q0 = cq[r], q1 = cq[r + 1];
+                double am = 0.0;
+                if (q1 - q0 <= 2 * RB) {
+#pragma unroll 4
+                    for (int q = q0 + tid; q < q1; q += BLOCK) prod[q - q0] = p.val[q] * bj[p.ci[q]];
+                    __syncthreads();
+                    for (int q = 0; q < rlen[r]; ++q) am += prod[rbeg[r] - q0 + q];
+                    __syncthreads();
+                } else {
+                    for (int q = 0; q < rlen[r]; ++q) am += p.val[rbeg[r] + q] * bj[p.ci[rbeg[r] + q]];
                 }
+                m[r] = am;
+            }
+        } else {
+            // one row per thread, nonzeros in order
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double am = 0.0;
+                for (int q = 0; q < rlen[r]; ++q) am += p.val[rbeg[r] + q] * bj[p.ci[rbeg[r] + q]];
+                m[r] = am;
             }
         }
         dots_to_partials(m, j, kw, p.part_a);
+        tick(0);
+        bar.arrive();
+        // block sketch partials of b_j and m_j, first third, overlap the barrier
+        double* sk_dst = p.part_sk + static_cast<int64_t>(j) * slab;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double bv;
+            if constexpr (KW > 0) bv = win[0][r];
+            else bv = Wg(j, 0, r);
+            vals[r * BLOCK + tid] = bv;
+            vals[RB + r * BLOCK + tid] = m[r];
+        }
         __syncthreads();
-        for (int e = tid; e < 2 * s; e += BLOCK) {
-            p.part_sk[static_cast<int64_t>(e) * G + blk] = acc[e];
-            acc[e] = 0.0;
-        }
-        bar.sync();
+        block_sketch(2, 0, sk_cut1, sk_dst);
+        tick(1);
+        bar.wait();
+        tick(2);
 
-        // ---- phase 2: h, w = m - W h, partial dots; sketch column j -------
+        // ---- phase 2: h, w = m - W h, partial dots ------------------------
         grid_sum(p.part_a, G, kw + 1, coef);  // coef[0] = <m,m>, coef[1+a] = h_a
-        {
-            const int E = (j == 0) ? 3 * s : 2 * s;
-            const int per = (E + G - 1) / G;
-            const int e0 = blk * per;
-            const int e1 = min(E, e0 + per);
-            for (int e = e0 + wid; e < e1; e += NW) {
-                double t = 0.0;
-                for (int g = lane; g < G; g += kWave) t += p.part_sk[static_cast<int64_t>(e) * G + g];
-                t = wave_sum(t) * scale;
-                if (lane == 0) {
-                    if (e < s) p.SB[static_cast<int64_t>(j) * s + e] = t;
-                    else if (e < 2 * s) p.SAB[static_cast<int64_t>(j) * s + (e - s)] = t;
-                    else p.g[e - 2 * s] = t;
-                }
-            }
+        if (j == p.d - 1) {
+            block_sketch(2, sk_cut1, s, sk_dst);
+            break;
         }
-        if (j == p.d - 1) break;
-
         double w[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) w[r] = m[r];
@@ -219,9 +353,13 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             }
         }
         dots_to_partials(w, j, kw, p.part_b);
-        bar.sync();
+        tick(3);
+        bar.arrive();
+        block_sketch(2, sk_cut1, sk_cut2, sk_dst);  // second third
+        bar.wait();
+        tick(4);
 
-        // ---- phase 3: h2, nu, b_{j+1} -----------------------------------
+        // ---- phase 3: h2, nu, b_{j+1} -------------------------------------
         double* c2 = coef + p.k + 1;
         grid_sum(p.part_b, G, kw + 1, c2);  // c2[0] = <w,w>, c2[1+a] = h2_a
         double h2sq = 0.0;
@@ -238,6 +376,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             p.H[static_cast<int64_t>(j) * (p.k + 1) + tid] = hv;
         }
         if (breakdown) {
+            block_sketch(2, sk_cut2, s, sk_dst);
             dc = j + 1;
             flags |= SGMRES_FLAG_BREAKDOWN;
             break;
@@ -276,8 +415,36 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
             for (int r = 0; r < R; ++r) win[0][r] = bnew[r];
         }
-        bar.sync();
+        tick(5);
+        bar.arrive();
+        block_sketch(2, sk_cut2, s, sk_dst);  // last third
+        bar.wait();
+        tick(6);
     }
+
+    // ---- end of cycle: sum the block sketch partials across blocks ----------
+    bar.sync();  // the last step's partials were written after its arrival
+    {
+        const int64_t E = static_cast<int64_t>(2 * s) * dc + s;
+        const int64_t per = (E + G - 1) / G;
+        const int64_t e0 = static_cast<int64_t>(blk) * per;
+        const int64_t e1 = min(E, e0 + per);
+        for (int64_t e = e0 + wid; e < e1; e += NW) {
+            const int64_t jj = e / (2 * s);  // == dc for the g entries
+            const int ee = static_cast<int>(e - jj * 2 * s);
+            const double* col = (jj < dc) ? p.part_sk + jj * slab + static_cast<int64_t>(ee) * G
+                                          : p.part_sk + static_cast<int64_t>(p.d) * slab + static_cast<int64_t>(ee) * G;
+            double t = 0.0;
+            for (int g = lane; g < G; g += kWave) t += col[g];
+            t = wave_sum(t) * scale;
+            if (lane == 0) {
+                if (jj == dc) p.g[ee] = t;
+                else if (ee < s) p.SB[jj * s + ee] = t;
+                else p.SAB[jj * s + (ee - s)] = t;
+            }
+        }
+    }
+    tick(7);
     if (blk == 0 && tid == 0) {
         p.status[0] = dc;
         p.status[1] |= flags;
@@ -290,7 +457,7 @@ template <int BLOCK>
 KernelFn pick(int R, int KW) {
 #define SG_CASE(RR, KK) \
     if (R == RR && KW == KK) return arnoldi_kernel<RR, KK, BLOCK>;
-#define SG_ROW(RR) SG_CASE(RR, 0) SG_CASE(RR, 2) SG_CASE(RR, 4) SG_CASE(RR, 8)
+#define SG_ROW(RR) SG_CASE(RR, 0) SG_CASE(RR, 4) SG_CASE(RR, 8)
     SG_ROW(1) SG_ROW(2) SG_ROW(4) SG_ROW(8)
 #undef SG_ROW
 #undef SG_CASE
@@ -310,8 +477,10 @@ KernelFn pick_kernel(int block, int R, int KW) {
 
 size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta) {
     const int nw = block / kWave;
-    return sizeof(double) * static_cast<size_t>(2 * s + nw * kRedSlots + kRedSlots + 2 * k + 2) +
-           sizeof(uint16_t) * static_cast<size_t>(zeta) * R * block;
+    const int RB = R * block;
+    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw * kRedSlots + kRedSlots + 2 * k + 2 +
+                                                2 * s * kSketchParts) +
+           sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
 }
 
 hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {
@@ -326,49 +495,50 @@ hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {
     err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     if (err != hipSuccess) return err;
 
-    const int blocks_try[3] = {shape.block ? shape.block : 512, 1024, 256};
+    const int blocks_try[3] = {1024, 512, 256};
     const int rows_try[4] = {1, 2, 4, 8};
-    for (int bi = 0; bi < 3; ++bi) {
-        const int block = blocks_try[bi];
-        if (shape.block && block != shape.block) continue;
-        for (int ri = 0; ri < 4; ++ri) {
-            const int R = rows_try[ri];
-            if (shape.rows_per_thread && R != shape.rows_per_thread) continue;
-            int KW = 0;
-            if (kw_need <= 2) KW = 2;
-            else if (kw_need <= 4) KW = 4;
-            else if (kw_need <= 8) KW = 8;
-            if (KW * R > 32) KW = 0;  // keep the register window within 64 VGPRs
-            if (shape.force_global_window) KW = 0;
-            const size_t lds = arnoldi_lds_bytes(block, R, shape.s, shape.k, shape.zeta);
-            if (lds > static_cast<size_t>(lds_max)) continue;
-            KernelFn fn = pick_kernel(block, R, KW);
-            if (!fn) continue;
-            if (lds > 65536) {
+    // candidates in order of preference; the first whose grid fits the chip wins
+    {
+        for (int bi = 0; bi < 3; ++bi) {
+            const int block = blocks_try[bi];
+            if (shape.block && block != shape.block) continue;
+            for (int ri = 0; ri < 4; ++ri) {
+                const int R = rows_try[ri];
+                if (shape.rows_per_thread && R != shape.rows_per_thread) continue;
+                int KW = 0;
+                if (kw_need <= 4) KW = 4;
+                else if (kw_need <= 8) KW = 8;
+                if (KW * R > 32) KW = 0;  // keep the register window within 64 VGPRs
+                if (shape.force_global_window) KW = 0;
+                const size_t lds = arnoldi_lds_bytes(block, R, shape.s, shape.k, shape.zeta);
+                if (lds > static_cast<size_t>(lds_max)) continue;
+                KernelFn fn = pick_kernel(block, R, KW);
+                if (!fn) continue;
                 err = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          static_cast<int>(lds));
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
                 if (err != hipSuccess) continue;
+                int per_cu = 0;
+                err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void*>(fn), block, lds);
+                if (err != hipSuccess || per_cu < 1) continue;
+                const int64_t need = (shape.n + static_cast<int64_t>(R) * block - 1) /
+                                     (static_cast<int64_t>(R) * block);
+                const int64_t gmax = static_cast<int64_t>(per_cu) * cus;
+                if (need > gmax) continue;
+                out->fn = reinterpret_cast<const void*>(fn);
+                out->block = block;
+                out->R = R;
+                out->KW = KW;
+                out->grid = static_cast<int>(need);
+                out->lds = lds;
+                return hipSuccess;
             }
-            int per_cu = 0;
-            err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(fn), block, lds);
-            if (err != hipSuccess || per_cu < 1) continue;
-            const int64_t need = (shape.n + static_cast<int64_t>(R) * block - 1) /
-                                 (static_cast<int64_t>(R) * block);
-            const int64_t gmax = static_cast<int64_t>(per_cu) * cus;
-            if (need > gmax) continue;
-            out->fn = reinterpret_cast<const void*>(fn);
-            out->block = block;
-            out->R = R;
-            out->KW = KW;
-            out->grid = static_cast<int>(need);
-            out->lds = lds;
-            return hipSuccess;
         }
     }
     return hipErrorInvalidValue;
 }
+
+size_t sync_words_bytes() { return sizeof(SyncWords); }
 
 hipError_t arnoldi_launch(const ArnoldiLaunch& L, ArnoldiParams params, hipStream_t stream) {
     void* args[] = {&params};

@@ -41,6 +41,7 @@ struct DevScalars {
     int abort;      // grid-barrier wait limit hit
     int csr_bad;    // CSR validation failed
     int pad1[2];
+    unsigned long long phase_ticks[8];  // basis-kernel phase timers (profile)
 };
 
 struct Workspace {
@@ -58,6 +59,9 @@ struct Workspace {
     size_t g_cap = 0;
     double* y = nullptr;
     size_t y_cap = 0;
+    double* tau = nullptr;
+    size_t tau_cap = 0;
+    unsigned* lsq_sync = nullptr;
     double* part_a = nullptr;
     size_t part_a_cap = 0;
     double* part_b = nullptr;
@@ -66,7 +70,7 @@ struct Workspace {
     size_t part_sk_cap = 0;
     double* part_vec = nullptr;
     size_t part_vec_cap = 0;
-    unsigned* bar = nullptr;
+    unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
     int32_t* t_rp = nullptr;
@@ -120,7 +124,8 @@ int workspace(Workspace** out) {
     if (!ws.sc) {
         SG_TRY(hipMalloc(reinterpret_cast<void**>(&ws.sc), sizeof(DevScalars)));
         SG_TRY(hipMemset(ws.sc, 0, sizeof(DevScalars)));
-        SG_TRY(hipMalloc(reinterpret_cast<void**>(&ws.bar), 64));
+        SG_TRY(hipMalloc(reinterpret_cast<void**>(&ws.sync), sync_words_bytes()));
+        SG_TRY(hipMalloc(reinterpret_cast<void**>(&ws.lsq_sync), lsq_sync_bytes()));
         hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ws.host_sc), sizeof(DevScalars),
                                      hipHostMallocDefault);
         if (e != hipSuccess) return SGMRES_ENOMEM;
@@ -151,6 +156,8 @@ struct SolveArgs {
     double kappa_max;
     int block, rows_per_thread;
     int profile;
+    int per_block_release;
+    int spmv_mode;
     hipStream_t stream;
 };
 
@@ -187,8 +194,9 @@ int copy_scalars(Workspace& ws, hipStream_t stream) {
 // One basis cycle on the residual in ws.r (norm already in ws.sc->beta).
 int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zeta, uint64_t seed,
               uint32_t cycle, const ArnoldiLaunch& L, double* B, int64_t ldb, double* SB, double* SAB,
-              double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr) {
-    SG_TRY(launch_fill_u32(ws.bar, 1, 0u, stream));
+              double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
+              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0) {
+    SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ArnoldiParams p{};
     p.n = A.n;
@@ -212,11 +220,28 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
     p.part_a = ws.part_a;
     p.part_b = ws.part_b;
     p.part_sk = ws.part_sk;
-    p.bar_count = ws.bar;
+    p.sync = ws.sync;
+    p.per_block_release = per_block_release;
     p.abort = &ws.sc->abort;
     p.status = &ws.sc->dc;
     p.spin_limit = kSpinLimitTicks;
+    p.phase_ticks = phase_timing ? ws.sc->phase_ticks : nullptr;
+    p.spmv_mode = spmv_mode;
     SG_TRY(arnoldi_launch(L, p, stream));
+    return SGMRES_OK;
+}
+
+// Sketched least squares on C (s x dc): the column-owner pipeline when s fits
+// its register layout, else the one-workgroup kernel.
+int run_lsq(Workspace& ws, int s, int d_max, const int* dc_dev, int dc_host, double* C, double* g, double kappa_max,
+            double* y, hipStream_t st) {
+    if (s <= kLsqPipeMaxS) {
+        SG_TRY(ensure(ws.tau, ws.tau_cap, static_cast<size_t>(d_max > 0 ? d_max : 1)));
+        SG_TRY(launch_lsq_pipeline(s, d_max, dc_dev, dc_host, C, g, ws.tau, kappa_max, y, &ws.sc->rest,
+                                   &ws.sc->d_eff, ws.lsq_sync, &ws.sc->abort, kSpinLimitTicks, st));
+    } else {
+        SG_TRY(launch_lsq(s, dc_dev, dc_host, C, g, kappa_max, y, &ws.sc->rest, &ws.sc->d_eff, st));
+    }
     return SGMRES_OK;
 }
 
@@ -231,11 +256,11 @@ int check_csr(Workspace& ws, const sgmres_csr_t& A, hipStream_t st) {
 
 int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int block, int rpt,
                     ArnoldiLaunch* L) {
-    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0};
+    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0};
     if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
     SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(k + 1) * L->grid));
     SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
-    SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(3 * s) * L->grid));
+    SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
     return SGMRES_OK;
 }
 
@@ -265,6 +290,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
 
     // |b|, and clear the per-solve counters
     SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
+    SG_TRY(hipMemsetAsync(ws.sc->phase_ticks, 0, sizeof(ws.sc->phase_ticks), st));
     SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, a.b, nullptr, ws.r, ws.part_vec, st));
     SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(n), &ws.sc->nf, nullptr, st));
     rc = copy_scalars(ws, st);
@@ -322,16 +348,20 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
             break;
         }
         rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
-                       ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr);
+                       ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
+                       a.spmv_mode);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
-        SG_TRY(launch_lsq(a.s, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, &ws.sc->rest, &ws.sc->d_eff, st));
+        rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
+        if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.l1, st));
         SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st));
         if (ev.on) SG_TRY(hipEventRecord(ev.c1, st));
         ++cycles;
     }
     rep.cycles = cycles;
+    if (ev.on)
+        for (int q = 0; q < 8; ++q) rep.phase_us[q] = 1e-2 * static_cast<double>(ws.host_sc->phase_ticks[q]);
     if (info) *info = rep;
     return status;
 }
@@ -357,6 +387,8 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     a.block = opts ? opts->block_size : 0;
     a.rows_per_thread = opts ? opts->rows_per_thread : 0;
     a.profile = opts ? opts->profile : 0;
+    a.per_block_release = opts ? opts->barrier_mode : 0;
+    a.spmv_mode = opts ? opts->spmv_mode : 0;
     a.stream = static_cast<hipStream_t>(stream);
     if (opts && opts->transposed) {
         Workspace* wsp = nullptr;
@@ -495,9 +527,12 @@ int sgmres_sketched_lsq(int s, int dc, double* C, double* g, double kappa_max, d
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     SG_TRY(hipMemsetAsync(&ws->sc->d_eff, 0, 2 * sizeof(int), st));
-    SG_TRY(launch_lsq(s, nullptr, dc, C, g, kappa_max, y, &ws->sc->rest, &ws->sc->d_eff, st));
+    SG_TRY(hipMemsetAsync(&ws->sc->abort, 0, sizeof(int), st));
+    rc = run_lsq(*ws, s, dc, nullptr, dc, C, g, kappa_max, y, st);
+    if (rc) return rc;
     rc = copy_scalars(*ws, st);
     if (rc) return rc;
+    if (ws->host_sc->abort) return SGMRES_ETIMEOUT;
     if (d_eff) *d_eff = ws->host_sc->d_eff;
     if (rest) *rest = ws->host_sc->rest;
     if (kappa) *kappa = ws->host_sc->kappa;
@@ -545,8 +580,8 @@ void sgmres_release_workspace(void) {
     for (auto& kv : g_ws) {
         (void)hipSetDevice(kv.first);
         Workspace& w = kv.second;
-        void* ptrs[] = {w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.part_a, w.part_b, w.part_sk, w.part_vec,
-                        w.bar, w.sc, w.t_rp, w.t_ci, w.t_val, w.t_scratch};
+        void* ptrs[] = {w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
+                        w.part_vec, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val, w.t_scratch};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);

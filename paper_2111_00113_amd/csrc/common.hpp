@@ -78,10 +78,35 @@ __device__ __forceinline__ void sketch_column(uint64_t seed, uint32_t cycle, int
 // and every block that reduces the same data in the same order gets the same
 // bits, which keeps grid-wide decisions (breakdown, kappa) consistent.
 // --------------------------------------------------------------------------
+// One DPP step on a double: each lane adds the value the DPP pattern `CTRL`
+// reads from another lane (lanes outside ROW_MASK, or with no source, add 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x) {
+    const int lo = __double2loint(x);
+    const int hi = __double2hiint(x);
+    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, true);
+    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, true);
+    return x + __hiloint2double(hi2, lo2);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront with DPP (pairs, quads, half rows, rows,
+// then the row broadcasts of lanes 15 and 31); the total forms in lane 63 and
+// is broadcast.  The addition order is fixed, so the result is reproducible
+// and identical in every lane.  All lanes must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return readlane_d(v, kWave - 1);
 }
 
 // Sum over the workgroup of nv per-thread values; result in lds_out[0..nv).
@@ -124,38 +149,113 @@ __device__ __forceinline__ void grid_sum(const double* partial, int G, int nv, d
 }
 
 // --------------------------------------------------------------------------
-// Grid barrier for a cooperative launch (all blocks resident).  The counter is
-// monotone within a launch: barrier number q waits for q * G arrivals.  The
-// release by thread 0 after __syncthreads() publishes the block's global writes
-// at agent scope; the acquire makes every other block's writes visible.  The
-// wait is bounded: after `limit` ticks of the 100 MHz real-time counter the
-// block raises abort[0] and every later barrier returns at once, so the kernel
-// always drains; the host reports SGMRES_ETIMEOUT.
+// Split-phase grid barrier for a cooperative launch (all blocks resident).
+//
+// Arrival is counted per XCD (the chip's 8 L2 domains, read from the XCC_ID
+// hardware register): each block adds 1 to its XCD's counter, and the last
+// arriver on an XCD -- by then every block of that XCD has finished its stores
+// into the shared L2 -- issues one agent-scope release (L2 write-back) for the
+// whole XCD and adds 1 to a global counter.  The last XCD publishes the
+// generation number with a release store; waiters poll it and take an
+// agent-scope acquire.  This replaces G serialised L2 write-backs and G
+// contended atomics with 8 of each.  In `per_block_release` mode every block
+// also releases before arriving (the textbook protocol), which must give
+// bit-identical results.
+//
+// Waits are bounded: after `limit` ticks of the 100 MHz real-time counter the
+// block raises abort[0]; later waits return at once, so the kernel drains and
+// the host reports SGMRES_ETIMEOUT.  Counters are monotone within a launch and
+// must be zero at launch (SyncWords, cleared by the host before each launch).
 // --------------------------------------------------------------------------
-struct GridBarrier {
-    unsigned* count;
-    int* abort;
-    unsigned G;
-    unsigned seq;
-    uint64_t limit;
+struct SyncWords {
+    unsigned xcnt[16 * 64];  // per-XCD arrivals, 256 B apart
+    unsigned reg[16 * 64];   // per-XCD registered blocks, 256 B apart
+    unsigned gcount;         // XCD-leader arrivals (+ registrations)
+    unsigned pad0[63];
+    unsigned gen;            // published generation
+    unsigned pad1[63];
+};
 
-    __device__ __forceinline__ void sync() {
+__device__ __forceinline__ unsigned xcc_id() {
+    // HW_REG_XCC_ID (hardware register 20), bits [3:0]
+    return static_cast<unsigned>(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20)) & 0xfu;
+}
+
+struct GridSync {
+    SyncWords* w;
+    int* abort;
+    uint64_t limit;
+    unsigned G;
+    unsigned xcc;
+    unsigned my_size;  // blocks on this XCD
+    unsigned nx;       // XCDs holding at least one block
+    unsigned seq;
+    bool per_block_release;
+
+    __device__ __forceinline__ bool spin_ge(unsigned* p, unsigned target) {
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+            if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return true;
+    }
+
+    // Once per launch, by every block: count blocks per XCD (one flat barrier).
+    __device__ void setup(unsigned* lds2) {
+        seq = 0;
+        xcc = xcc_id();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&w->reg[xcc * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&w->gcount, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            spin_ge(&w->gcount, G);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            unsigned k = 0;
+            for (int i = 0; i < 16; ++i)
+                k += __hip_atomic_load(&w->reg[i * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+            lds2[0] = __hip_atomic_load(&w->reg[xcc * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            lds2[1] = k;
+        }
+        __syncthreads();
+        my_size = lds2[0];
+        nx = lds2[1];
+        __syncthreads();
+    }
+
+    // All prior global writes of this block become visible to every block that
+    // returns from the matching wait().
+    __device__ __forceinline__ void arrive() {
         ++seq;
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned target = seq * G;
-            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-            while (__hip_atomic_load(count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
-                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+            if (per_block_release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned old =
+                __hip_atomic_fetch_add(&w->xcnt[xcc * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 == seq * my_size) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const unsigned o2 =
+                    __hip_atomic_fetch_add(&w->gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // this leader's release above already covers its XCD
+                if (o2 + 1 == G + seq * nx) __hip_atomic_store(&w->gen, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+    }
+
+    __device__ __forceinline__ void wait() {
+        if (threadIdx.x == 0) {
+            spin_ge(&w->gen, seq);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
         __syncthreads();
+    }
+
+    __device__ __forceinline__ void sync() {
+        arrive();
+        wait();
     }
 };
 

@@ -28,11 +28,14 @@ struct ArnoldiParams {
     uint32_t cycle;
     double* part_a;   // (k+1) x G
     double* part_b;   // (k+1) x G
-    double* part_sk;  // 3s x G
-    unsigned* bar_count;
+    double* part_sk;  // (2s x G) per step for d steps, then s x G for g
+    void* sync;       // SyncWords, zero at launch
+    int per_block_release;
     int* abort;
     int* status;  // [0] columns built, [1] flags (OR)
     uint64_t spin_limit;
+    unsigned long long* phase_ticks;  // null, or 8 accumulators (block 0's time per phase)
+    int spmv_mode;                    // 0 row per thread, 1 CSR-stream through LDS
 };
 
 struct ArnoldiShape {
@@ -41,6 +44,7 @@ struct ArnoldiShape {
     int block;            // 0 = auto
     int rows_per_thread;  // 0 = auto
     int force_global_window;
+    int per_block_release;
 };
 
 struct ArnoldiLaunch {
@@ -49,9 +53,16 @@ struct ArnoldiLaunch {
     size_t lds;
 };
 
+// doubles of the LDS value area: two staged vectors (also the SpMV product
+// buffer), or the raw sketch pattern at init
+__host__ __device__ constexpr int arnoldi_vals_doubles(int RB, int zeta) {
+    return (2 * RB > (zeta * RB + 3) / 4) ? 2 * RB : (zeta * RB + 3) / 4;
+}
+
 size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta);
 hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
 hipError_t arnoldi_launch(const ArnoldiLaunch& L, ArnoldiParams params, hipStream_t stream);
+size_t sync_words_bytes();
 
 // ---- vector kernels (vec.hip) ----------------------------------------------
 constexpr int kVecBlock = 256;
@@ -89,6 +100,13 @@ hipError_t launch_sketch_apply(int64_t n, const double* v, uint64_t seed, uint32
 hipError_t launch_lsq(int s, const int* dc_dev, int dc_host, double* C, double* g,
                       double kappa_max, double* y, double* dout, int* iout, hipStream_t stream);
 constexpr int kLsqMaxCols = 1024;
+// Column-owner pipeline version for s <= 512: one wavefront per column of C
+// (and one for g); tau needs d_max doubles, sync lsq_sync_bytes() (cleared here).
+constexpr int kLsqPipeMaxS = 512;
+size_t lsq_sync_bytes();
+hipError_t launch_lsq_pipeline(int s, int d_max, const int* dc_dev, int dc_host, double* C, double* g, double* tau,
+                               double kappa_max, double* y, double* dout, int* iout, void* sync, int* abort,
+                               uint64_t limit, hipStream_t stream);
 
 // ---- CSR transpose (transpose.hip) -----------------------------------------
 // scratch: transpose_scratch_ints(n) int32 (counts, fill counters, scan tile sums)

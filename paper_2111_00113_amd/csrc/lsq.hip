@@ -4,8 +4,10 @@
 //   condition guard on the diagonal of T (Sections 3.4 and 5.3),
 //   back substitution T y = Q^T g on the kept prefix,
 //   residual estimate |(Q^T g)[d_eff:]|.
-// One workgroup of 1024 threads; the s x dc matrix stays in global memory
-// (L2-resident), the current reflector is staged in LDS.
+// Two versions: a column-owner pipeline over many workgroups (s <= 512, the
+// default) and one workgroup of 1024 threads for larger s, where the s x dc
+// matrix stays in global memory (L2-resident) and each reflector is staged in
+// LDS.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kLsqBlock) void lsq_kernel(int s, const int* __rest
 #pragma unroll
             for (int c = 0; c < kZSlots; ++c)
                 if (c == slot) mine = z[c];
-            const double zi = __shfl(mine, i & (kWave - 1), kWave);
+            const double zi = readlane_d(mine, i & (kWave - 1));
             const double* tcol = C + static_cast<int64_t>(i) * s;
             const double yi = zi / tcol[i];
             if (lane == 0) y[i] = yi;
@@ -138,12 +140,328 @@ __global__ __launch_bounds__(kLsqBlock) void lsq_kernel(int s, const int* __rest
     if (tid == 0) dout[0] = sqrt(red[0]);
 }
 
+// ---------------------------------------------------------------------------
+// Blocked column-owner pipeline (s <= 64*S): wavefront w keeps columns
+// [w*CB, w*CB + CB) of C -- column dc stands for g -- in registers for the
+// whole factorisation.  It applies the reflectors of earlier wavefronts in
+// order as they are published, factors its own columns locally (each new
+// reflector applied at once to its later columns), writes them back (T entries
+// above the diagonal, beta on it, the reflector tail below) and publishes them
+// by raising a counter.  Every column therefore sees the reflectors in the
+// same order as in the one-workgroup kernel above.  The wavefront holding g
+// finishes with the kappa guard, the back substitution and the residual
+// estimate.  Launched cooperatively (all wavefronts resident); every wait is
+// bounded by a real-time limit.
+// ---------------------------------------------------------------------------
+constexpr int kPipeWaves = 4;
+constexpr int kPipeBlock = kPipeWaves * kWave;
+constexpr int kPipeCols = 8;  // columns per wavefront
+
+struct LsqSync {
+    unsigned npub;  // reflectors published (monotone, in order)
+    unsigned pad[63];
+};
+
+// row p of a register-resident column (row p lives in lane p % 64, slot p / 64)
+template <int S>
+__device__ __forceinline__ double row_of(const double (&col)[S], int p) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+        if (q == (p >> 6)) v = col[q];
+    return readlane_d(v, p & (kWave - 1));
+}
+
+// col <- (I - tau v v^T) col with v = [1 at row p; vt below p] (vt zero at and above p)
+template <int S>
+__device__ __forceinline__ void apply_reflector(double (&col)[S], const double (&vt)[S], double tau, int p, int lane) {
+    const double head = row_of<S>(col, p);
+    double sd = 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) sd += vt[q] * col[q];
+    sd = (head + wave_sum(sd)) * tau;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const int i = lane + q * kWave;
+        if (i == p) col[q] = head - sd;
+        else col[q] -= sd * vt[q];
+    }
+}
+
+// The same reflector applied to the first `ncol` of CB register-resident
+// columns; the CB dot products and their DPP reductions are interleaved so
+// their latencies overlap.  Per column the arithmetic equals apply_reflector.
+template <int S, int CB>
+__device__ __forceinline__ void apply_reflector_cols(double (&col)[CB][S], const double (&vt)[S], double tau, int p,
+                                                     int lane, int i0, int ncol) {
+    double head[CB], sd[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+        head[i] = 0.0;
+        sd[i] = 0.0;
+        if (i >= i0 && i < ncol) {
+            double hl = 0.0;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (q == (p >> 6)) hl = col[i][q];
+                sd[i] += vt[q] * col[i][q];
+            }
+            head[i] = readlane_d(hl, p & (kWave - 1));
+        }
+    }
+    // interleaved wave sums (same step order as wave_sum)
+#pragma unroll
+    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0xb1, 0xf>(sd[i]);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x4e, 0xf>(sd[i]);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x141, 0xf>(sd[i]);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x140, 0xf>(sd[i]);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x142, 0xa>(sd[i]);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x143, 0xc>(sd[i]);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+        if (i >= i0 && i < ncol) {
+            const double t = (head[i] + readlane_d(sd[i], kWave - 1)) * tau;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                if (r == p) col[i][q] = head[i] - t;
+                else col[i][q] -= t * vt[q];
+            }
+        }
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const int* __restrict__ dc_dev, int dc_host,
+                                                                  double* __restrict__ C, double* __restrict__ g,
+                                                                  double* __restrict__ tau, double kappa_max,
+                                                                  double* __restrict__ y, double* __restrict__ dout,
+                                                                  int* __restrict__ iout, LsqSync* sync, int* abort,
+                                                                  uint64_t limit) {
+    constexpr int CB = kPipeCols;
+    const int dc = dc_dev ? *dc_dev : dc_host;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c0 = (blockIdx.x * kPipeWaves + threadIdx.x / kWave) * CB;
+    if (c0 > dc) return;
+    const int ncol = min(CB, dc + 1 - c0);  // columns held (column dc is g)
+    double col[CB][S];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+        const int c = c0 + i;
+        const double* src = (c < dc) ? C + static_cast<int64_t>(c) * s : g;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int r = lane + q * kWave;
+            col[i][q] = (i < ncol && r < s) ? src[r] : 0.0;
+        }
+    }
+
+    // reflectors of earlier wavefronts, applied in order as they are published;
+    // kBatch of them are loaded together so their loads overlap
+    constexpr int kBatch = 4;
+    const int pmax = min(c0, dc);
+    unsigned avail = 0;
+    for (int p0 = 0; p0 < pmax; p0 += kBatch) {
+        const int pend = min(p0 + kBatch, pmax);
+        if (static_cast<unsigned>(pend) > avail) {
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            while ((avail = __hip_atomic_load(&sync->npub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
+                   static_cast<unsigned>(pend)) {
+                if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+                if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    return;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        double vt[kBatch][S];
+        double tb[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int p = p0 + b;
+            tb[b] = (p < pend) ? tau[p] : 0.0;
+            const double* vp = C + static_cast<int64_t>(p) * s;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                vt[b][q] = (p < pend && r > p && r < s) ? vp[r] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int p = p0 + b;
+            if (p < pend && tb[b] != 0.0) apply_reflector_cols<S, CB>(col, vt[b], tb[b], p, lane, 0, ncol);
+        }
+    }
+
+    // local factorisation of the held columns below dc
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+        const int c = c0 + i;
+        if (i < ncol && c < dc) {
+            double xl = 0.0;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                if (r > c && r < s) xl += col[i][q] * col[i][q];
+            }
+            const double xn2 = wave_sum(xl);
+            const double alpha = row_of<S>(col[i], c);
+            double beta, tc, sc;
+            if (xn2 == 0.0) {
+                beta = alpha;
+                tc = 0.0;
+                sc = 1.0;
+            } else {
+                const double nrm = sqrt(alpha * alpha + xn2);
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                tc = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
+            }
+            double vt[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                double v = col[i][q];
+                if (r == c) v = beta;
+                else if (r > c && tc != 0.0) v = col[i][q] * sc;
+                col[i][q] = v;
+                vt[q] = (r > c && r < s) ? v : 0.0;
+            }
+            double* dst = C + static_cast<int64_t>(c) * s;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                if (r < s) dst[r] = col[i][q];
+            }
+            if (lane == 0) tau[c] = tc;
+            if (tc != 0.0) apply_reflector_cols<S, CB>(col, vt, tc, c, lane, i + 1, ncol);
+        }
+    }
+    if (c0 < dc && lane == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&sync->npub, static_cast<unsigned>(min(c0 + CB, dc)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (dc >= c0 + CB) return;
+
+    // ---- holder of g: Q^T g out, kappa guard, back substitution, r_est --------
+    double z[S];
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+        if (c0 + i == dc)
+#pragma unroll
+            for (int q = 0; q < S; ++q) z[q] = col[i][q];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const int r = lane + q * kWave;
+        if (r < s) g[r] = z[q];
+    }
+    // diagonal of T, one entry per lane-slot (all loads in flight together)
+    double dg[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const int j = lane + q * kWave;
+        dg[q] = (j < dc) ? fabs(C[static_cast<int64_t>(j) * s + j]) : 0.0;
+    }
+    int d_eff = 0;
+    double tmax = 0.0, tmin = INFINITY, kap = 0.0;
+    for (int j = 0; j < dc; ++j) {
+        const double a = row_of<S>(dg, j);
+        const double nmax = a > tmax ? a : tmax;
+        const double nmin = a < tmin ? a : tmin;
+        if (!(nmin > 0.0) || nmax / nmin > kappa_max) break;
+        tmax = nmax;
+        tmin = nmin;
+        kap = tmax / tmin;
+        d_eff = j + 1;
+    }
+    double rl = 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const int r = lane + q * kWave;
+        if (r >= d_eff && r < s) rl += z[q] * z[q];
+    }
+    const double rest = sqrt(wave_sum(rl));
+    // back substitution, column-oriented; the next columns of T are fetched
+    // kPrefetch steps ahead so the loads overlap the updates
+    constexpr int kPrefetch = 4;
+    double tc[kPrefetch][S];
+    double td[kPrefetch];
+#pragma unroll
+    for (int f = 0; f < kPrefetch; ++f) {
+        const int i = d_eff - 1 - f;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int r = lane + q * kWave;
+            tc[f][q] = (i >= 0 && r < i) ? C[static_cast<int64_t>(i) * s + r] : 0.0;
+        }
+        td[f] = (i >= 0) ? C[static_cast<int64_t>(i) * s + i] : 1.0;
+    }
+    for (int i0 = d_eff - 1; i0 >= 0; i0 -= kPrefetch) {
+#pragma unroll
+        for (int f = 0; f < kPrefetch; ++f) {
+            const int i = i0 - f;
+            if (i >= 0) {
+                const double zi = row_of<S>(z, i);
+                const double yi = zi / td[f];
+                if (lane == 0) y[i] = yi;
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+                    if (lane + q * kWave < i) z[q] -= tc[f][q] * yi;
+            }
+            // refill slot f with column i - kPrefetch
+            const int inext = i - kPrefetch;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                tc[f][q] = (inext >= 0 && r < inext) ? C[static_cast<int64_t>(inext) * s + r] : 0.0;
+            }
+            td[f] = (inext >= 0) ? C[static_cast<int64_t>(inext) * s + inext] : 1.0;
+        }
+    }
+    if (lane == 0) {
+        dout[0] = rest;
+        dout[1] = kap;
+        iout[0] = d_eff;
+        if (d_eff < dc) iout[1] |= SGMRES_FLAG_KAPPA_TRUNC;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_lsq(int s, const int* dc_dev, int dc_host, double* C, double* g, double kappa_max,
                       double* y, double* dout, int* iout, hipStream_t stream) {
     lsq_kernel<<<1, kLsqBlock, sizeof(double) * s, stream>>>(s, dc_dev, dc_host, C, g, kappa_max, y, dout, iout);
     return hipGetLastError();
+}
+
+size_t lsq_sync_bytes() { return sizeof(LsqSync); }
+
+hipError_t launch_lsq_pipeline(int s, int d_max, const int* dc_dev, int dc_host, double* C, double* g, double* tau,
+                               double kappa_max, double* y, double* dout, int* iout, void* sync, int* abort,
+                               uint64_t limit, hipStream_t stream) {
+    const int slots = (s + kWave - 1) / kWave;
+    const void* fn = nullptr;
+    if (slots <= 1) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<1>);
+    else if (slots <= 2) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<2>);
+    else if (slots <= 4) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<4>);
+    else if (slots <= 8) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<8>);
+    else return hipErrorInvalidValue;
+    hipError_t err = hipMemsetAsync(sync, 0, sizeof(LsqSync), stream);
+    if (err != hipSuccess) return err;
+    const int waves = (d_max + 1 + kPipeCols - 1) / kPipeCols;
+    const int blocks = (waves + kPipeWaves - 1) / kPipeWaves;
+    LsqSync* sp = static_cast<LsqSync*>(sync);
+    void* args[] = {&s, &dc_dev, &dc_host, &C, &g, &tau, &kappa_max, &y, &dout, &iout, &sp, &abort, &limit};
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kPipeBlock), args, 0, stream);
 }
 
 }  // namespace sg

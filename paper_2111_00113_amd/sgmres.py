@@ -60,6 +60,7 @@ class _Info(ctypes.Structure):
         ("t_basis_ms", ctypes.c_double),
         ("t_lsq_ms", ctypes.c_double),
         ("t_combine_ms", ctypes.c_double),
+        ("phase_us", ctypes.c_double * 8),
     ]
 
 
@@ -71,7 +72,8 @@ class _Options(ctypes.Structure):
         ("block_size", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("barrier_mode", ctypes.c_int32),
+        ("spmv_mode", ctypes.c_int32),
     ]
 
 
@@ -170,7 +172,8 @@ def _stream(stream):
 def _info(i: _Info) -> dict:
     return dict(cycles=i.cycles, steps=i.steps, d_eff_last=i.d_eff_last, flags=i.flags, relres=i.relres,
                 rest_est=i.rest_est, kappa_est=i.kappa_est, t_residual_ms=i.t_residual_ms,
-                t_basis_ms=i.t_basis_ms, t_lsq_ms=i.t_lsq_ms, t_combine_ms=i.t_combine_ms)
+                t_basis_ms=i.t_basis_ms, t_lsq_ms=i.t_lsq_ms, t_combine_ms=i.t_combine_ms,
+                phase_us=list(i.phase_us))
 
 
 def _raise(fn, rc):
@@ -180,7 +183,8 @@ def _raise(fn, rc):
 
 
 def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
-                 transposed=False, block_size=0, rows_per_thread=0, profile=False, stream=None):
+                 transposed=False, block_size=0, rows_per_thread=0, profile=False, barrier_mode=0,
+                 spmv_mode=0, stream=None):
     """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
 
     Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED (1);
@@ -188,7 +192,8 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     _check_dev(b, torch.float64, A.n)
     _check_dev(x, torch.float64, A.n)
     info = _Info()
-    opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0)
+    opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
+                    barrier_mode, spmv_mode)
     rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
                                ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     return _raise("sgmres_solve", rc), _info(info)

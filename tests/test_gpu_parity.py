@@ -101,7 +101,7 @@ CYCLE_CASES = [
     ("cd20_full", lambda: synth.convection_diffusion(20, (50.0, 20.0)), 40, 39, 82),
     ("cd30_k8", lambda: synth.convection_diffusion(30, (5.0, 1.0)), 20, 8, 42),
     ("cd45_k12_global", lambda: synth.convection_diffusion(45, (50.0, 20.0)), 24, 12, 50),
-    ("d1", lambda: synth.convection_diffusion(10), 1, 1, 2),
+    ("d1", lambda: synth.convection_diffusion(10), 1, 1, 8),
 ]
 
 
@@ -138,7 +138,8 @@ def test_arnoldi_breakdown(sg, orc):
 
 
 # ---------------------------------------------------------------- least squares
-@pytest.mark.parametrize("s,d,decay", [(80, 40, 1e-3), (400, 200, 1e-6), (7, 3, 1.0), (50, 1, 1.0)])
+@pytest.mark.parametrize("s,d,decay", [(80, 40, 1e-3), (400, 200, 1e-6), (7, 3, 1.0), (50, 1, 1.0), (600, 250, 1e-4),
+                                       (512, 511, 1e-2), (65, 64, 1e-3)])
 def test_sketched_lsq(sg, orc, s, d, decay):
     rng = np.random.default_rng(s + d)
     C = rng.standard_normal((s, d)) @ np.diag(np.logspace(0, np.log10(decay), d))
@@ -251,6 +252,25 @@ def test_solve_teacher_forced_cycles(sg, orc):
         x_o = x_next
 
 
+def test_barrier_modes_bit_identical(sg, orc):
+    # Every reduction on the GPU path runs in a fixed order, so a solve is
+    # bitwise reproducible; the XCD-leader grid barrier and the per-workgroup
+    # release reference barrier must therefore give identical bits.  Stale
+    # data behind a barrier would break that.
+    A = synth.convection_diffusion(256, (50.0, 20.0))  # n = 65536 spans all 8 XCDs
+    f = _t(synth.rhs(A.n, 0))
+    dA = sg.DeviceCSR.from_host(A)
+    outs = []
+    for mode in (0, 1, 0, 1):
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc, info = sg.sgmres_solve(dA, f, x, 60, 4, 120, 3, 0.0, 2, barrier_mode=mode)
+        outs.append((_np(x), info["relres"]))
+    ref = outs[0][0]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], ref)
+        assert o[1] == outs[0][1]
+
+
 def test_solve_edge_cases(sg, orc):
     A = synth.convection_diffusion(12)
     dA = sg.DeviceCSR.from_host(A)
@@ -264,6 +284,9 @@ def test_solve_edge_cases(sg, orc):
     with pytest.raises(sg.SGMRESError) as e:
         sg.sgmres_solve(dA, f, x, A.n + 1, 2, 2 * A.n + 4)
     assert e.value.rc == -1
+    with pytest.raises(sg.SGMRESError) as e:
+        sg.sgmres_solve(dA, f, x, 1, 1, 2)  # zeta = 8 > s
+    assert e.value.rc == -1
     bad = f.clone()
     bad[5] = float("nan")
     with pytest.raises(sg.SGMRESError) as e:
@@ -272,7 +295,7 @@ def test_solve_edge_cases(sg, orc):
     # n = 1 and d = 1
     A1 = synth.diagonal([3.0])
     x1 = torch.zeros(1, dtype=torch.float64, device=DEV)
-    rc, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A1), _t([6.0]), x1, 1, 1, 2, 0, 1e-14, 2)
+    rc, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A1), _t([6.0]), x1, 1, 1, 8, 0, 1e-14, 2)
     assert rc == sg.OK and abs(float(x1[0]) - 2.0) < 1e-15
 
 
