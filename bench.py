@@ -30,21 +30,40 @@ if ROOT not in sys.path:
 METRIC = "sGMRES solves/s at rel. residual 1e-10 (n=1M, d=200); HBM GB/s vs peak"
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
+# Basis-kernel HBM traffic per launch on the cd1024 workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE scaled by the copy calibration (summary and commands
+# in profiles/arnoldi_kernel_cd1024_hbm_counters.md).  Valid only for the kernel
+# source it was measured on; any change to it makes the figure stale (null).
+MEASURED_TRAFFIC = {"source_hash": "ecfc91c59e07f6ae", "bytes_per_launch": 19.1192e9}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    m = hashlib.sha256()
+    for f in ("arnoldi.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2111_00113_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def basis_launch_bytes(n: int, nnz: int, dc: float) -> float:
-    """Compulsory HBM bytes of one basis-kernel launch building dc columns.
+def basis_launch_bytes(n: int, nnz: int, k: int, dc: float) -> float:
+    """Algorithmic HBM bytes of one basis-kernel launch (dc Arnoldi steps).
 
-    Per column: CSR arrays (12 B per nonzero + 4 B per row pointer), the gathered
-    input column b_j (8n); per new column the written b_{j+1} (8n); at start the
-    residual read and b_1 written (16n).  The truncation window, m_j, w and the
-    sketch pattern stay on chip; block partial sums (a few kB per step) are not
-    counted."""
-    per_step = 12.0 * nnz + 4.0 * (n + 1) + 8.0 * n
-    return dc * per_step + 8.0 * n * (dc - 1) + 16.0 * n
+    Per step: the CSR arrays (12 B per nonzero + 4 B per row), the k window
+    columns read and b_{j+1} written: 12 nnz + 4n + 8n(k+1)."""
+    return dc * (12.0 * nnz + 4.0 * n + 8.0 * n * (k + 1))
+
+
+def compulsory_launch_bytes(n: int, nnz: int, dc: float) -> float:
+    """Bytes this kernel must move per launch: it keeps the window and the row
+    pointers on chip, so per step only the CSR column indices and values, the
+    gathered b_j and the written b_{j+1}; plus r read and b_1 written once."""
+    return dc * (12.0 * nnz + 8.0 * n) + 8.0 * n * (dc - 1) + 16.0 * n + 4.0 * (n + 1)
 
 
 def cpu_baseline(A, f, p, cycles_per_solve: float, sample_cols: int) -> dict:
@@ -166,7 +185,7 @@ def main() -> int:
     t_res = sum(i["t_residual_ms"] for i in infos)
     dc_avg = steps / cycles
     launch_ms = t_basis / cycles
-    launch_bytes = basis_launch_bytes(A.n, A.nnz, dc_avg)
+    launch_bytes = basis_launch_bytes(A.n, A.nnz, k, dc_avg)
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     # x after the last timed solve: confirm the residual with an independent host SpMV
     xr = x.cpu().numpy()
@@ -202,9 +221,13 @@ def main() -> int:
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
+                        if kernel_source_hash() == MEASURED_TRAFFIC["source_hash"] and args.workload == "cd1024"
+                        else None),
+            "traffic_unit": "bytes per launch",
             "kernel": "arnoldi_kernel (spmv_truncarnoldi)",
             "bytes_per_launch": launch_bytes,
+            "compulsory_bytes_per_launch": compulsory_launch_bytes(A.n, A.nnz, dc_avg),
             "avg_launch_ms": launch_ms,
         },
         "cycles_per_solve": cycles / args.steps,
