@@ -108,6 +108,45 @@ def cpu_baseline(A, f, p, cycles_per_solve: float, sample_cols: int) -> dict:
     }
 
 
+def grad_bench(args, A, f, p, sg, torch, np) -> int:
+    """Differentiable solve: L = |x(A, b) - x_t|^2, forward sGMRES on A, backward
+    sGMRES on A^T plus the gradient on A's pattern; one step = forward + backward."""
+    dev = "cuda:0"
+    rp = torch.as_tensor(A.row_ptr, device=dev)
+    ci = torch.as_tensor(A.col_idx, device=dev)
+    val = torch.as_tensor(A.val, device=dev)
+    bt = torch.as_tensor(f, device=dev)
+    xt = torch.as_tensor(np.random.default_rng(1).standard_normal(A.n), device=dev)
+
+    def step():
+        v = val.clone().requires_grad_(True)
+        b = bt.clone().requires_grad_(True)
+        x = sg.sgmres_solve_diff(rp, ci, v, b, d=p["d"], k=p["k"], s=p["s"], seed=p["seed"], tol=p["tol"],
+                                 restarts=p["restarts"])
+        L = ((x - xt) ** 2).sum()
+        L.backward()
+        return float(L.detach())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        L = step()
+        log(f"grad step {i}: L={L:.6e}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({
+        "metric": "differentiable sGMRES steps/s (forward solve + adjoint solve + dL/dA, dL/db)",
+        "value": args.steps / el, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: loss |x - x_t|^2, x_t ~ N(0,1) seed 1; forward and adjoint "
+                               f"d={p['d']}, k={p['k']}, s={p['s']}, tol={p['tol']:g}"},
+    }), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +158,8 @@ def main() -> int:
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
     ap.add_argument("--spmv-mode", type=int, default=0, help="0 row per thread, 1 CSR-stream")
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad"],
+                    help="solve: the sGMRES metric; grad: differentiable solve (forward + adjoint)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -164,6 +205,9 @@ def main() -> int:
         if rc != sg.OK:
             raise RuntimeError(f"solve did not converge: {info}")
         return info
+
+    if args.mode == "grad":
+        return grad_bench(args, A, f, p, sg, torch, np)
 
     for w in range(args.warmup):
         info = solve(False)

@@ -188,6 +188,14 @@ int sgmres_basis_combine(int64_t n, int d_eff, const double *B, int64_t ldb, con
 int sgmres_csr_transpose(const sgmres_csr_t *A, int32_t *t_row_ptr, int32_t *t_col_idx,
                          double *t_val, void *stream);
 
+/* Gradient of a linear solve with respect to the matrix entries, on A's
+ * sparsity pattern: dval[q] = alpha * u[i] * v[j] for each stored entry
+ * q = (i, j) of A (same order as A->val).  With x = A^{-1} b and the adjoint
+ * A^T lambda = dL/dx, alpha = -1, u = lambda, v = x gives dL/dA_ij =
+ * -lambda_i x_j (and dL/db = lambda).  u, v: n entries; dval: nnz entries. */
+int sgmres_csr_outer_grad(const sgmres_csr_t *A, const double *u, const double *v, double alpha,
+                          double *dval, void *stream);
+
 /* Frees the cached workspace of every device. */
 void sgmres_release_workspace(void);
 

@@ -16,7 +16,7 @@ __all__ = [
     "OK", "NOT_CONVERGED", "FLAG_KAPPA_TRUNC", "FLAG_BREAKDOWN", "KAPPA_MAX",
     "philox4x32_10", "sketch_pattern", "sketch_apply", "sketch_dense", "csr_spmv",
     "csr_transpose", "residual", "arnoldi_cycle", "sketched_lsq", "basis_combine",
-    "sgmres_solve", "sgmres_solve_transposed", "lib",
+    "sgmres_solve", "sgmres_solve_transposed", "dense_solve_gradient", "lib",
 ]
 
 OK = 0
@@ -236,3 +236,19 @@ def sgmres_solve_transposed(A, b, x0=None, d=40, k=2, s=None, zeta=8, seed=0, to
     """Restarted sGMRES on A^T x = b.  Returns (rc, x, info)."""
     s = 2 * d if s is None else s
     return _solve("oracle_sgmres_solve_transposed", A, b, x0, d, k, s, zeta, seed, tol, restarts, kappa_max)
+
+
+def dense_solve_gradient(A, b, xt):
+    """Loss L = |x - xt|^2 with x = A^{-1} b, in dense FP64 (numpy.linalg.solve).
+
+    Adjoint: A^T lam = dL/dx = 2 (x - xt); dL/db = lam; dL/dA_ij = -lam_i x_j,
+    returned on A's stored pattern (same order as A.val).  Returns
+    (x, L, dL/db, dL/dval)."""
+    D = A.to_dense()
+    x = np.linalg.solve(D, np.asarray(b, np.float64))
+    diff = x - xt
+    L = float(diff @ diff)
+    lam = np.linalg.solve(D.T, 2.0 * diff)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    gval = -lam[rows] * x[A.col_idx]
+    return x, L, lam, gval

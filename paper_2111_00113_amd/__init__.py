@@ -24,6 +24,8 @@ from .sgmres import (  # noqa: F401
     sgmres_sketched_lsq,
     sgmres_basis_combine,
     sgmres_csr_transpose,
+    sgmres_csr_outer_grad,
     sgmres_release_workspace,
     sgmres_version,
 )
+from .autograd import SGMRESSolve, sgmres_solve_diff  # noqa: F401,E402

@@ -573,6 +573,21 @@ int sgmres_csr_transpose(const sgmres_csr_t* A, int32_t* t_row_ptr, int32_t* t_c
     return SGMRES_OK;
 }
 
+int sgmres_csr_outer_grad(const sgmres_csr_t* A, const double* u, const double* v, double alpha, double* dval,
+                          void* stream) {
+    if (!csr_ok(A) || !u || !v || (A->nnz > 0 && !dval)) return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    SG_TRY(launch_csr_outer(A->n, A->row_ptr, A->col_idx, u, v, alpha, dval, st));
+    SG_TRY(hipStreamSynchronize(st));
+    return SGMRES_OK;
+}
+
 void sgmres_release_workspace(void) {
     std::lock_guard<std::mutex> lock(g_mutex);
     int cur = 0;

@@ -79,6 +79,9 @@ hipError_t launch_norm_finish(const double* part, int G, double* out, const doub
 // bad[0] |= 1 when the CSR arrays are malformed
 hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int* bad,
                             hipStream_t stream);
+// dval[q] = alpha * u[row(q)] * v[col(q)] on the sparsity pattern of A
+hipError_t launch_csr_outer(int64_t n, const int32_t* rp, const int32_t* ci, const double* u, const double* v,
+                            double alpha, double* dval, hipStream_t stream);
 // x[i] = v  for i < n
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t stream);
 hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t stream);

@@ -102,7 +102,28 @@ __global__ void csr_check_kernel(int64_t n, int64_t nnz, const int32_t* __restri
     if (err) atomicOr(bad, 1);
 }
 
+// dval[q] = alpha * u[i] * v[col[q]] for every nonzero q of row i
+__global__ void csr_outer_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const double* __restrict__ u, const double* __restrict__ v, double alpha,
+                                 double* __restrict__ dval) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double ai = alpha * u[i];
+        const int q1 = rp[i + 1];
+        for (int q = rp[i]; q < q1; ++q) dval[q] = ai * v[ci[q]];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_csr_outer(int64_t n, const int32_t* rp, const int32_t* ci, const double* u, const double* v,
+                            double alpha, double* dval, hipStream_t stream) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    csr_outer_kernel<<<static_cast<int>(g), 256, 0, stream>>>(n, rp, ci, u, v, alpha, dval);
+    return hipGetLastError();
+}
 
 hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int* bad,
                             hipStream_t stream) {

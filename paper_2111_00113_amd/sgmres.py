@@ -102,13 +102,14 @@ def lib():
     L.sgmres_sketched_lsq.argtypes = [i32, i32, vp, vp, dbl, vp, P(i32), P(dbl), P(dbl), P(i32), vp]
     L.sgmres_basis_combine.argtypes = [i64, i32, vp, i64, vp, vp, vp]
     L.sgmres_csr_transpose.argtypes = [P(_CSR), vp, vp, vp, vp]
+    L.sgmres_csr_outer_grad.argtypes = [P(_CSR), vp, vp, dbl, vp, vp]
     L.sgmres_release_workspace.argtypes = []
     L.sgmres_release_workspace.restype = None
     L.sgmres_version.argtypes = []
     L.sgmres_version.restype = ctypes.c_char_p
     for name in ("sgmres_solve", "sgmres_solve_transposed", "sgmres_solve_ex", "sgmres_sketch_pattern",
                  "sgmres_sketch_apply", "sgmres_residual", "sgmres_arnoldi_cycle", "sgmres_sketched_lsq",
-                 "sgmres_basis_combine", "sgmres_csr_transpose"):
+                 "sgmres_basis_combine", "sgmres_csr_transpose", "sgmres_csr_outer_grad"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -304,6 +305,17 @@ def sgmres_csr_transpose(A: DeviceCSR, stream=None) -> DeviceCSR:
                                     _stream(stream))
     _raise("sgmres_csr_transpose", rc)
     return DeviceCSR(A.n, trp, tci[: A.nnz], tv[: A.nnz])
+
+
+def sgmres_csr_outer_grad(A: DeviceCSR, u, v, alpha=-1.0, stream=None):
+    """Values alpha * u[i] * v[j] on A's pattern (gradient of a solve w.r.t. A)."""
+    _check_dev(u, torch.float64, A.n)
+    _check_dev(v, torch.float64, A.n)
+    dval = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=u.device)
+    rc = lib().sgmres_csr_outer_grad(ctypes.byref(A._c()), u.data_ptr(), v.data_ptr(), alpha, dval.data_ptr(),
+                                     _stream(stream))
+    _raise("sgmres_csr_outer_grad", rc)
+    return dval[: A.nnz]
 
 
 def sgmres_release_workspace():

@@ -389,3 +389,31 @@ def test_zero_rhs_and_argument_errors(orc):
     bad = f.copy()
     bad[3] = np.nan
     assert orc.sgmres_solve(A, bad, d=10, k=2, s=22)[0] == -5
+
+
+# --------------------------------------------------------------------------
+# Adjoint gradient of a solve (dense FP64 reference for the differentiable solve)
+# --------------------------------------------------------------------------
+def test_dense_gradient_matches_finite_differences(orc):
+    A = synth.random_dominant(30, offdiag=4, seed=41)
+    rng = np.random.default_rng(5)
+    b, xt = rng.standard_normal(30), rng.standard_normal(30)
+    x, L, gb, gval = orc.dense_solve_gradient(A, b, xt)
+
+    def loss(val, bb):
+        B = synth.CSR(A.n, A.row_ptr, A.col_idx, val)
+        return orc.dense_solve_gradient(B, bb, xt)[1]
+
+    h = 1e-6
+    for q in rng.choice(A.nnz, 12, replace=False):
+        vp, vm = A.val.copy(), A.val.copy()
+        vp[q] += h
+        vm[q] -= h
+        fd = (loss(vp, b) - loss(vm, b)) / (2 * h)
+        assert abs(fd - gval[q]) <= 1e-6 * max(1.0, abs(gval[q]))
+    for i in rng.choice(30, 6, replace=False):
+        bp, bm = b.copy(), b.copy()
+        bp[i] += h
+        bm[i] -= h
+        fd = (loss(A.val, bp) - loss(A.val, bm)) / (2 * h)
+        assert abs(fd - gb[i]) <= 1e-6 * max(1.0, abs(gb[i]))
