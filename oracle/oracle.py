@@ -17,6 +17,7 @@ __all__ = [
     "philox4x32_10", "sketch_pattern", "sketch_apply", "sketch_dense", "csr_spmv",
     "csr_transpose", "residual", "arnoldi_cycle", "sketched_lsq", "basis_combine",
     "sgmres_solve", "sgmres_solve_transposed", "dense_solve_gradient", "lib",
+    "chebyshev_cycle", "sgmres_solve_chebyshev",
 ]
 
 OK = 0
@@ -70,6 +71,17 @@ def lib():
         L.oracle_sketched_lsq.restype = _c.c_int
         L.oracle_basis_combine.argtypes = [_c.c_int64, _c.c_int, _f64p, _f64p, _f64p]
         L.oracle_basis_combine.restype = None
+        L.oracle_chebyshev_cycle.argtypes = [
+            _c.c_int64, _i32p, _i32p, _f64p, _f64p, _c.c_int, _c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32,
+            _c.c_double, _c.c_double, _c.c_double, _f64p, _f64p, _f64p, _f64p, _f64p,
+        ]
+        L.oracle_chebyshev_cycle.restype = _c.c_int
+        L.oracle_sgmres_solve_basis.argtypes = [
+            _c.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p, _c.c_int, _c.c_int, _c.c_int,
+            _c.c_int, _c.c_uint64, _c.c_double, _c.c_int, _c.c_double, _c.c_int, _c.c_double, _c.c_double,
+            _c.c_double, _f64p,
+        ]
+        L.oracle_sgmres_solve_basis.restype = _c.c_int
         for name in ("oracle_sgmres_solve", "oracle_sgmres_solve_transposed"):
             fn = getattr(L, name)
             fn.argtypes = [
@@ -175,6 +187,23 @@ def arnoldi_cycle(A, r, d: int, k: int, s: int, zeta: int, seed: int, cycle: int
     return dict(B=B.T.copy(), SB=SB.T.copy(), SAB=SAB.T.copy(), H=H.T.copy(), g=g, dc=dc, flags=flags.value)
 
 
+def chebyshev_cycle(A, r, d: int, s: int, zeta: int, seed: int, cycle: int, c: float, dx: float, dy: float):
+    """One Chebyshev-basis cycle (Section 4.4) + sketching; returns a dict with the
+    normalised basis B (n x d), SB, SAB (s x d), the raw norms nrm (d) and g."""
+    rp, ci, v = _csr(A)
+    n = A.n
+    B = np.zeros((d, n))
+    SB = np.zeros((d, s))
+    SAB = np.zeros((d, s))
+    nrm = np.zeros(d)
+    g = np.zeros(s)
+    rc = lib().oracle_chebyshev_cycle(n, rp, ci, v, np.ascontiguousarray(r, np.float64), d, s, zeta, seed, cycle,
+                                      c, dx, dy, B, SB, SAB, nrm, g)
+    if rc < 0:
+        raise ValueError(f"oracle_chebyshev_cycle rc={rc}")
+    return dict(B=B.T.copy(), SB=SB.T.copy(), SAB=SAB.T.copy(), nrm=nrm, g=g)
+
+
 def sketched_lsq(SAB, g, kappa_max: float = KAPPA_MAX):
     """Householder sketched LS on SAB (s x dc) and g; returns a dict."""
     SAB = np.asarray(SAB, np.float64)
@@ -229,6 +258,24 @@ def sgmres_solve(A, b, x0=None, d=40, k=2, s=None, zeta=8, seed=0, tol=1e-10, re
     """Restarted sGMRES on A x = b.  Returns (rc, x, info)."""
     s = 2 * d if s is None else s
     return _solve("oracle_sgmres_solve", A, b, x0, d, k, s, zeta, seed, tol, restarts, kappa_max)
+
+
+def sgmres_solve_chebyshev(A, b, box, x0=None, d=40, s=None, zeta=8, seed=0, tol=1e-10, restarts=100,
+                           kappa_max=KAPPA_MAX):
+    """Restarted sGMRES with the Chebyshev basis for box = (c, dx, dy).  Returns (rc, x, info)."""
+    s = 2 * d if s is None else s
+    rp, ci, v = _csr(A)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, np.float64, copy=True)
+    info = np.zeros(8)
+    c, dx, dy = (float(t) for t in box)
+    rc = lib().oracle_sgmres_solve_basis(
+        A.n, rp, ci, v, np.ascontiguousarray(b, np.float64), x, d, 1, s, zeta, seed, tol, restarts, kappa_max,
+        1, c, dx, dy, info,
+    )
+    return rc, x, dict(
+        cycles=int(info[0]), steps=int(info[1]), d_eff_last=int(info[2]), flags=int(info[3]),
+        relres=float(info[4]), rest_est=float(info[5]), kappa_est=float(info[6]),
+    )
 
 
 def sgmres_solve_transposed(A, b, x0=None, d=40, k=2, s=None, zeta=8, seed=0, tol=1e-10,

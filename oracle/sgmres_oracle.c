@@ -38,6 +38,9 @@
  *   R-tol     the stopping tolerance is the true relative residual |b-Ax|/|b|;
  *             the paper's `tol` (a condition-number bound) is kappa_max.
  *   R-restart a fresh sketch per cycle: Philox counter word 2 = cycle index.
+ *   R-cheb    Chebyshev basis (Section 4.4): the recurrence runs on the
+ *             unnormalised vectors; each is scaled to unit norm only for B,
+ *             S B and S A B.  A vector of norm 0 gives a zero column.
  */
 #include <math.h>
 #include <stdint.h>
@@ -272,6 +275,74 @@ int oracle_arnoldi_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col_i
 }
 
 /* ------------------------------------------------------------------------ */
+/* One cycle of the shifted-and-scaled Chebyshev basis (Section 4.4) with      */
+/* sketching (R-cheb).  The spectrum of A lies in the box [c - dx, c + dx] x   */
+/* [-dy, dy]; rho = max(dx, dy).  The recurrence, in the paper's scaling:      */
+/*   b_1 = r / |r|,   b_2 = (A - c I) b_1 / (2 rho),                           */
+/*   b_j = [ (A - c I) b_{j-1} - (dx^2 - dy^2) / (4 rho) b_{j-2} ] / rho.      */
+/* Outputs (column-major, caller-allocated):                                  */
+/*   B   n x d   normalised columns b_j / |b_j|                                */
+/*   SB  s x d   S of the normalised columns                                   */
+/*   SAB s x d   S (A times the normalised columns)                            */
+/*   nrm d       |b_j| of the unnormalised recurrence vectors                  */
+/*   g   s       S r                                                           */
+/* The unnormalised vectors shrink like 2^(1-j) for an interval box, so d is   */
+/* limited to where they stay normal numbers (d of a few hundred).             */
+/* ------------------------------------------------------------------------ */
+int oracle_chebyshev_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                           const double *val, const double *r, int d, int s, int zeta,
+                           uint64_t seed, uint32_t cycle, double c, double dx, double dy,
+                           double *B, double *SB, double *SAB, double *nrm, double *g) {
+    if (n < 1 || d < 1 || s < 1 || zeta < 1 || zeta > s || !(dx >= 0.0) || !(dy >= 0.0)) return OR_EINVAL;
+    const double rho = dx > dy ? dx : dy;
+    if (!(rho > 0.0)) return OR_EINVAL;
+    double *prev = (double *)calloc((size_t)n, sizeof(double)); /* b_{j-2} */
+    double *cur = (double *)malloc(sizeof(double) * (size_t)n);  /* b_{j-1} */
+    double *nxt = (double *)malloc(sizeof(double) * (size_t)n);  /* b_j */
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!prev || !cur || !nxt || !t) {
+        free(prev);
+        free(cur);
+        free(nxt);
+        free(t);
+        return OR_ENOMEM;
+    }
+    oracle_sketch_apply(n, r, seed, cycle, s, zeta, g);
+    const double beta = sqrt(dot(n, r, r));
+    const double qcoef = (dx * dx - dy * dy) / (4.0 * rho);
+    for (int j = 0; j < d; ++j) { /* 0-based: this iteration forms b_{j+1} */
+        if (j == 0) {
+            for (int64_t i = 0; i < n; ++i) nxt[i] = r[i] / beta;
+        } else {
+            oracle_csr_spmv(n, row_ptr, col_idx, val, cur, t); /* t = A b_{j} (1-based j) */
+            for (int64_t i = 0; i < n; ++i) t[i] -= c * cur[i];
+            if (j == 1) {
+                for (int64_t i = 0; i < n; ++i) nxt[i] = t[i] / (2.0 * rho);
+            } else {
+                for (int64_t i = 0; i < n; ++i) nxt[i] = (t[i] - qcoef * prev[i]) / rho;
+            }
+        }
+        /* normalised copy into B (the recurrence keeps the raw vector) */
+        const double nj = sqrt(dot(n, nxt, nxt));
+        nrm[j] = nj;
+        double *bj = B + (size_t)j * n;
+        for (int64_t i = 0; i < n; ++i) bj[i] = nj > 0.0 ? nxt[i] / nj : 0.0;
+        oracle_csr_spmv(n, row_ptr, col_idx, val, bj, t);
+        oracle_sketch_apply(n, bj, seed, cycle, s, zeta, SB + (size_t)j * s);
+        oracle_sketch_apply(n, t, seed, cycle, s, zeta, SAB + (size_t)j * s);
+        double *tmp = prev;
+        prev = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    free(prev);
+    free(cur);
+    free(nxt);
+    free(t);
+    return d;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sketched least squares, Algorithm 1 lines 9-13 and Section 3.3.             */
 /*                                                                            */
 /* C (s x dc, column-major, leading dim s) is overwritten by its Householder   */
@@ -364,12 +435,13 @@ void oracle_basis_combine(int64_t n, int d_eff, const double *B, const double *y
 /*   [3] flags (OR of all cycles)  [4] final relative residual                 */
 /*   [5] last r_est / |b|  [6] last kappa_est  [7] unused                      */
 /* ------------------------------------------------------------------------ */
-int oracle_sgmres_solve(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
-                        const double *val, const double *b, double *x, int d, int k, int s,
-                        int zeta, uint64_t seed, double tol, int restarts, double kappa_max,
-                        double *info) {
+/* basis: 0 = k-truncated Arnoldi; 1 = Chebyshev for the box (c, dx, dy), k unused. */
+int oracle_sgmres_solve_basis(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                              const double *val, const double *b, double *x, int d, int k, int s,
+                              int zeta, uint64_t seed, double tol, int restarts, double kappa_max,
+                              int basis, double c, double dx, double dy, double *info) {
     if (n < 1 || d < 1 || d > n || k < 1 || s < d + 1 || zeta < 1 || zeta > s || !(tol >= 0.0) ||
-        restarts < 0)
+        restarts < 0 || (basis != 0 && basis != 1))
         return OR_EINVAL;
     double stat[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int flags = 0;
@@ -386,11 +458,12 @@ int oracle_sgmres_solve(int64_t n, const int32_t *row_ptr, const int32_t *col_id
     double *SB = (double *)malloc(sizeof(double) * (size_t)s * d);
     double *SAB = (double *)malloc(sizeof(double) * (size_t)s * d);
     double *H = (double *)malloc(sizeof(double) * (size_t)(kk + 1) * d);
+    double *nrm = (double *)malloc(sizeof(double) * (size_t)d);
     double *g = (double *)malloc(sizeof(double) * (size_t)s);
     double *y = (double *)malloc(sizeof(double) * (size_t)d);
     double *tau = (double *)malloc(sizeof(double) * (size_t)d);
     int rc = OR_OK;
-    if (!r || !B || !SB || !SAB || !H || !g || !y || !tau) {
+    if (!r || !B || !SB || !SAB || !H || !nrm || !g || !y || !tau) {
         rc = OR_ENOMEM;
         goto done;
     }
@@ -411,8 +484,14 @@ int oracle_sgmres_solve(int64_t n, const int32_t *row_ptr, const int32_t *col_id
             rc = OR_NOT_CONVERGED;
             break;
         }
-        const int dc = oracle_arnoldi_cycle(n, row_ptr, col_idx, val, r, d, kk, s, zeta, seed,
-                                            (uint32_t)cycles, 2, B, SB, SAB, H, g, &flags);
+        const int dc = basis == 0 ? oracle_arnoldi_cycle(n, row_ptr, col_idx, val, r, d, kk, s, zeta, seed,
+                                                         (uint32_t)cycles, 2, B, SB, SAB, H, g, &flags)
+                                  : oracle_chebyshev_cycle(n, row_ptr, col_idx, val, r, d, s, zeta, seed,
+                                                           (uint32_t)cycles, c, dx, dy, B, SB, SAB, nrm, g);
+        if (dc < 0) {
+            rc = dc;
+            break;
+        }
         int d_eff = 0;
         double rest = 0.0, kap = 0.0;
         oracle_sketched_lsq(s, dc, SAB, g, kappa_max, y, tau, &d_eff, &rest, &kap, &flags);
@@ -433,10 +512,19 @@ done:
     free(SB);
     free(SAB);
     free(H);
+    free(nrm);
     free(g);
     free(y);
     free(tau);
     return rc;
+}
+
+int oracle_sgmres_solve(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        const double *val, const double *b, double *x, int d, int k, int s,
+                        int zeta, uint64_t seed, double tol, int restarts, double kappa_max,
+                        double *info) {
+    return oracle_sgmres_solve_basis(n, row_ptr, col_idx, val, b, x, d, k, s, zeta, seed, tol, restarts,
+                                     kappa_max, 0, 0.0, 0.0, 0.0, info);
 }
 
 /* Solve A^T x = b: transpose once, then the same restarted method. */

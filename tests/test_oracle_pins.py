@@ -417,3 +417,104 @@ def test_dense_gradient_matches_finite_differences(orc):
         bm[i] -= h
         fd = (loss(A.val, bp) - loss(A.val, bm)) / (2 * h)
         assert abs(fd - gb[i]) <= 1e-6 * max(1.0, abs(gb[i]))
+
+
+# --------------------------------------------------------------------------
+# Chebyshev basis, Section 4.4.  On a diagonal matrix the recurrence acts
+# entrywise, so column j (0-based) is b_1 times a degree-j polynomial of the
+# eigenvalue.  For a box [c +- dx] x [+-dy] with dx != dy it is
+# sigma^j T_j((lambda - c)/f) with f = sqrt(dx^2 - dy^2) (imaginary when
+# dy > dx; the powers of i then cancel) and sigma = f / (2 rho),
+# rho = max(dx, dy).  numpy's Chebyshev evaluator is the independent route.
+# --------------------------------------------------------------------------
+def _cheb_columns(lam, b1, d, c, dx, dy):
+    from numpy.polynomial import chebyshev as C
+
+    rho = max(dx, dy)
+    f = np.sqrt(complex(dx * dx - dy * dy))
+    sigma = f / (2 * rho)
+    cols, raw = [], []
+    for j in range(d):
+        v = b1 * C.chebval((lam - c) / f, [0] * j + [1]) * sigma**j
+        assert np.abs(v.imag).max() <= 1e-12 * np.abs(v.real).max()
+        v = v.real
+        raw.append(np.linalg.norm(v))
+        cols.append(v / np.linalg.norm(v))
+    return np.array(cols).T, np.array(raw)
+
+
+@pytest.mark.parametrize("c,dx,dy", [(4.0, 4.0, 0.0), (4.0, 4.0, 2.5), (3.0, 2.0, 3.5)])
+def test_chebyshev_basis_closed_form_on_diagonal(orc, c, dx, dy):
+    n, d = 64, 12
+    lam = np.linspace(c - dx, c + dx, n)
+    A = synth.diagonal(lam)
+    r = np.random.default_rng(7).standard_normal(n)
+    out = orc.chebyshev_cycle(A, r, d, 30, 4, 3, 1, c, dx, dy)
+    ref, raw = _cheb_columns(lam, r / np.linalg.norm(r), d, c, dx, dy)
+    assert np.abs(out["B"] - ref).max() <= 1e-12
+    # the paper's unnormalised scaling: |b_j| = |sigma|^j |T_j(u) b_1|
+    np.testing.assert_allclose(out["nrm"], raw, rtol=1e-12)
+
+
+def test_chebyshev_disk_box_gives_monomials(orc):
+    # dx = dy: gamma = 0, the recurrence is b_{j+1} = (A - c) b_j / rho (halved once)
+    n, d, c, rho = 40, 8, 2.0, 1.5
+    lam = np.linspace(0.7, 3.3, n)
+    A = synth.diagonal(lam)
+    r = np.random.default_rng(8).standard_normal(n)
+    out = orc.chebyshev_cycle(A, r, d, 20, 4, 0, 0, c, rho, rho)
+    b1 = r / np.linalg.norm(r)
+    for j in range(d):
+        v = b1 * ((lam - c) / rho) ** j * (0.5 if j >= 1 else 1.0)
+        assert np.abs(out["B"][:, j] - v / np.linalg.norm(v)).max() <= 1e-13
+        assert abs(out["nrm"][j] - np.linalg.norm(v)) <= 1e-13 * np.linalg.norm(v)
+
+
+def test_chebyshev_sketches_match_dense_sketch(orc):
+    A = synth.convection_diffusion(12, (10.0, 10.0))
+    r = np.random.default_rng(9).standard_normal(A.n)
+    d, s, zeta, seed, cyc = 10, 30, 5, 11, 2
+    out = orc.chebyshev_cycle(A, r, d, s, zeta, seed, cyc, 4.0, 4.0, 0.0)
+    S = orc.sketch_dense(A.n, seed, cyc, s, zeta)
+    D = A.to_dense()
+    np.testing.assert_allclose(out["SB"], S @ out["B"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(out["SAB"], S @ (D @ out["B"]), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(out["g"], S @ r, rtol=0, atol=1e-13)
+    # columns have unit norm and span the Krylov space K_d(A, r)
+    np.testing.assert_allclose(np.linalg.norm(out["B"], axis=0), 1.0, rtol=1e-14)
+    K = np.empty((A.n, d))
+    K[:, 0] = r / np.linalg.norm(r)
+    for j in range(1, d):
+        K[:, j] = D @ K[:, j - 1]
+        K[:, j] /= np.linalg.norm(K[:, j])
+    Q, _ = np.linalg.qr(K)
+    assert np.linalg.norm(out["B"] - Q @ (Q.T @ out["B"])) <= 1e-9
+
+
+def test_chebyshev_solve_exact_on_whole_space(orc):
+    # d = n: the basis spans R^n, so one cycle solves the system (Section 3)
+    A = synth.random_dominant(16, offdiag=4, seed=3)
+    ev = np.linalg.eigvals(A.to_dense())
+    c = 0.5 * (ev.real.max() + ev.real.min())
+    dx = 0.5 * (ev.real.max() - ev.real.min()) * 1.05
+    dy = np.abs(ev.imag).max() * 1.05
+    b = np.random.default_rng(4).standard_normal(16)
+    rc, x, info = orc.sgmres_solve_chebyshev(A, b, (c, dx, dy), d=16, s=40, zeta=6, tol=0.0, restarts=0)
+    x_ref = np.linalg.solve(A.to_dense(), b)
+    assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+
+
+def test_chebyshev_restarted_solve_reaches_tolerance(orc):
+    A = synth.convection_diffusion(24, (10.0, 10.0))
+    b = synth.rhs(A.n, 0)
+    rc, x, info = orc.sgmres_solve_chebyshev(A, b, (4.0, 4.0, 0.0), d=40, s=90, zeta=8, tol=1e-10, restarts=200)
+    assert rc == orc.OK
+    assert info["relres"] <= 1e-10
+    r = b - A.to_scipy() @ x
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+
+
+def test_chebyshev_rejects_empty_box(orc):
+    A = synth.diagonal(np.ones(5))
+    with pytest.raises(ValueError):
+        orc.chebyshev_cycle(A, np.ones(5), 2, 4, 2, 0, 0, 1.0, 0.0, 0.0)
