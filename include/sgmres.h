@@ -50,6 +50,9 @@ extern "C" {
 #define SGMRES_FLAG_KAPPA_TRUNC 1 /* a cycle used a prefix of its basis (kappa guard) */
 #define SGMRES_FLAG_BREAKDOWN 2   /* a cycle's basis ended early (invariant subspace) */
 
+#define SGMRES_BASIS_ARNOLDI 0   /* k-truncated Arnoldi (Algorithm 1) */
+#define SGMRES_BASIS_CHEBYSHEV 1 /* shifted-and-scaled Chebyshev recurrence (Section 4.4) */
+
 /* Square sparse matrix in CSR form; all arrays on the device. */
 typedef struct {
     int64_t n;              /* order, 1 <= n < 2^31 */
@@ -78,7 +81,9 @@ typedef struct {
      * (microseconds; profile only): [0] SpMV + dots, [1] sketch scatter,
      * [2] wait after phase 1, [3] first Gram-Schmidt update + dots,
      * [4] barrier after phase 2, [5] second update + new column,
-     * [6] sketch column sums, [7] wait after phase 3. */
+     * [6] sketch column sums, [7] wait after phase 3.  Chebyshev basis:
+     * [0] SpMV + recurrence, [1] norm and sketch partials, [2] barrier wait,
+     * [7] end-of-cycle reduction. */
     double phase_us[8];
 } sgmres_info_t;
 
@@ -95,7 +100,11 @@ typedef struct {
                              results are bit-identical) */
     int32_t spmv_mode;  /* basis-kernel SpMV: 0 one row per thread (default), 1
                            nonzeros streamed through LDS in BLOCK-row chunks; both
-                           sum each row in nonzero order */
+                           sum each row in nonzero order (Arnoldi basis only) */
+    int32_t basis;      /* SGMRES_BASIS_ARNOLDI (default) or SGMRES_BASIS_CHEBYSHEV */
+    double cheb_c;      /* Chebyshev basis: the spectrum of A lies in the box */
+    double cheb_dx;     /* [cheb_c - cheb_dx, cheb_c + cheb_dx] x [-cheb_dy, cheb_dy] */
+    double cheb_dy;     /* (Section 4.4); dx, dy >= 0, max(dx, dy) > 0; k is unused */
 } sgmres_options_t;
 
 /*
@@ -167,6 +176,24 @@ int sgmres_residual(const sgmres_csr_t *A, const double *f, const double *x, dou
 int sgmres_arnoldi_cycle(const sgmres_csr_t *A, const double *r, int d, int k, int s, int zeta,
                          uint64_t seed, uint32_t cycle, double *B, int64_t ldb, double *SB,
                          double *SAB, double *H, double *g, int *dc, int *flags, void *stream);
+
+/* One cycle of the Chebyshev basis (Section 4.4) with sketching.  For the
+ * box [c - dx, c + dx] x [-dy, dy] containing the spectrum, rho = max(dx, dy):
+ * b_1 = r/|r|, b_2 = (A - cI) b_1 / (2 rho),
+ * b_j = [(A - cI) b_{j-1} - (dx^2 - dy^2)/(4 rho) b_{j-2}] / rho, and each
+ * column is scaled to unit norm after its use.  Outputs (device):
+ *   B        n x d, ld ldb >= n: the unnormalised recurrence vectors
+ *            kappa^(j-1) b_j, kappa = 2 rho / (dx + dy) (a constant rescale
+ *            per step that normalisation removes)
+ *   colnorm  d: |B[:, j]|_2; column j of the normalised basis is B[:, j]/colnorm[j]
+ *   SB, SAB  s x d (ld s): S and S A applied to the normalised columns
+ *   g        s: S r
+ * A column of norm 0 gives zero sketch columns.  1 <= d <= 1024,
+ * 1 <= s <= 4096, 1 <= zeta <= min(s, 32); dx, dy >= 0 with max(dx, dy) > 0. */
+int sgmres_chebyshev_cycle(const sgmres_csr_t *A, const double *r, int d, int s, int zeta,
+                           uint64_t seed, uint32_t cycle, double c, double dx, double dy,
+                           double *B, int64_t ldb, double *SB, double *SAB, double *colnorm,
+                           double *g, void *stream);
 
 /* Sketched least squares (Algorithm 1 solve step; Section 3.3).  C (s x dc,
  * ld s) is overwritten by its Householder factorisation (T in the upper

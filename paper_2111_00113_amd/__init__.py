@@ -13,6 +13,8 @@ from .sgmres import (  # noqa: F401
     NOT_CONVERGED,
     FLAG_BREAKDOWN,
     FLAG_KAPPA_TRUNC,
+    BASIS_ARNOLDI,
+    BASIS_CHEBYSHEV,
     LIB_PATH,
     lib,
     sgmres_solve,
@@ -21,6 +23,7 @@ from .sgmres import (  # noqa: F401
     sgmres_sketch_apply,
     sgmres_residual,
     sgmres_arnoldi_cycle,
+    sgmres_chebyshev_cycle,
     sgmres_sketched_lsq,
     sgmres_basis_combine,
     sgmres_csr_transpose,

@@ -33,7 +33,7 @@ CFLAGS = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
-SOURCES = ["arnoldi.hip", "capi.hip", "lsq.hip", "sketch.hip", "transpose.hip", "vec.hip"]
+SOURCES = ["arnoldi.hip", "arnoldi_sb.hip", "capi.hip", "chebyshev.hip", "lsq.hip", "sketch.hip", "transpose.hip", "vec.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

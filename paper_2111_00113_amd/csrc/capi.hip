@@ -70,6 +70,10 @@ struct Workspace {
     size_t part_sk_cap = 0;
     double* part_vec = nullptr;
     size_t part_vec_cap = 0;
+    double* part_nrm = nullptr;  // Chebyshev column-norm partials, d x G
+    size_t part_nrm_cap = 0;
+    double* colnorm = nullptr;  // Chebyshev column norms, d
+    size_t colnorm_cap = 0;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
@@ -158,8 +162,32 @@ struct SolveArgs {
     int profile;
     int per_block_release;
     int spmv_mode;
+    int basis;  // SGMRES_BASIS_*
+    double cheb_c, cheb_dx, cheb_dy;
     hipStream_t stream;
 };
+
+// Coefficients of the rescaled Chebyshev recurrence for the box [c +- dx, +-dy]
+// (Section 4.4): with rho = max(dx, dy), gamma = (dx^2 - dy^2) / (4 rho^2) and
+// the per-step rescale kappa = 2 rho / (dx + dy),
+//   bt_2 = (kappa / (2 rho)) (A - c) bt_1,
+//   bt_{j+1} = (kappa / rho) (A - c) bt_j - kappa^2 gamma bt_{j-1}.
+struct ChebCoef {
+    double c, a1, a, q;
+};
+
+bool cheb_coefficients(double c, double dx, double dy, ChebCoef* out) {
+    if (!std::isfinite(c) || !std::isfinite(dx) || !std::isfinite(dy) || dx < 0.0 || dy < 0.0) return false;
+    const double rho = dx > dy ? dx : dy;
+    if (!(rho > 0.0)) return false;
+    const double kap = 2.0 * rho / (dx + dy);
+    const double gam = (dx * dx - dy * dy) / (4.0 * rho * rho);
+    out->c = c;
+    out->a1 = kap / (2.0 * rho);
+    out->a = kap / rho;
+    out->q = kap * kap * gam;
+    return true;
+}
 
 // HIP events bracketing the kernels of one cycle (profiling only).
 struct CycleEvents {
@@ -231,6 +259,48 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
     return SGMRES_OK;
 }
 
+// One Chebyshev basis cycle on the residual in ws.r (norm in ws.sc->beta).
+int run_cheb_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int s, int zeta, uint64_t seed, uint32_t cycle,
+                   const ArnoldiLaunch& L, const ChebCoef& cf, double* B, int64_t ldb, double* SB, double* SAB,
+                   double* colnorm, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
+                   int per_block_release = 0, bool phase_timing = false, int sketch_basis = 1) {
+    SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
+    if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
+    ChebParams p{};
+    p.n = A.n;
+    p.rp = A.row_ptr;
+    p.ci = A.col_idx;
+    p.val = A.val;
+    p.r = ws.r;
+    p.beta = &ws.sc->beta;
+    p.B = B;
+    p.ldb = ldb;
+    p.SB = SB;
+    p.SAB = SAB;
+    p.colnorm = colnorm;
+    p.g = g;
+    p.d = d;
+    p.s = s;
+    p.zeta = zeta;
+    p.seed = seed;
+    p.cycle = cycle;
+    p.c = cf.c;
+    p.a1 = cf.a1;
+    p.a = cf.a;
+    p.q = cf.q;
+    p.part_sk = ws.part_sk;
+    p.part_nrm = ws.part_nrm;
+    p.sync = ws.sync;
+    p.per_block_release = per_block_release;
+    p.abort = &ws.sc->abort;
+    p.status = &ws.sc->dc;
+    p.spin_limit = kSpinLimitTicks;
+    p.phase_ticks = phase_timing ? ws.sc->phase_ticks : nullptr;
+    p.sketch_basis = sketch_basis;
+    SG_TRY(chebyshev_launch(L, p, stream));
+    return SGMRES_OK;
+}
+
 // Sketched least squares on C (s x dc): the column-owner pipeline when s fits
 // its register layout, else the one-workgroup kernel.
 int run_lsq(Workspace& ws, int s, int d_max, const int* dc_dev, int dc_host, double* C, double* g, double kappa_max,
@@ -254,13 +324,23 @@ int check_csr(Workspace& ws, const sgmres_csr_t& A, hipStream_t st) {
     return ws.host_sc->csr_bad ? SGMRES_ECSR : SGMRES_OK;
 }
 
+// sketch_basis selects the kernel instance that also forms S B (the cycle
+// entry point); the solve uses S A B and g only.
 int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int block, int rpt,
-                    ArnoldiLaunch* L) {
-    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0};
+                    ArnoldiLaunch* L, int sketch_basis) {
+    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis};
     if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
     SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(k + 1) * L->grid));
     SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
     SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
+    return SGMRES_OK;
+}
+
+int prepare_cheb(Workspace& ws, int64_t n, int d, int s, int zeta, int block, int rpt, ArnoldiLaunch* L) {
+    ArnoldiShape shape{n, d, 1, s, zeta, block, rpt, 0, 0, 0};
+    if (chebyshev_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
+    SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
+    SG_TRY(ensure(ws.part_nrm, ws.part_nrm_cap, static_cast<size_t>(d) * L->grid));
     return SGMRES_OK;
 }
 
@@ -282,8 +362,13 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     SG_TRY(ensure(ws.g, ws.g_cap, static_cast<size_t>(a.s)));
     SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(a.d)));
     SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    const bool cheb = a.basis == SGMRES_BASIS_CHEBYSHEV;
+    ChebCoef cf{};
+    if (cheb && !cheb_coefficients(a.cheb_c, a.cheb_dx, a.cheb_dy, &cf)) return SGMRES_EINVAL;
+    if (cheb) SG_TRY(ensure(ws.colnorm, ws.colnorm_cap, static_cast<size_t>(a.d)));
     ArnoldiLaunch L{};
-    rc = prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L);
+    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L)
+              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0);
     if (rc) return rc;
     rc = check_csr(ws, a.A, st);
     if (rc) return rc;
@@ -347,15 +432,21 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
             status = SGMRES_NOT_CONVERGED;
             break;
         }
-        rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
-                       ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
-                       a.spmv_mode);
+        // the solve needs S A B and g only; S B is not formed
+        if (cheb)
+            rc = run_cheb_cycle(ws, a.A, a.d, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, cf, ws.B, n,
+                                ws.SB, ws.SAB, ws.colnorm, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release,
+                                ev.on, 0);
+        else
+            rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
+                           ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
+                           a.spmv_mode);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
         rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.l1, st));
-        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st));
+        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st, cheb ? ws.colnorm : nullptr));
         if (ev.on) SG_TRY(hipEventRecord(ev.c1, st));
         ++cycles;
     }
@@ -389,6 +480,15 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     a.profile = opts ? opts->profile : 0;
     a.per_block_release = opts ? opts->barrier_mode : 0;
     a.spmv_mode = opts ? opts->spmv_mode : 0;
+    a.basis = opts ? opts->basis : SGMRES_BASIS_ARNOLDI;
+    if (a.basis != SGMRES_BASIS_ARNOLDI && a.basis != SGMRES_BASIS_CHEBYSHEV) return SGMRES_EINVAL;
+    if (a.basis == SGMRES_BASIS_CHEBYSHEV) {
+        ChebCoef cf{};
+        if (!cheb_coefficients(opts->cheb_c, opts->cheb_dx, opts->cheb_dy, &cf)) return SGMRES_EINVAL;
+        a.cheb_c = opts->cheb_c;
+        a.cheb_dx = opts->cheb_dx;
+        a.cheb_dy = opts->cheb_dy;
+    }
     a.stream = static_cast<hipStream_t>(stream);
     if (opts && opts->transposed) {
         Workspace* wsp = nullptr;
@@ -497,7 +597,7 @@ int sgmres_arnoldi_cycle(const sgmres_csr_t* A, const double* r, int d, int k, i
     SG_TRY(ensure(ws->r, ws->r_cap, static_cast<size_t>(n)));
     SG_TRY(ensure(ws->part_vec, ws->part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
     ArnoldiLaunch L{};
-    rc = prepare_arnoldi(*ws, n, d, k, s, zeta, 0, 0, &L);
+    rc = prepare_arnoldi(*ws, n, d, k, s, zeta, 0, 0, &L, 1);
     if (rc) return rc;
     rc = check_csr(*ws, *A, st);
     if (rc) return rc;
@@ -513,6 +613,37 @@ int sgmres_arnoldi_cycle(const sgmres_csr_t* A, const double* r, int d, int k, i
     if (ws->host_sc->abort) return SGMRES_ETIMEOUT;
     if (dc) *dc = ws->host_sc->dc;
     if (flags) *flags |= ws->host_sc->flags;
+    return SGMRES_OK;
+}
+
+int sgmres_chebyshev_cycle(const sgmres_csr_t* A, const double* r, int d, int s, int zeta, uint64_t seed,
+                           uint32_t cycle, double c, double dx, double dy, double* B, int64_t ldb, double* SB,
+                           double* SAB, double* colnorm, double* g, void* stream) {
+    if (!csr_ok(A) || !r || !B || !SB || !SAB || !colnorm || !g || ldb < A->n) return SGMRES_EINVAL;
+    if (d < 1 || d > kMaxD || s < 1 || s > kMaxS || zeta < 1 || zeta > s || zeta > kMaxZeta) return SGMRES_EINVAL;
+    ChebCoef cf{};
+    if (!cheb_coefficients(c, dx, dy, &cf)) return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = A->n;
+    SG_TRY(ensure(ws->r, ws->r_cap, static_cast<size_t>(n)));
+    SG_TRY(ensure(ws->part_vec, ws->part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    ArnoldiLaunch L{};
+    rc = prepare_cheb(*ws, n, d, s, zeta, 0, 0, &L);
+    if (rc) return rc;
+    rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    SG_TRY(hipMemsetAsync(&ws->sc->dc, 0, 5 * sizeof(int), st));
+    SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, r, nullptr, ws->r, ws->part_vec, st));
+    SG_TRY(launch_norm_finish(ws->part_vec, vec_grid(n), &ws->sc->beta, nullptr, st));
+    rc = run_cheb_cycle(*ws, *A, d, s, zeta, seed, cycle, L, cf, B, ldb, SB, SAB, colnorm, g, st);
+    if (rc) return rc;
+    rc = copy_scalars(*ws, st);
+    if (rc) return rc;
+    if (ws->host_sc->abort) return SGMRES_ETIMEOUT;
     return SGMRES_OK;
 }
 
@@ -596,7 +727,8 @@ void sgmres_release_workspace(void) {
         (void)hipSetDevice(kv.first);
         Workspace& w = kv.second;
         void* ptrs[] = {w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
-                        w.part_vec, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val, w.t_scratch};
+                        w.part_vec, w.part_nrm, w.colnorm, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
+                        w.t_scratch};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);

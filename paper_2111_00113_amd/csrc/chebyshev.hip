@@ -1,0 +1,280 @@
+// Chebyshev basis cycle: the shifted-and-scaled Chebyshev recurrence of
+// arXiv:2111.00113 Section 4.4 (equation for b_j, j >= 3, with the starting
+// vectors b_1 = r/|r|, b_2 = (A - cI) b_1 / (2 rho)), fused with CSR SpMV and
+// sparse-sign sketching in one persistent cooperative launch.
+//
+// The recurrence has no inner products, so a step needs one grid barrier (the
+// new column must be complete before any block gathers it for the next SpMV)
+// and no grid reduction.  The paper rescales every column to unit norm after
+// its use in the recurrence; here the norms are accumulated as block partials
+// during the cycle and applied to the sketched columns at the end, so B holds
+// the raw recurrence vectors and `colnorm` their norms.  The raw vectors are
+// bt_j = kappa^(j-1) b_j with kappa = 2 rho / (dx + dy): a constant rescale per
+// step (removed again by the normalisation) that keeps |bt_j| near |r|/|r| when
+// the box encloses the spectrum, instead of decaying like 2^(1-j) for an
+// interval.
+//
+// Per step j (row state in registers: bt_{j-1}, bt_j):
+//   m = A bt_j;  bt_{j+1} = a (m - c bt_j) - q bt_{j-1} -> B[:, j+1]  -- arrive --
+//   block partials: |bt_j|^2, S m (and S bt_j when SB is wanted)     -- wait --
+// End of cycle: block u reduces column u's norm, then its sketch entries
+// scaled by 1/(sqrt(zeta) |bt_u|); the last unit is g = S r.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace sg {
+
+namespace {
+
+template <int R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
+    extern __shared__ double smem[];
+    constexpr int NW = BLOCK / kWave;
+    constexpr int RB = R * BLOCK;
+    const int s = p.s;
+    const int zeta = p.zeta;
+    const int64_t n = p.n;
+    // LDS: vals (2 RB doubles; raw pattern at init) | reduction scratch (NW + 1)
+    //      | sketch piece sums | list starts (s+1) | counters (s) | lists (zeta RB)
+    double* vals = smem;
+    double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
+    double* red_out = red_tmp + NW;
+    double* sk_tmp = red_out + 1;
+    int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
+    int* lcount = lstart + (s + 1);
+    uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
+    __shared__ unsigned sync_lds[2];
+    __shared__ double unit_scale;
+
+    const int G = gridDim.x;
+    const int blk = xcd_logical_block(blockIdx.x, G);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const int64_t base = static_cast<int64_t>(blk) * RB + tid;
+    const double scale = 1.0 / sqrt(static_cast<double>(zeta));
+    const int64_t slab = static_cast<int64_t>(2 * s) * G;
+
+    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
+                 p.per_block_release != 0};
+    bar.setup(sync_lds);
+
+    int rbeg[R], rlen[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        rbeg[r] = 0;
+        rlen[r] = 0;
+        if (row < n) {
+            rbeg[r] = p.rp[row];
+            rlen[r] = p.rp[row + 1] - rbeg[r];
+        }
+    }
+    sketch_lists_build<R, BLOCK>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
+                                 lcount, lists);
+
+    const int sk_v0 = p.sketch_basis ? 0 : 1;
+    const int sk_nv = p.sketch_basis ? 2 : 1;
+
+    // ---- init: g partial (S r), bt_1 = r/|r| ---------------------------------
+    const double beta = *p.beta;
+    double bprev[R], bcur[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        double rv = 0.0;
+        bprev[r] = 0.0;
+        bcur[r] = 0.0;
+        if (row < n) {
+            rv = p.r[row];
+            bcur[r] = rv / beta;
+            p.B[row] = bcur[r];
+        }
+        vals[r * BLOCK + tid] = rv;
+    }
+    __syncthreads();
+    sketch_lists_apply<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, sk_tmp,
+                              p.part_sk + static_cast<int64_t>(p.d) * slab, G, blk);
+    bar.sync();
+
+    const bool timing = p.phase_ticks != nullptr && blk == 0 && tid == 0;
+    uint64_t t_last = timing ? __builtin_amdgcn_s_memrealtime() : 0;
+    auto tick = [&](int k) {
+        if (timing) {
+            const uint64_t t = __builtin_amdgcn_s_memrealtime();
+            p.phase_ticks[k] += t - t_last;
+            t_last = t;
+        }
+    };
+
+    for (int j = 0; j < p.d; ++j) {
+        const double* bj = p.B + static_cast<int64_t>(j) * p.ldb;
+        double m[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double am = 0.0;
+            for (int q = 0; q < rlen[r]; ++q) am += p.val[rbeg[r] + q] * bj[p.ci[rbeg[r] + q]];
+            m[r] = am;
+        }
+        const bool more = j + 1 < p.d;
+        double bnext[R];
+        if (more) {
+            const double a = (j == 0) ? p.a1 : p.a;
+            const double q = (j == 0) ? 0.0 : p.q;
+            double* bn = p.B + static_cast<int64_t>(j + 1) * p.ldb;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+                bnext[r] = a * (m[r] - p.c * bcur[r]) - q * bprev[r];
+                if (row < n) bn[row] = bnext[r];
+            }
+            tick(0);
+            bar.arrive();
+        } else {
+            tick(0);
+        }
+        // partials of this step while the barrier completes
+        double nn = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            nn += bcur[r] * bcur[r];
+            if (p.sketch_basis) vals[r * BLOCK + tid] = bcur[r];
+            vals[RB + r * BLOCK + tid] = m[r];
+        }
+        const double nv[1] = {nn};
+        block_sum<1>(nv, 1, red_tmp, red_out);  // also publishes vals
+        if (tid == 0) p.part_nrm[static_cast<int64_t>(j) * G + blk] = red_out[0];
+        sketch_lists_apply<BLOCK>(sk_v0, sk_nv, 0, s, vals, RB, s, lstart, lists, sk_tmp,
+                                  p.part_sk + static_cast<int64_t>(j) * slab, G, blk);
+        tick(1);
+        if (more) {
+            bar.wait();
+            tick(2);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bprev[r] = bcur[r];
+                bcur[r] = bnext[r];
+            }
+        }
+    }
+
+    // ---- end of cycle: normalise and sum the sketch partials across blocks ---
+    bar.sync();
+    const int nsl = p.sketch_basis ? 2 * s : s;
+    const int off = p.sketch_basis ? 0 : s;
+    for (int u = blk; u <= p.d; u += G) {
+        if (u < p.d) {
+            if (wid == 0) {
+                const double* col = p.part_nrm + static_cast<int64_t>(u) * G;
+                double t = 0.0;
+                for (int g = lane; g < G; g += kWave) t += col[g];
+                t = wave_sum(t);
+                if (lane == 0) {
+                    const double nrm = sqrt(t);
+                    p.colnorm[u] = nrm;
+                    unit_scale = nrm > 0.0 ? scale / nrm : 0.0;
+                }
+            }
+        } else if (tid == 0) {
+            unit_scale = scale;
+        }
+        __syncthreads();
+        const double us = unit_scale;
+        const int ne = (u < p.d) ? nsl : s;
+        for (int e = wid; e < ne; e += NW) {
+            const int ee = (u < p.d) ? e + off : e;
+            const double* col = p.part_sk + static_cast<int64_t>(u) * slab + static_cast<int64_t>(ee) * G;
+            double t = 0.0;
+            for (int g = lane; g < G; g += kWave) t += col[g];
+            t = wave_sum(t) * us;
+            if (lane == 0) {
+                if (u == p.d) p.g[ee] = t;
+                else if (ee < s) p.SB[static_cast<int64_t>(u) * s + ee] = t;
+                else p.SAB[static_cast<int64_t>(u) * s + (ee - s)] = t;
+            }
+        }
+        __syncthreads();
+    }
+    tick(7);
+    if (blk == 0 && tid == 0) p.status[0] = p.d;
+}
+
+using KernelFn = void (*)(ChebParams);
+
+template <int BLOCK>
+KernelFn pick(int R) {
+    switch (R) {
+        case 1: return chebyshev_kernel<1, BLOCK>;
+        case 2: return chebyshev_kernel<2, BLOCK>;
+        case 4: return chebyshev_kernel<4, BLOCK>;
+        case 8: return chebyshev_kernel<8, BLOCK>;
+        default: return nullptr;
+    }
+}
+
+KernelFn pick_kernel(int block, int R) {
+    switch (block) {
+        case 256: return pick<256>(R);
+        case 512: return pick<512>(R);
+        case 1024: return pick<1024>(R);
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+size_t chebyshev_lds_bytes(int block, int R, int s, int zeta) {
+    const int nw = block / kWave;
+    const int RB = R * block;
+    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw + 1 + 2 * s * kSketchParts) +
+           sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
+}
+
+hipError_t chebyshev_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {
+    int device = 0;
+    hipError_t err = hipGetDevice(&device);
+    if (err != hipSuccess) return err;
+    int cus = 0;
+    err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (err != hipSuccess) return err;
+    int lds_max = 0;
+    err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (err != hipSuccess) return err;
+    const int blocks_try[3] = {1024, 512, 256};
+    const int rows_try[4] = {1, 2, 4, 8};
+    for (int bi = 0; bi < 3; ++bi) {
+        const int block = blocks_try[bi];
+        if (shape.block && block != shape.block) continue;
+        for (int ri = 0; ri < 4; ++ri) {
+            const int R = rows_try[ri];
+            if (shape.rows_per_thread && R != shape.rows_per_thread) continue;
+            const size_t lds = chebyshev_lds_bytes(block, R, shape.s, shape.zeta);
+            if (lds > static_cast<size_t>(lds_max)) continue;
+            KernelFn fn = pick_kernel(block, R);
+            if (!fn) continue;
+            err = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(lds));
+            if (err != hipSuccess) continue;
+            int per_cu = 0;
+            err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), block, lds);
+            if (err != hipSuccess || per_cu < 1) continue;
+            const int64_t need = (shape.n + static_cast<int64_t>(R) * block - 1) / (static_cast<int64_t>(R) * block);
+            if (need > static_cast<int64_t>(per_cu) * cus) continue;
+            out->fn = reinterpret_cast<const void*>(fn);
+            out->block = block;
+            out->R = R;
+            out->KW = 0;
+            out->grid = static_cast<int>(need);
+            out->lds = lds;
+            return hipSuccess;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t chebyshev_launch(const ArnoldiLaunch& L, ChebParams params, hipStream_t stream) {
+    void* args[] = {&params};
+    return hipLaunchCooperativeKernel(L.fn, dim3(L.grid), dim3(L.block), args, static_cast<unsigned>(L.lds), stream);
+}
+
+}  // namespace sg

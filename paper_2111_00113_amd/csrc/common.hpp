@@ -259,6 +259,127 @@ struct GridSync {
     }
 };
 
+// --------------------------------------------------------------------------
+// Block-local sketch lists.  The sparse sign pattern of the block's own rows
+// (RB = R * BLOCK rows; thread t owns local rows r * BLOCK + t) is generated
+// once per cycle and regrouped by sketch row: list e holds the local rows
+// whose column of S has a nonzero in row e, each packed as
+// (local << 1) | negative, in ascending local order.  A block's share of S v
+// is then a fixed-order sum over each list: no atomics, reproducible bits.
+// --------------------------------------------------------------------------
+constexpr int kSketchParts = 4;  // each list is summed in this many pieces
+
+// raw: zeta * RB uint16 of scratch; lstart: s + 1 ints; lcount: s ints;
+// lists: zeta * RB uint16.  Ends with a __syncthreads().
+template <int R, int BLOCK>
+__device__ __forceinline__ void sketch_lists_build(uint64_t seed, uint32_t cycle, int64_t base, int64_t n, int s, int zeta,
+                                   uint16_t* raw, int* lstart, int* lcount, uint16_t* lists) {
+    constexpr int RB = R * BLOCK;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        if (row < n) sketch_column(seed, cycle, row, s, zeta, raw + r * BLOCK + tid, RB);
+    }
+    for (int e = tid; e < s; e += BLOCK) lcount[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        if (row < n)
+            for (int t = 0; t < zeta; ++t) atomicAdd(&lcount[raw[t * RB + r * BLOCK + tid] >> 1], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int e = 0; e < s; ++e) {
+            lstart[e] = run;
+            run += lcount[e];
+            lcount[e] = 0;
+        }
+        lstart[s] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        if (row < n) {
+            const int local = r * BLOCK + tid;
+            for (int t = 0; t < zeta; ++t) {
+                const unsigned e = raw[t * RB + local];
+                const int pos = lstart[e >> 1] + atomicAdd(&lcount[e >> 1], 1);
+                lists[pos] = static_cast<uint16_t>((local << 1) | (e & 1u));
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < s; e += BLOCK) {  // insertion sort: fixed order inside each list
+        const int q0 = lstart[e], q1 = lstart[e + 1];
+        for (int q = q0 + 1; q < q1; ++q) {
+            const uint16_t key = lists[q];
+            int z = q - 1;
+            while (z >= q0 && lists[z] > key) {
+                lists[z + 1] = lists[z];
+                --z;
+            }
+            lists[z + 1] = key;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double signed_val(const double* v, unsigned u) {
+    const double x = v[u >> 1];
+    return (u & 1u) ? -x : x;
+}
+
+// Block partial (unscaled) of S v over sketch rows [r0, r1) for vectors
+// v = v0 .. v0+nvec-1 staged in vals[v * RB + local]; entry (v, row) goes to
+// dst[(v * s + row) * G + blk].  Each list is cut into kSketchParts pieces,
+// each piece summed four entries at a time (independent loads), and the
+// pieces added in a fixed order.  sk_tmp: nvec * (r1 - r0) * kSketchParts
+// doubles.  Starts after the caller's __syncthreads() that published vals;
+// contains one __syncthreads().
+template <int BLOCK>
+__device__ __forceinline__ void sketch_lists_apply(int v0, int nvec, int r0, int r1, const double* vals, int RB,
+                                                   int s, const int* lstart, const uint16_t* lists, double* sk_tmp,
+                                                   double* dst, int G, int blk) {
+    const int tid = threadIdx.x;
+    const int nrow = r1 - r0;
+    const int tasks = nvec * nrow * kSketchParts;
+    for (int t = tid; t < tasks; t += BLOCK) {
+        const int part = t % kSketchParts;
+        const int e = t / kSketchParts;
+        const int v = e / nrow;
+        const int row = r0 + (e - v * nrow);
+        const int q0 = lstart[row];
+        const int len = lstart[row + 1] - q0;
+        const int a0 = q0 + (len * part) / kSketchParts;
+        const int a1 = q0 + (len * (part + 1)) / kSketchParts;
+        const double* vv = vals + (v0 + v) * RB;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        int q = a0;
+        for (; q + 4 <= a1; q += 4) {
+            const unsigned u0 = lists[q], u1 = lists[q + 1], u2 = lists[q + 2], u3 = lists[q + 3];
+            acc0 += signed_val(vv, u0);
+            acc1 += signed_val(vv, u1);
+            acc2 += signed_val(vv, u2);
+            acc3 += signed_val(vv, u3);
+        }
+        for (; q < a1; ++q) acc0 += signed_val(vv, lists[q]);
+        sk_tmp[t] = (acc0 + acc1) + (acc2 + acc3);
+    }
+    __syncthreads();
+    for (int e = tid; e < nvec * nrow; e += BLOCK) {
+        double a = 0.0;
+#pragma unroll
+        for (int part = 0; part < kSketchParts; ++part) a += sk_tmp[e * kSketchParts + part];
+        const int v = e / nrow;
+        const int row = r0 + (e - v * nrow);
+        dst[static_cast<int64_t>((v0 + v) * s + row) * G + blk] = a;
+    }
+}
+
 // Blocks of a launch are dealt round-robin to the 8 XCDs; give each XCD a
 // contiguous range of logical blocks so that neighbouring rows share an L2.
 __device__ __forceinline__ int xcd_logical_block(int phys, int G) {

@@ -45,6 +45,7 @@ struct ArnoldiShape {
     int rows_per_thread;  // 0 = auto
     int force_global_window;
     int per_block_release;
+    int sketch_basis;  // nonzero: the instance that also forms S b_j
 };
 
 struct ArnoldiLaunch {
@@ -63,6 +64,44 @@ size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta);
 hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
 hipError_t arnoldi_launch(const ArnoldiLaunch& L, ArnoldiParams params, hipStream_t stream);
 size_t sync_words_bytes();
+// instance of the basis kernel that also forms S b_j (arnoldi_sb.hip)
+const void* arnoldi_pick_sb(int block, int R, int KW);
+
+// ---- Chebyshev basis kernel (chebyshev.hip) --------------------------------
+struct ChebParams {
+    int64_t n;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+    const double* r;     // cycle residual, n
+    const double* beta;  // device scalar |r|
+    double* B;           // n x d raw recurrence vectors, leading dim ldb
+    int64_t ldb;
+    double* SB;       // s x d, sketches of the normalised columns (when sketch_basis)
+    double* SAB;      // s x d, S A of the normalised columns
+    double* colnorm;  // d, |B[:, j]|
+    double* g;        // s
+    int d, s, zeta;
+    uint64_t seed;
+    uint32_t cycle;
+    double c;   // centre of the spectral box
+    double a1;  // B[:,1] = a1 (A - c) B[:,0]
+    double a;   // B[:,j+1] = a (A - c) B[:,j] - q B[:,j-1]
+    double q;
+    double* part_sk;   // (2s x G) per step for d steps, then s x G for g
+    double* part_nrm;  // d x G
+    void* sync;        // SyncWords, zero at launch
+    int per_block_release;
+    int* abort;
+    int* status;  // [0] columns built
+    uint64_t spin_limit;
+    unsigned long long* phase_ticks;
+    int sketch_basis;
+};
+
+size_t chebyshev_lds_bytes(int block, int R, int s, int zeta);
+hipError_t chebyshev_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
+hipError_t chebyshev_launch(const ArnoldiLaunch& L, ChebParams params, hipStream_t stream);
 
 // ---- vector kernels (vec.hip) ----------------------------------------------
 constexpr int kVecBlock = 256;
@@ -85,9 +124,10 @@ hipError_t launch_csr_outer(int64_t n, const int32_t* rp, const int32_t* ci, con
 // x[i] = v  for i < n
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t stream);
 hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t stream);
-// x += B[:, :*d_eff] y
+// x += B[:, :*d_eff] y, or x += B[:, :*d_eff] (y ./ colnorm) when colnorm is
+// given (columns with colnorm 0 are skipped)
 hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const double* B, int64_t ldb,
-                          const double* y, double* x, hipStream_t stream);
+                          const double* y, double* x, hipStream_t stream, const double* colnorm = nullptr);
 
 // ---- sketch kernels (sketch.hip) -------------------------------------------
 hipError_t launch_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s,

@@ -69,10 +69,12 @@ constexpr int kCombineBlock = 256;
 __global__ __launch_bounds__(kCombineBlock) void combine_kernel(int64_t n, const int* __restrict__ d_eff_p,
                                                                 const double* __restrict__ B, int64_t ldb,
                                                                 const double* __restrict__ y,
-                                                                double* __restrict__ x) {
+                                                                double* __restrict__ x,
+                                                                const double* __restrict__ cn) {
     extern __shared__ double ys[];
     const int d_eff = *d_eff_p;
-    for (int c = threadIdx.x; c < d_eff; c += kCombineBlock) ys[c] = y[c];
+    for (int c = threadIdx.x; c < d_eff; c += kCombineBlock)
+        ys[c] = cn ? (cn[c] > 0.0 ? y[c] / cn[c] : 0.0) : y[c];
     __syncthreads();
     if (d_eff <= 0) return;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kCombineBlock;
@@ -165,12 +167,12 @@ hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t strea
 }
 
 hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const double* B, int64_t ldb,
-                          const double* y, double* x, hipStream_t stream) {
+                          const double* y, double* x, hipStream_t stream, const double* colnorm) {
     int64_t g = (n + kCombineBlock - 1) / kCombineBlock;
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
     combine_kernel<<<static_cast<int>(g), kCombineBlock, sizeof(double) * (d_max > 0 ? d_max : 1), stream>>>(
-        n, d_eff, B, ldb, y, x);
+        n, d_eff, B, ldb, y, x, colnorm);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ OK = 0
 NOT_CONVERGED = 1
 FLAG_KAPPA_TRUNC = 1
 FLAG_BREAKDOWN = 2
+BASIS_ARNOLDI = 0
+BASIS_CHEBYSHEV = 1
 ERRORS = {
     -1: "SGMRES_EINVAL (bad argument)",
     -2: "SGMRES_ECSR (malformed CSR)",
@@ -74,6 +76,10 @@ class _Options(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("barrier_mode", ctypes.c_int32),
         ("spmv_mode", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
+        ("cheb_c", ctypes.c_double),
+        ("cheb_dx", ctypes.c_double),
+        ("cheb_dy", ctypes.c_double),
     ]
 
 
@@ -99,6 +105,8 @@ def lib():
     L.sgmres_residual.argtypes = [P(_CSR), vp, vp, vp, P(dbl), vp]
     L.sgmres_arnoldi_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, i32, u64, u32, vp, i64, vp, vp, vp, vp,
                                        P(i32), P(i32), vp]
+    L.sgmres_chebyshev_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, u64, u32, dbl, dbl, dbl, vp, i64, vp, vp,
+                                         vp, vp, vp]
     L.sgmres_sketched_lsq.argtypes = [i32, i32, vp, vp, dbl, vp, P(i32), P(dbl), P(dbl), P(i32), vp]
     L.sgmres_basis_combine.argtypes = [i64, i32, vp, i64, vp, vp, vp]
     L.sgmres_csr_transpose.argtypes = [P(_CSR), vp, vp, vp, vp]
@@ -185,16 +193,19 @@ def _raise(fn, rc):
 
 def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
                  transposed=False, block_size=0, rows_per_thread=0, profile=False, barrier_mode=0,
-                 spmv_mode=0, stream=None):
+                 spmv_mode=0, cheb_box=None, stream=None):
     """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
 
-    Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED (1);
-    raises SGMRESError on the negative error codes."""
+    cheb_box=(c, dx, dy) selects the Chebyshev basis for a spectrum inside
+    [c - dx, c + dx] x [-dy, dy] (k is then unused); None selects k-truncated
+    Arnoldi.  Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED
+    (1); raises SGMRESError on the negative error codes."""
     _check_dev(b, torch.float64, A.n)
     _check_dev(x, torch.float64, A.n)
     info = _Info()
+    basis, (cc, cdx, cdy) = (0, (0.0, 0.0, 0.0)) if cheb_box is None else (1, tuple(float(t) for t in cheb_box))
     opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
-                    barrier_mode, spmv_mode)
+                    barrier_mode, spmv_mode, basis, cc, cdx, cdy)
     rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
                                ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     return _raise("sgmres_solve", rc), _info(info)
@@ -258,6 +269,24 @@ def sgmres_arnoldi_cycle(A: DeviceCSR, r, d, k, s, zeta=8, seed=0, cycle=0, stre
                                     ctypes.byref(dc), ctypes.byref(flags), _stream(stream))
     _raise("sgmres_arnoldi_cycle", rc)
     return dict(B=B.T, SB=SB.T, SAB=SAB.T, H=H.T, g=g, dc=dc.value, flags=flags.value)
+
+
+def sgmres_chebyshev_cycle(A: DeviceCSR, r, d, s, c, dx, dy, zeta=8, seed=0, cycle=0, stream=None):
+    """One Chebyshev-basis + sketch cycle; returns dict of GPU tensors: B (n x d,
+    unnormalised recurrence vectors), colnorm (d), SB, SAB (s x d, of the
+    normalised columns) and g."""
+    _check_dev(r, torch.float64, A.n)
+    dev = r.device
+    B = torch.empty((d, A.n), dtype=torch.float64, device=dev)
+    SB = torch.zeros((d, s), dtype=torch.float64, device=dev)
+    SAB = torch.zeros((d, s), dtype=torch.float64, device=dev)
+    cn = torch.empty(d, dtype=torch.float64, device=dev)
+    g = torch.empty(s, dtype=torch.float64, device=dev)
+    rc = lib().sgmres_chebyshev_cycle(ctypes.byref(A._c()), r.data_ptr(), d, s, zeta, seed, cycle, c, dx, dy,
+                                      B.data_ptr(), A.n, SB.data_ptr(), SAB.data_ptr(), cn.data_ptr(), g.data_ptr(),
+                                      _stream(stream))
+    _raise("sgmres_chebyshev_cycle", rc)
+    return dict(B=B.T, colnorm=cn, SB=SB.T, SAB=SAB.T, g=g)
 
 
 def sgmres_sketched_lsq(SAB, g, kappa_max=1e14, stream=None):
