@@ -31,17 +31,22 @@ METRIC = "sGMRES solves/s at rel. residual 1e-10 (n=1M, d=200); HBM GB/s vs peak
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 # Basis-kernel HBM traffic per launch on the cd1024 workload, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE scaled by the copy calibration (summary and commands
-# in profiles/arnoldi_kernel_cd1024_hbm_counters.md).  Valid only for the kernel
+# FETCH_SIZE / WRITE_SIZE scaled by the copy calibration (summaries and commands
+# in profiles/<kernel>_cd1024_hbm_counters.md).  Valid only for the kernel
 # source it was measured on; any change to it makes the figure stale (null).
-MEASURED_TRAFFIC = {"source_hash": "ecfc91c59e07f6ae", "bytes_per_launch": 19.1192e9}
+MEASURED_TRAFFIC = {
+    "arnoldi": {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "9fe1edae4d572753",
+                "bytes_per_launch": 18.7306e9},
+    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "be78029846cdd4ee",
+                  "bytes_per_launch": 17.2580e9},
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(basis: str) -> str:
     import hashlib
 
     m = hashlib.sha256()
-    for f in ("arnoldi_kernel.hpp", "common.hpp"):
+    for f in MEASURED_TRAFFIC[basis]["files"]:
         with open(os.path.join(ROOT, "paper_2111_00113_amd", "csrc", f), "rb") as fh:
             m.update(fh.read())
     return m.hexdigest()[:16]
@@ -162,7 +167,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--workload", default="cd1024")
-    ap.add_argument("--cpu-sample-cols", type=int, default=40)
+    ap.add_argument("--cpu-sample-cols", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
@@ -281,9 +286,9 @@ def main() -> int:
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
-                        if kernel_source_hash() == MEASURED_TRAFFIC["source_hash"] and args.workload == "cd1024"
-                        and not cheb else None),
+            "traffic": (MEASURED_TRAFFIC[args.basis]["bytes_per_launch"]
+                        if kernel_source_hash(args.basis) == MEASURED_TRAFFIC[args.basis]["source_hash"]
+                        and args.workload == "cd1024" else None),
             "traffic_unit": "bytes per launch",
             "kernel": "chebyshev_kernel" if cheb else "arnoldi_kernel (spmv_truncarnoldi)",
             "bytes_per_launch": launch_bytes,
