@@ -56,19 +56,27 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def basis_launch_bytes(n: int, nnz: int, k: int, dc: float) -> float:
+# bytes of one value of A and of one stored basis entry per precision mode
+VAL_BYTES = {"fp64": 8.0, "fp32": 4.0, "bf16": 4.0}
+BASIS_BYTES = {"fp64": 8.0, "fp32": 4.0, "bf16": 2.0}
+
+
+def basis_launch_bytes(n: int, nnz: int, k: int, dc: float, prec: str = "fp64") -> float:
     """Algorithmic HBM bytes of one basis-kernel launch (dc Arnoldi steps).
 
-    Per step: the CSR arrays (12 B per nonzero + 4 B per row), the k window
-    columns read and b_{j+1} written: 12 nnz + 4n + 8n(k+1)."""
-    return dc * (12.0 * nnz + 4.0 * n + 8.0 * n * (k + 1))
+    Per step: the CSR arrays (4 B index + the value per nonzero, 4 B per row),
+    the k window columns read and b_{j+1} written: in FP64
+    12 nnz + 4n + 8n(k+1); values and basis entries shrink with the precision."""
+    vb, eb = VAL_BYTES[prec], BASIS_BYTES[prec]
+    return dc * ((4.0 + vb) * nnz + 4.0 * n + eb * n * (k + 1))
 
 
-def compulsory_launch_bytes(n: int, nnz: int, dc: float) -> float:
+def compulsory_launch_bytes(n: int, nnz: int, dc: float, prec: str = "fp64") -> float:
     """Bytes this kernel must move per launch: it keeps the window and the row
     pointers on chip, so per step only the CSR column indices and values, the
     gathered b_j and the written b_{j+1}; plus r read and b_1 written once."""
-    return dc * (12.0 * nnz + 8.0 * n) + 8.0 * n * (dc - 1) + 16.0 * n + 4.0 * (n + 1)
+    vb, eb = VAL_BYTES[prec], BASIS_BYTES[prec]
+    return dc * ((4.0 + vb) * nnz + eb * n) + eb * n * (dc - 1) + (8.0 + eb) * n + 4.0 * (n + 1)
 
 
 def cpu_baseline(A, f, p, cycles_per_solve: float, sample_cols: int) -> dict:
@@ -152,13 +160,14 @@ def grad_bench(args, A, f, p, sg, torch, np) -> int:
     return 0
 
 
-def cheb_launch_bytes(n: int, nnz: int, dc: float) -> float:
+def cheb_launch_bytes(n: int, nnz: int, dc: float, prec: str = "fp64") -> float:
     """Algorithmic HBM bytes of one Chebyshev basis-kernel launch (dc steps).
 
-    Per step: the CSR arrays (12 B per nonzero + 4 B per row), b_j gathered and
-    b_{j+1} written (the two previous vectors stay in registers):
-    12 nnz + 4n + 16n."""
-    return dc * (12.0 * nnz + 4.0 * n + 16.0 * n)
+    Per step: the CSR arrays (4 B index + the value per nonzero, 4 B per row),
+    b_j gathered and b_{j+1} written (the two previous vectors stay in
+    registers): in FP64 12 nnz + 4n + 16n."""
+    vb, eb = VAL_BYTES[prec], BASIS_BYTES[prec]
+    return dc * ((4.0 + vb) * nnz + 4.0 * n + 2.0 * eb * n)
 
 
 def main() -> int:
@@ -175,6 +184,8 @@ def main() -> int:
     ap.add_argument("--basis", default="arnoldi", choices=["arnoldi", "chebyshev"],
                     help="arnoldi: k-truncated Arnoldi (the method's default); chebyshev: Section 4.4 recurrence")
     ap.add_argument("--cheb-box", default="4,4,0", help="c,dx,dy of the spectral box for --basis chebyshev")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="basis cycles in FP64, FP32, or FP32 with a bfloat16 basis (FP64 refinement)")
     ap.add_argument("--mode", default="solve", choices=["solve", "grad"],
                     help="solve: the sGMRES metric; grad: differentiable solve (forward + adjoint)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -220,7 +231,8 @@ def main() -> int:
         x.zero_()
         rc, info = sg.sgmres_solve(dA, fb, x, d, k, s, p["seed"], p["tol"], p["restarts"], zeta=p["zeta"],
                                    profile=profile, block_size=args.block_size,
-                                   rows_per_thread=args.rows_per_thread, spmv_mode=args.spmv_mode, cheb_box=box)
+                                   rows_per_thread=args.rows_per_thread, spmv_mode=args.spmv_mode, cheb_box=box,
+                                   precision=args.precision)
         if rc != sg.OK:
             raise RuntimeError(f"solve did not converge: {info}")
         return info
@@ -248,7 +260,9 @@ def main() -> int:
     t_res = sum(i["t_residual_ms"] for i in infos)
     dc_avg = steps / cycles
     launch_ms = t_basis / cycles
-    launch_bytes = cheb_launch_bytes(A.n, A.nnz, dc_avg) if cheb else basis_launch_bytes(A.n, A.nnz, k, dc_avg)
+    pr = args.precision
+    launch_bytes = (cheb_launch_bytes(A.n, A.nnz, dc_avg, pr) if cheb
+                    else basis_launch_bytes(A.n, A.nnz, k, dc_avg, pr))
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     # x after the last timed solve: confirm the residual with an independent host SpMV
     xr = x.cpu().numpy()
@@ -265,13 +279,19 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32 basis cycles, f64 refinement",
+                  "bf16": "f32 arithmetic, bf16 basis, f64 refinement"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": (f"{args.workload}: 2D convection-diffusion 5-point, n={A.n}, nnz={A.nnz}, "
+            "workload": (f"{args.workload}: "
+                         + ("random sparse nonsymmetric, 7 nonzeros per row, diagonal dominance 1.2"
+                            if args.workload.startswith("rd") else "2D convection-diffusion 5-point")
+                         + f", n={A.n}, nnz={A.nnz}, "
                          f"d={d}, k={k}, s={s}, zeta={p['zeta']}, tol={p['tol']:g}, b~N(0,1) seed 0, x0=0"
-                         + (f", Chebyshev basis box c,dx,dy={args.cheb_box}" if cheb else "")),
+                         + (f", Chebyshev basis box c,dx,dy={args.cheb_box}" if cheb else "")
+                         + (f", {args.precision} basis cycles" if args.precision != "fp64" else "")),
             "basis": args.basis,
+            "precision": args.precision,
             "n": A.n,
             "nnz": A.nnz,
             "d": d,
@@ -288,11 +308,11 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": (MEASURED_TRAFFIC[args.basis]["bytes_per_launch"]
                         if kernel_source_hash(args.basis) == MEASURED_TRAFFIC[args.basis]["source_hash"]
-                        and args.workload == "cd1024" else None),
+                        and args.workload == "cd1024" and args.precision == "fp64" else None),
             "traffic_unit": "bytes per launch",
             "kernel": "chebyshev_kernel" if cheb else "arnoldi_kernel (spmv_truncarnoldi)",
             "bytes_per_launch": launch_bytes,
-            "compulsory_bytes_per_launch": compulsory_launch_bytes(A.n, A.nnz, dc_avg),
+            "compulsory_bytes_per_launch": compulsory_launch_bytes(A.n, A.nnz, dc_avg, pr),
             "avg_launch_ms": launch_ms,
         },
         "cycles_per_solve": cycles / args.steps,
@@ -307,7 +327,7 @@ def main() -> int:
             "residual": t_res / args.steps,
         },
     }
-    if not args.no_cpu_baseline and not cheb:
+    if not args.no_cpu_baseline and not cheb and args.precision == "fp64":
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(A, f, p, cycles / args.steps, args.cpu_sample_cols)
     print(json.dumps(out), flush=True)

@@ -53,6 +53,15 @@ extern "C" {
 #define SGMRES_BASIS_ARNOLDI 0   /* k-truncated Arnoldi (Algorithm 1) */
 #define SGMRES_BASIS_CHEBYSHEV 1 /* shifted-and-scaled Chebyshev recurrence (Section 4.4) */
 
+/* Precision of the basis cycles (the residual b - A x, the sums of partial
+ * results, the sketched least squares and x stay FP64 in every mode; restarting
+ * from the FP64 residual is the iterative refinement that wins the accuracy
+ * back). */
+#define SGMRES_PREC_FP64 0       /* everything FP64 */
+#define SGMRES_PREC_FP32 1       /* SpMV (on an FP32 copy of A's values), basis and
+                                    sketch inputs in FP32, basis stored in FP32 */
+#define SGMRES_PREC_BF16_BASIS 2 /* as FP32, with the basis stored in bfloat16 */
+
 /* Square sparse matrix in CSR form; all arrays on the device. */
 typedef struct {
     int64_t n;              /* order, 1 <= n < 2^31 */
@@ -105,6 +114,7 @@ typedef struct {
     double cheb_c;      /* Chebyshev basis: the spectrum of A lies in the box */
     double cheb_dx;     /* [cheb_c - cheb_dx, cheb_c + cheb_dx] x [-cheb_dy, cheb_dy] */
     double cheb_dy;     /* (Section 4.4); dx, dy >= 0, max(dx, dy) > 0; k is unused */
+    int32_t precision;  /* SGMRES_PREC_* (0 = FP64) */
 } sgmres_options_t;
 
 /*

@@ -15,6 +15,9 @@ from .sgmres import (  # noqa: F401
     FLAG_KAPPA_TRUNC,
     BASIS_ARNOLDI,
     BASIS_CHEBYSHEV,
+    PREC_FP64,
+    PREC_FP32,
+    PREC_BF16_BASIS,
     LIB_PATH,
     lib,
     sgmres_solve,

@@ -10,9 +10,14 @@ namespace {
 
 using KernelFn = void (*)(ArnoldiParams);
 
-KernelFn pick_kernel(int block, int R, int KW, bool sketch_basis) {
-    if (sketch_basis) return reinterpret_cast<KernelFn>(const_cast<void*>(arnoldi_pick_sb(block, R, KW)));
-    return reinterpret_cast<KernelFn>(const_cast<void*>(arnoldi_pick<false>(block, R, KW)));
+// FP64 solve instances live here; the others in their own translation units
+KernelFn pick_kernel(int block, int R, int KW, bool sketch_basis, int precision) {
+    const void* f = nullptr;
+    if (precision == SGMRES_PREC_FP32) f = sketch_basis ? nullptr : arnoldi_pick_f32(block, R, KW);
+    else if (precision == SGMRES_PREC_BF16_BASIS) f = sketch_basis ? nullptr : arnoldi_pick_bf16(block, R, KW);
+    else if (precision == SGMRES_PREC_FP64)
+        f = sketch_basis ? arnoldi_pick_sb(block, R, KW) : arnoldi_pick<false, double, double>(block, R, KW);
+    return reinterpret_cast<KernelFn>(const_cast<void*>(f));
 }
 
 }  // namespace
@@ -54,7 +59,7 @@ hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {
                 if (shape.force_global_window) KW = 0;
                 const size_t lds = arnoldi_lds_bytes(block, R, shape.s, shape.k, shape.zeta);
                 if (lds > static_cast<size_t>(lds_max)) continue;
-                KernelFn fn = pick_kernel(block, R, KW, shape.sketch_basis != 0);
+                KernelFn fn = pick_kernel(block, R, KW, shape.sketch_basis != 0, shape.precision);
                 if (!fn) continue;
                 err = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));

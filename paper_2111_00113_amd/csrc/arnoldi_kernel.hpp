@@ -41,8 +41,10 @@ namespace arnoldi_detail {
 constexpr int kChunk = 8;     // reduction values per block_sum pass (global window)
 constexpr int kRedSlots = 9;  // max values per block_sum: window of 8 plus a norm
 
-// SKB: also form S b_j (SB); the solve needs only S m_j.
-template <int R, int KW, int BLOCK, bool SKB>
+// SKB: also form S b_j (SB); the solve needs only S m_j.  TC: per-row
+// arithmetic type (A's values are read in TC); TS: storage type of B.  Sums of
+// block partials, H and the sketch sums are FP64 in every variant.
+template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS>
 __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
@@ -70,6 +72,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     const int64_t base = static_cast<int64_t>(blk) * RB + tid;
     const double scale = 1.0 / sqrt(static_cast<double>(zeta));
     const int64_t slab = static_cast<int64_t>(2 * s) * G;  // sketch partials of one step
+    const TC* Av = static_cast<const TC*>(p.val);
+    TS* Bs = static_cast<TS*>(p.B);
+    constexpr double uround = BasisPrec<TC>::unit_roundoff;
 
     GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
@@ -114,20 +119,20 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 
     // ---- init: g partial (S r), b_1 = r/|r| ----------------------------------
     const double beta = *p.beta;
-    double win[KW > 0 ? KW : 1][R];
+    TC win[KW > 0 ? KW : 1][R];
 #pragma unroll
     for (int a = 0; a < (KW > 0 ? KW : 1); ++a)
 #pragma unroll
-        for (int r = 0; r < R; ++r) win[a][r] = 0.0;
+        for (int r = 0; r < R; ++r) win[a][r] = TC(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
         double rv = 0.0;
         if (row < n) {
             rv = p.r[row];
-            const double b1 = rv / beta;
-            p.B[row] = b1;
-            win[0][r] = b1;
+            const TS b1 = to_basis<TS>(static_cast<TC>(rv / beta));
+            Bs[row] = b1;
+            win[0][r] = from_basis<TC>(b1);
         }
         vals[r * BLOCK + tid] = rv;
     }
@@ -137,26 +142,26 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     bar.sync();  // B[:,0] and the g partials are complete
 
     // window entry a (0 = newest) of own row r at step j
-    auto Wg = [&](int j, int a, int r) -> double {
+    auto Wg = [&](int j, int a, int r) -> TC {
         const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-        return row < n ? p.B[static_cast<int64_t>(j - a) * p.ldb + row] : 0.0;
+        return row < n ? from_basis<TC>(Bs[static_cast<int64_t>(j - a) * p.ldb + row]) : TC(0);
     };
 
     // partial sums of <x,x> and W^T x over own rows -> part[q*G + blk]
     // slot q = 0: <x,x>; slot q = 1 + a: <W_a, x>
-    auto dots_to_partials = [&](const double (&x)[R], int j, int kw, double* part) {
+    auto dots_to_partials = [&](const TC (&x)[R], int j, int kw, double* part) {
         if constexpr (KW > 0) {
             double v[KW + 1];
-            double t = 0.0;
+            TC t = TC(0);
 #pragma unroll
             for (int r = 0; r < R; ++r) t += x[r] * x[r];
-            v[0] = t;
+            v[0] = static_cast<double>(t);
 #pragma unroll
             for (int a = 0; a < KW; ++a) {
-                double u = 0.0;
+                TC u = TC(0);
 #pragma unroll
                 for (int r = 0; r < R; ++r) u += win[a][r] * x[r];
-                v[a + 1] = u;
+                v[a + 1] = static_cast<double>(u);
             }
             block_sum<KW + 1>(v, kw + 1, red_tmp, red_out);
             if (tid <= kw) part[static_cast<int64_t>(tid) * G + blk] = red_out[tid];
@@ -166,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
                 for (int c = 0; c < kChunk; ++c) {
                     const int q = q0 + c;
-                    double u = 0.0;
+                    TC u = TC(0);
                     if (q == 0) {
 #pragma unroll
                         for (int r = 0; r < R; ++r) u += x[r] * x[r];
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
                         for (int r = 0; r < R; ++r) u += Wg(j, q - 1, r) * x[r];
                     }
-                    v[c] = u;
+                    v[c] = static_cast<double>(u);
                 }
                 const int cnt = min(kChunk, kw + 1 - q0);
                 block_sum<kChunk>(v, cnt, red_tmp, red_out);
@@ -197,11 +202,11 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     int dc = p.d;
     int flags = 0;
     for (int j = 0; j < p.d; ++j) {
-        const double* bj = p.B + static_cast<int64_t>(j) * p.ldb;
+        const TS* bj = Bs + static_cast<int64_t>(j) * p.ldb;
         const int kw = min(j + 1, p.k);
 
         // ---- phase 1: m = A b_j and partial dots ---------------------------
-        double m[R];
+        TC m[R];
         if (p.spmv_mode == 1) {
             // CSR-stream: the chunk's products val[q] * b_j[col[q]] go to LDS with
             // coalesced loads, then each thread sums its row in nonzero order.
@@ -209,15 +214,17 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int q0 = cq[r], q1 = cq[r + 1];
-                double am = 0.0;
+                TC am = TC(0);
                 if (q1 - q0 <= 2 * RB) {
 #pragma unroll 4
-                    for (int q = q0 + tid; q < q1; q += BLOCK) prod[q - q0] = p.val[q] * bj[p.ci[q]];
+                    for (int q = q0 + tid; q < q1; q += BLOCK)
+                        prod[q - q0] = static_cast<double>(Av[q] * from_basis<TC>(bj[p.ci[q]]));
                     __syncthreads();
-                    for (int q = 0; q < rlen[r]; ++q) am += prod[rbeg[r] - q0 + q];
+                    for (int q = 0; q < rlen[r]; ++q) am += static_cast<TC>(prod[rbeg[r] - q0 + q]);
                     __syncthreads();
                 } else {
-                    for (int q = 0; q < rlen[r]; ++q) am += p.val[rbeg[r] + q] * bj[p.ci[rbeg[r] + q]];
+                    for (int q = 0; q < rlen[r]; ++q)
+                        am += Av[rbeg[r] + q] * from_basis<TC>(bj[p.ci[rbeg[r] + q]]);
                 }
                 m[r] = am;
             }
@@ -225,8 +232,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             // one row per thread, nonzeros in order
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                double am = 0.0;
-                for (int q = 0; q < rlen[r]; ++q) am += p.val[rbeg[r] + q] * bj[p.ci[rbeg[r] + q]];
+                TC am = TC(0);
+                for (int q = 0; q < rlen[r]; ++q) am += Av[rbeg[r] + q] * from_basis<TC>(bj[p.ci[rbeg[r] + q]]);
                 m[r] = am;
             }
         }
@@ -238,12 +245,12 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (SKB) {
-                double bv;
+                TC bv;
                 if constexpr (KW > 0) bv = win[0][r];
                 else bv = Wg(j, 0, r);
-                vals[r * BLOCK + tid] = bv;
+                vals[r * BLOCK + tid] = static_cast<double>(bv);
             }
-            vals[RB + r * BLOCK + tid] = m[r];
+            vals[RB + r * BLOCK + tid] = static_cast<double>(m[r]);
         }
         __syncthreads();
         block_sketch(0, sk_cut1, sk_dst);
@@ -257,21 +264,21 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             block_sketch(sk_cut1, s, sk_dst);
             break;
         }
-        double w[R];
+        TC w[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) w[r] = m[r];
         if constexpr (KW > 0) {
 #pragma unroll
             for (int a = 0; a < KW; ++a) {
                 if (a < kw) {
-                    const double h = coef[1 + a];
+                    const TC h = static_cast<TC>(coef[1 + a]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) w[r] -= h * win[a][r];
                 }
             }
         } else {
             for (int a = 0; a < kw; ++a) {
-                const double h = coef[1 + a];
+                const TC h = static_cast<TC>(coef[1 + a]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) w[r] -= h * Wg(j, a, r);
             }
@@ -290,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         for (int a = 0; a < kw; ++a) h2sq += c2[1 + a] * c2[1 + a];
         const double nu2 = c2[0] - h2sq;
         const double mm = coef[0];
-        const bool breakdown = !(nu2 > 16.0 * kUnitRoundoff * kUnitRoundoff * mm);
+        const bool breakdown = !(nu2 > 16.0 * uround * uround * mm);
         const double nu = breakdown ? 0.0 : sqrt(nu2);
         if (blk == 0 && tid <= p.k) {
             double hv;
@@ -305,31 +312,33 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             flags |= SGMRES_FLAG_BREAKDOWN;
             break;
         }
-        double* bn = p.B + static_cast<int64_t>(j + 1) * p.ldb;
-        double bnew[R];
+        TS* bn = Bs + static_cast<int64_t>(j + 1) * p.ldb;
+        TC bnew[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) bnew[r] = w[r];
         if constexpr (KW > 0) {
 #pragma unroll
             for (int a = 0; a < KW; ++a) {
                 if (a < kw) {
-                    const double h = c2[1 + a];
+                    const TC h = static_cast<TC>(c2[1 + a]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) bnew[r] -= h * win[a][r];
                 }
             }
         } else {
             for (int a = 0; a < kw; ++a) {
-                const double h = c2[1 + a];
+                const TC h = static_cast<TC>(c2[1 + a]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) bnew[r] -= h * Wg(j, a, r);
             }
         }
+        const TC nu_t = static_cast<TC>(nu);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-            bnew[r] = bnew[r] / nu;
-            if (row < n) bn[row] = bnew[r];
+            const TS st = to_basis<TS>(bnew[r] / nu_t);
+            if (row < n) bn[row] = st;
+            bnew[r] = from_basis<TC>(st);
         }
         if constexpr (KW > 0) {
 #pragma unroll
@@ -382,10 +391,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 
 // Kernel instance for (BLOCK, R, KW); (R, KW) = (8, 8) is never selected
 // (the register window is capped at 32 doubles per thread).
-template <bool SKB, int BLOCK>
+template <bool SKB, typename TC, typename TS, int BLOCK>
 const void* pick_rows(int R, int KW) {
 #define SG_CASE(RR, KK) \
-    if (R == RR && KW == KK) return reinterpret_cast<const void*>(arnoldi_kernel<RR, KK, BLOCK, SKB>);
+    if (R == RR && KW == KK) return reinterpret_cast<const void*>(arnoldi_kernel<RR, KK, BLOCK, SKB, TC, TS>);
     SG_CASE(1, 0) SG_CASE(1, 4) SG_CASE(1, 8)
     SG_CASE(2, 0) SG_CASE(2, 4) SG_CASE(2, 8)
     SG_CASE(4, 0) SG_CASE(4, 4) SG_CASE(4, 8)
@@ -394,12 +403,12 @@ const void* pick_rows(int R, int KW) {
     return nullptr;
 }
 
-template <bool SKB>
+template <bool SKB, typename TC, typename TS>
 const void* arnoldi_pick(int block, int R, int KW) {
     switch (block) {
-        case 256: return pick_rows<SKB, 256>(R, KW);
-        case 512: return pick_rows<SKB, 512>(R, KW);
-        case 1024: return pick_rows<SKB, 1024>(R, KW);
+        case 256: return pick_rows<SKB, TC, TS, 256>(R, KW);
+        case 512: return pick_rows<SKB, TC, TS, 512>(R, KW);
+        case 1024: return pick_rows<SKB, TC, TS, 1024>(R, KW);
         default: return nullptr;
     }
 }

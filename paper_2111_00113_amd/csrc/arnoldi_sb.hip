@@ -4,6 +4,8 @@
 
 namespace sg {
 
-const void* arnoldi_pick_sb(int block, int R, int KW) { return arnoldi_detail::arnoldi_pick<true>(block, R, KW); }
+const void* arnoldi_pick_sb(int block, int R, int KW) {
+    return arnoldi_detail::arnoldi_pick<true, double, double>(block, R, KW);
+}
 
 }  // namespace sg

@@ -74,6 +74,8 @@ struct Workspace {
     size_t part_nrm_cap = 0;
     double* colnorm = nullptr;  // Chebyshev column norms, d
     size_t colnorm_cap = 0;
+    float* valf = nullptr;  // FP32 copy of A's values (mixed-precision cycles)
+    size_t valf_cap = 0;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
@@ -164,6 +166,7 @@ struct SolveArgs {
     int spmv_mode;
     int basis;  // SGMRES_BASIS_*
     double cheb_c, cheb_dx, cheb_dy;
+    int precision;  // SGMRES_PREC_*
     hipStream_t stream;
 };
 
@@ -220,17 +223,19 @@ int copy_scalars(Workspace& ws, hipStream_t stream) {
 }
 
 // One basis cycle on the residual in ws.r (norm already in ws.sc->beta).
+// B is stored in the launch's basis type; val (null = A.val) in its arithmetic type.
 int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zeta, uint64_t seed,
-              uint32_t cycle, const ArnoldiLaunch& L, double* B, int64_t ldb, double* SB, double* SAB,
+              uint32_t cycle, const ArnoldiLaunch& L, void* B, int64_t ldb, double* SB, double* SAB,
               double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
-              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0) {
+              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0,
+              const void* val = nullptr) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ArnoldiParams p{};
     p.n = A.n;
     p.rp = A.row_ptr;
     p.ci = A.col_idx;
-    p.val = A.val;
+    p.val = val ? val : A.val;
     p.r = ws.r;
     p.beta = &ws.sc->beta;
     p.B = B;
@@ -261,16 +266,17 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
 
 // One Chebyshev basis cycle on the residual in ws.r (norm in ws.sc->beta).
 int run_cheb_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int s, int zeta, uint64_t seed, uint32_t cycle,
-                   const ArnoldiLaunch& L, const ChebCoef& cf, double* B, int64_t ldb, double* SB, double* SAB,
+                   const ArnoldiLaunch& L, const ChebCoef& cf, void* B, int64_t ldb, double* SB, double* SAB,
                    double* colnorm, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
-                   int per_block_release = 0, bool phase_timing = false, int sketch_basis = 1) {
+                   int per_block_release = 0, bool phase_timing = false, int sketch_basis = 1,
+                   const void* val = nullptr) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ChebParams p{};
     p.n = A.n;
     p.rp = A.row_ptr;
     p.ci = A.col_idx;
-    p.val = A.val;
+    p.val = val ? val : A.val;
     p.r = ws.r;
     p.beta = &ws.sc->beta;
     p.B = B;
@@ -327,8 +333,8 @@ int check_csr(Workspace& ws, const sgmres_csr_t& A, hipStream_t st) {
 // sketch_basis selects the kernel instance that also forms S B (the cycle
 // entry point); the solve uses S A B and g only.
 int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int block, int rpt,
-                    ArnoldiLaunch* L, int sketch_basis) {
-    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis};
+                    ArnoldiLaunch* L, int sketch_basis, int precision = SGMRES_PREC_FP64) {
+    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis, precision};
     if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
     SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(k + 1) * L->grid));
     SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
@@ -336,8 +342,9 @@ int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int
     return SGMRES_OK;
 }
 
-int prepare_cheb(Workspace& ws, int64_t n, int d, int s, int zeta, int block, int rpt, ArnoldiLaunch* L) {
-    ArnoldiShape shape{n, d, 1, s, zeta, block, rpt, 0, 0, 0};
+int prepare_cheb(Workspace& ws, int64_t n, int d, int s, int zeta, int block, int rpt, ArnoldiLaunch* L,
+                 int precision = SGMRES_PREC_FP64) {
+    ArnoldiShape shape{n, d, 1, s, zeta, block, rpt, 0, 0, 0, precision};
     if (chebyshev_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
     SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
     SG_TRY(ensure(ws.part_nrm, ws.part_nrm_cap, static_cast<size_t>(d) * L->grid));
@@ -355,7 +362,8 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     hipStream_t st = a.stream;
 
     SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
-    SG_TRY(ensure(ws.B, ws.B_cap, static_cast<size_t>(n) * a.d));
+    // B in the basis storage type (allocated in doubles)
+    SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(n) * a.d * basis_elem_bytes(a.precision) + 7) / 8));
     SG_TRY(ensure(ws.SB, ws.SB_cap, static_cast<size_t>(a.s) * a.d));
     SG_TRY(ensure(ws.SAB, ws.SAB_cap, static_cast<size_t>(a.s) * a.d));
     SG_TRY(ensure(ws.H, ws.H_cap, static_cast<size_t>(kk + 1) * a.d));
@@ -367,11 +375,18 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     if (cheb && !cheb_coefficients(a.cheb_c, a.cheb_dx, a.cheb_dy, &cf)) return SGMRES_EINVAL;
     if (cheb) SG_TRY(ensure(ws.colnorm, ws.colnorm_cap, static_cast<size_t>(a.d)));
     ArnoldiLaunch L{};
-    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L)
-              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0);
+    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L, a.precision)
+              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0, a.precision);
     if (rc) return rc;
     rc = check_csr(ws, a.A, st);
     if (rc) return rc;
+    // the basis cycles of the mixed-precision modes read an FP32 copy of A's values
+    const void* cyc_val = a.A.val;
+    if (a.precision != SGMRES_PREC_FP64) {
+        SG_TRY(ensure(ws.valf, ws.valf_cap, static_cast<size_t>(a.A.nnz)));
+        SG_TRY(launch_to_f32(a.A.nnz, a.A.val, ws.valf, st));
+        cyc_val = ws.valf;
+    }
 
     // |b|, and clear the per-solve counters
     SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
@@ -436,17 +451,18 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         if (cheb)
             rc = run_cheb_cycle(ws, a.A, a.d, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, cf, ws.B, n,
                                 ws.SB, ws.SAB, ws.colnorm, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release,
-                                ev.on, 0);
+                                ev.on, 0, cyc_val);
         else
             rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
                            ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
-                           a.spmv_mode);
+                           a.spmv_mode, cyc_val);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
         rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.l1, st));
-        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st, cheb ? ws.colnorm : nullptr));
+        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st, cheb ? ws.colnorm : nullptr,
+                              a.precision));
         if (ev.on) SG_TRY(hipEventRecord(ev.c1, st));
         ++cycles;
     }
@@ -481,6 +497,9 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     a.per_block_release = opts ? opts->barrier_mode : 0;
     a.spmv_mode = opts ? opts->spmv_mode : 0;
     a.basis = opts ? opts->basis : SGMRES_BASIS_ARNOLDI;
+    a.precision = opts ? opts->precision : SGMRES_PREC_FP64;
+    if (a.precision != SGMRES_PREC_FP64 && a.precision != SGMRES_PREC_FP32 && a.precision != SGMRES_PREC_BF16_BASIS)
+        return SGMRES_EINVAL;
     if (a.basis != SGMRES_BASIS_ARNOLDI && a.basis != SGMRES_BASIS_CHEBYSHEV) return SGMRES_EINVAL;
     if (a.basis == SGMRES_BASIS_CHEBYSHEV) {
         ChebCoef cf{};
@@ -727,7 +746,7 @@ void sgmres_release_workspace(void) {
         (void)hipSetDevice(kv.first);
         Workspace& w = kv.second;
         void* ptrs[] = {w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
-                        w.part_vec, w.part_nrm, w.colnorm, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
+                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);

@@ -26,7 +26,8 @@ namespace sg {
 
 namespace {
 
-template <int R, int BLOCK>
+// TC: per-row arithmetic type; TS: storage type of B (see BasisPrec).
+template <int R, int BLOCK, typename TC, typename TS>
 __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
@@ -54,6 +55,9 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     const int64_t base = static_cast<int64_t>(blk) * RB + tid;
     const double scale = 1.0 / sqrt(static_cast<double>(zeta));
     const int64_t slab = static_cast<int64_t>(2 * s) * G;
+    const TC* Av = static_cast<const TC*>(p.val);
+    TS* Bs = static_cast<TS*>(p.B);
+    const TC cc = static_cast<TC>(p.c);
 
     GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
@@ -78,17 +82,18 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
 
     // ---- init: g partial (S r), bt_1 = r/|r| ---------------------------------
     const double beta = *p.beta;
-    double bprev[R], bcur[R];
+    TC bprev[R], bcur[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
         double rv = 0.0;
-        bprev[r] = 0.0;
-        bcur[r] = 0.0;
+        bprev[r] = TC(0);
+        bcur[r] = TC(0);
         if (row < n) {
             rv = p.r[row];
-            bcur[r] = rv / beta;
-            p.B[row] = bcur[r];
+            const TS st = to_basis<TS>(static_cast<TC>(rv / beta));
+            Bs[row] = st;
+            bcur[r] = from_basis<TC>(st);
         }
         vals[r * BLOCK + tid] = rv;
     }
@@ -108,25 +113,26 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     };
 
     for (int j = 0; j < p.d; ++j) {
-        const double* bj = p.B + static_cast<int64_t>(j) * p.ldb;
-        double m[R];
+        const TS* bj = Bs + static_cast<int64_t>(j) * p.ldb;
+        TC m[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            double am = 0.0;
-            for (int q = 0; q < rlen[r]; ++q) am += p.val[rbeg[r] + q] * bj[p.ci[rbeg[r] + q]];
+            TC am = TC(0);
+            for (int q = 0; q < rlen[r]; ++q) am += Av[rbeg[r] + q] * from_basis<TC>(bj[p.ci[rbeg[r] + q]]);
             m[r] = am;
         }
         const bool more = j + 1 < p.d;
-        double bnext[R];
+        TC bnext[R];
         if (more) {
-            const double a = (j == 0) ? p.a1 : p.a;
-            const double q = (j == 0) ? 0.0 : p.q;
-            double* bn = p.B + static_cast<int64_t>(j + 1) * p.ldb;
+            const TC a = static_cast<TC>((j == 0) ? p.a1 : p.a);
+            const TC q = static_cast<TC>((j == 0) ? 0.0 : p.q);
+            TS* bn = Bs + static_cast<int64_t>(j + 1) * p.ldb;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-                bnext[r] = a * (m[r] - p.c * bcur[r]) - q * bprev[r];
-                if (row < n) bn[row] = bnext[r];
+                const TS st = to_basis<TS>(a * (m[r] - cc * bcur[r]) - q * bprev[r]);
+                if (row < n) bn[row] = st;
+                bnext[r] = from_basis<TC>(st);
             }
             tick(0);
             bar.arrive();
@@ -137,9 +143,10 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
         double nn = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            nn += bcur[r] * bcur[r];
-            if (p.sketch_basis) vals[r * BLOCK + tid] = bcur[r];
-            vals[RB + r * BLOCK + tid] = m[r];
+            const double bc = static_cast<double>(bcur[r]);
+            nn += bc * bc;
+            if (p.sketch_basis) vals[r * BLOCK + tid] = bc;
+            vals[RB + r * BLOCK + tid] = static_cast<double>(m[r]);
         }
         const double nv[1] = {nn};
         block_sum<1>(nv, 1, red_tmp, red_out);  // also publishes vals
@@ -201,22 +208,32 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
 
 using KernelFn = void (*)(ChebParams);
 
-template <int BLOCK>
+template <int BLOCK, typename TC, typename TS>
 KernelFn pick(int R) {
     switch (R) {
-        case 1: return chebyshev_kernel<1, BLOCK>;
-        case 2: return chebyshev_kernel<2, BLOCK>;
-        case 4: return chebyshev_kernel<4, BLOCK>;
-        case 8: return chebyshev_kernel<8, BLOCK>;
+        case 1: return chebyshev_kernel<1, BLOCK, TC, TS>;
+        case 2: return chebyshev_kernel<2, BLOCK, TC, TS>;
+        case 4: return chebyshev_kernel<4, BLOCK, TC, TS>;
+        case 8: return chebyshev_kernel<8, BLOCK, TC, TS>;
         default: return nullptr;
     }
 }
 
-KernelFn pick_kernel(int block, int R) {
+template <typename TC, typename TS>
+KernelFn pick_block(int block, int R) {
     switch (block) {
-        case 256: return pick<256>(R);
-        case 512: return pick<512>(R);
-        case 1024: return pick<1024>(R);
+        case 256: return pick<256, TC, TS>(R);
+        case 512: return pick<512, TC, TS>(R);
+        case 1024: return pick<1024, TC, TS>(R);
+        default: return nullptr;
+    }
+}
+
+KernelFn pick_kernel(int block, int R, int precision) {
+    switch (precision) {
+        case SGMRES_PREC_FP64: return pick_block<double, double>(block, R);
+        case SGMRES_PREC_FP32: return pick_block<float, float>(block, R);
+        case SGMRES_PREC_BF16_BASIS: return pick_block<float, bf16_t>(block, R);
         default: return nullptr;
     }
 }
@@ -250,7 +267,7 @@ hipError_t chebyshev_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {
             if (shape.rows_per_thread && R != shape.rows_per_thread) continue;
             const size_t lds = chebyshev_lds_bytes(block, R, shape.s, shape.zeta);
             if (lds > static_cast<size_t>(lds_max)) continue;
-            KernelFn fn = pick_kernel(block, R);
+            KernelFn fn = pick_kernel(block, R, shape.precision);
             if (!fn) continue;
             err = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       static_cast<int>(lds));

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/sgmres.h"
 #include "internal.hpp"
 
@@ -16,6 +18,49 @@ namespace sg {
 
 constexpr int kWave = 64;
 constexpr double kUnitRoundoff = 0x1.0p-53;
+
+// --------------------------------------------------------------------------
+// Basis precisions.  TC is the type of the per-row arithmetic (SpMV, Gram-
+// Schmidt updates, recurrences), TS the storage type of the basis in HBM.  A
+// basis vector is rounded to TS once, when it is formed, and the rounded value
+// is what every later use sees (SpMV gathers, the register window, the
+// combine), so S A B is always formed for the B that is stored.
+// --------------------------------------------------------------------------
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <typename TC>
+struct BasisPrec;
+template <>
+struct BasisPrec<double> {
+    static constexpr double unit_roundoff = 0x1.0p-53;
+};
+template <>
+struct BasisPrec<float> {
+    static constexpr double unit_roundoff = 0x1.0p-24;
+};
+
+// TC -> TS; bfloat16 by round-to-nearest-even on the float bits (NaN stays NaN)
+template <typename TS, typename TC>
+__device__ __forceinline__ TS to_basis(TC x) {
+    if constexpr (std::is_same<TS, bf16_t>::value) {
+        const uint32_t u = __float_as_uint(static_cast<float>(x));
+        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{static_cast<uint16_t>((u >> 16) | 0x40u)};
+        return bf16_t{static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};
+    } else {
+        return static_cast<TS>(x);
+    }
+}
+
+template <typename TC, typename TS>
+__device__ __forceinline__ TC from_basis(TS v) {
+    if constexpr (std::is_same<TS, bf16_t>::value) {
+        return static_cast<TC>(__uint_as_float(static_cast<uint32_t>(v.bits) << 16));
+    } else {
+        return static_cast<TC>(v);
+    }
+}
 
 // --------------------------------------------------------------------------
 // Philox4x32-10: ten rounds of the 4x32 Philox bijection.  Each round takes the

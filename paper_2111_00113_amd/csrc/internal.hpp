@@ -14,10 +14,10 @@ struct ArnoldiParams {
     int64_t n;
     const int32_t* rp;
     const int32_t* ci;
-    const double* val;
+    const void* val;     // A's values in the kernel's arithmetic type
     const double* r;     // cycle residual, n
     const double* beta;  // device scalar |r|
-    double* B;           // n x d, leading dim ldb
+    void* B;             // n x d in the basis storage type, leading dim ldb
     int64_t ldb;
     double* SB;   // s x d
     double* SAB;  // s x d
@@ -46,6 +46,7 @@ struct ArnoldiShape {
     int force_global_window;
     int per_block_release;
     int sketch_basis;  // nonzero: the instance that also forms S b_j
+    int precision;     // SGMRES_PREC_*
 };
 
 struct ArnoldiLaunch {
@@ -66,16 +67,21 @@ hipError_t arnoldi_launch(const ArnoldiLaunch& L, ArnoldiParams params, hipStrea
 size_t sync_words_bytes();
 // instance of the basis kernel that also forms S b_j (arnoldi_sb.hip)
 const void* arnoldi_pick_sb(int block, int R, int KW);
+// FP32 arithmetic with an FP32 / bfloat16 basis (arnoldi_f32.hip, arnoldi_bf16.hip)
+const void* arnoldi_pick_f32(int block, int R, int KW);
+const void* arnoldi_pick_bf16(int block, int R, int KW);
+// bytes of one stored basis entry for SGMRES_PREC_*
+inline size_t basis_elem_bytes(int precision) { return precision == 1 ? 4 : (precision == 2 ? 2 : 8); }
 
 // ---- Chebyshev basis kernel (chebyshev.hip) --------------------------------
 struct ChebParams {
     int64_t n;
     const int32_t* rp;
     const int32_t* ci;
-    const double* val;
+    const void* val;     // A's values in the kernel's arithmetic type
     const double* r;     // cycle residual, n
     const double* beta;  // device scalar |r|
-    double* B;           // n x d raw recurrence vectors, leading dim ldb
+    void* B;             // n x d raw recurrence vectors (storage type), leading dim ldb
     int64_t ldb;
     double* SB;       // s x d, sketches of the normalised columns (when sketch_basis)
     double* SAB;      // s x d, S A of the normalised columns
@@ -125,9 +131,12 @@ hipError_t launch_csr_outer(int64_t n, const int32_t* rp, const int32_t* ci, con
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t stream);
 hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t stream);
 // x += B[:, :*d_eff] y, or x += B[:, :*d_eff] (y ./ colnorm) when colnorm is
-// given (columns with colnorm 0 are skipped)
-hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const double* B, int64_t ldb,
-                          const double* y, double* x, hipStream_t stream, const double* colnorm = nullptr);
+// given (columns with colnorm 0 are skipped); B stored per SGMRES_PREC_*
+hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B, int64_t ldb,
+                          const double* y, double* x, hipStream_t stream, const double* colnorm = nullptr,
+                          int precision = 0);
+// out[i] = (float) in[i]
+hipError_t launch_to_f32(int64_t count, const double* in, float* out, hipStream_t stream);
 
 // ---- sketch kernels (sketch.hip) -------------------------------------------
 hipError_t launch_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s,

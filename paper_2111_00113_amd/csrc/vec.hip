@@ -66,8 +66,9 @@ __global__ void fill_u32_kernel(unsigned* x, int64_t n, unsigned v) {
 // x[i] += sum_{c < d_eff} B[c*ldb + i] y[c]; y staged in LDS; eight columns in
 // flight per thread.
 constexpr int kCombineBlock = 256;
+template <typename TS>
 __global__ __launch_bounds__(kCombineBlock) void combine_kernel(int64_t n, const int* __restrict__ d_eff_p,
-                                                                const double* __restrict__ B, int64_t ldb,
+                                                                const TS* __restrict__ B, int64_t ldb,
                                                                 const double* __restrict__ y,
                                                                 double* __restrict__ x,
                                                                 const double* __restrict__ cn) {
@@ -83,9 +84,10 @@ __global__ __launch_bounds__(kCombineBlock) void combine_kernel(int64_t n, const
         int c = 0;
         for (; c + 8 <= d_eff; c += 8) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += B[static_cast<int64_t>(c + u) * ldb + i] * ys[c + u];
+            for (int u = 0; u < 8; ++u)
+                acc[u] += from_basis<double>(B[static_cast<int64_t>(c + u) * ldb + i]) * ys[c + u];
         }
-        for (; c < d_eff; ++c) acc[0] += B[static_cast<int64_t>(c) * ldb + i] * ys[c];
+        for (; c < d_eff; ++c) acc[0] += from_basis<double>(B[static_cast<int64_t>(c) * ldb + i]) * ys[c];
         const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         x[i] += sum;
     }
@@ -166,13 +168,35 @@ hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t strea
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const double* B, int64_t ldb,
-                          const double* y, double* x, hipStream_t stream, const double* colnorm) {
+hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B, int64_t ldb,
+                          const double* y, double* x, hipStream_t stream, const double* colnorm, int precision) {
     int64_t g = (n + kCombineBlock - 1) / kCombineBlock;
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
-    combine_kernel<<<static_cast<int>(g), kCombineBlock, sizeof(double) * (d_max > 0 ? d_max : 1), stream>>>(
-        n, d_eff, B, ldb, y, x, colnorm);
+    const size_t lds = sizeof(double) * (d_max > 0 ? d_max : 1);
+    if (precision == SGMRES_PREC_FP32)
+        combine_kernel<float><<<static_cast<int>(g), kCombineBlock, lds, stream>>>(
+            n, d_eff, static_cast<const float*>(B), ldb, y, x, colnorm);
+    else if (precision == SGMRES_PREC_BF16_BASIS)
+        combine_kernel<bf16_t><<<static_cast<int>(g), kCombineBlock, lds, stream>>>(
+            n, d_eff, static_cast<const bf16_t*>(B), ldb, y, x, colnorm);
+    else
+        combine_kernel<double><<<static_cast<int>(g), kCombineBlock, lds, stream>>>(
+            n, d_eff, static_cast<const double*>(B), ldb, y, x, colnorm);
+    return hipGetLastError();
+}
+
+__global__ void to_f32_kernel(int64_t count, const double* __restrict__ in, float* __restrict__ out) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)
+        out[i] = static_cast<float>(in[i]);
+}
+
+hipError_t launch_to_f32(int64_t count, const double* in, float* out, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    int64_t g = (count + 255) / 256;
+    if (g > 4096) g = 4096;
+    to_f32_kernel<<<static_cast<int>(g), 256, 0, stream>>>(count, in, out);
     return hipGetLastError();
 }
 

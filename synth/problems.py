@@ -151,12 +151,19 @@ WORKLOADS = {
     "cd2048": dict(N=2048, beta=(50.0, 20.0), d=200, k=4, s=400, zeta=8, seed=0, tol=1e-10, restarts=1000),
     # differentiable-solve finite-difference check: n = 1024
     "cd32": dict(N=32, beta=(50.0, 20.0), d=200, k=4, s=400, zeta=8, seed=0, tol=1e-10, restarts=1000),
+    # random sparse nonsymmetric, well conditioned (diagonal dominance 1.2):
+    # n = 1,048,576, 7 nonzeros per row, the batched-workload parameters
+    "rd1m": dict(rand_n=1 << 20, offdiag=6, mat_seed=4, d=100, k=2, s=200, zeta=8, seed=0, tol=1e-10,
+                 restarts=1000),
 }
 
 
 def workload(name: str):
-    """Return (A, b, params) for a named convection-diffusion workload."""
+    """Return (A, b, params) for a named workload."""
     p = dict(WORKLOADS[name])
-    A = convection_diffusion(p.pop("N"), p.pop("beta"))
+    if "rand_n" in p:
+        A = random_dominant(p.pop("rand_n"), offdiag=p.pop("offdiag"), seed=p.pop("mat_seed"))
+    else:
+        A = convection_diffusion(p.pop("N"), p.pop("beta"))
     b = rhs(A.n, 0)
     return A, b, p

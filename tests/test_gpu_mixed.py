@@ -1,0 +1,147 @@
+"""Mixed-precision basis cycles with FP64 refinement, against the FP64 oracle.
+
+The modes change the basis cycles only: FP32 arithmetic on an FP32 copy of A's
+values, and the basis stored in FP32 or bfloat16.  The residual b - A x, the
+sums of block partials, the sketched least squares and x stay FP64, so each
+restart is an iterative-refinement step against the FP64 residual.
+
+Errors against the FP64 oracle, stated per result (the tests print them):
+  * one cycle, FP32: the basis and S A B carry relative errors of order
+    u32 = 6e-8 per operation, growing mildly over the d steps; the least-squares
+    solution moves by about kappa(S A B) times that.  Bound: 1e-4 relative on x,
+    1e-4 relative on the residual norm.
+  * one cycle, bfloat16 basis: the stored basis is a different basis of nearly the
+    same space (each entry rounded to 8 bits, u = 2^-9), and sGMRES minimises over
+    whatever basis is stored, consistently (S A B is formed from the stored
+    vectors).  Only the residual is comparable: within 10% of the FP64 residual
+    for truncated Arnoldi (Gram-Schmidt re-centres each rounded vector against
+    the window); within a factor 2 for the Chebyshev recurrence, which carries
+    the rounding of every stored vector into the next ones (measured: 1.39).
+  * refined to 1e-10: the true FP64 residual (recomputed by the oracle) is below
+    1e-10 in every mode, and x agrees with the oracle's FP64 solution to
+    kappa(A) * 2e-10 (kappa of the cd96 operator is about 4e3: bound 1e-6).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import paper_2111_00113_amd as sg
+
+    sg.lib()
+    return sg
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+BOX = (4.0, 4.0, 0.0)
+
+
+def _oracle_solve(orc, basis, A, f, **kw):
+    if basis == "chebyshev":
+        return orc.sgmres_solve_chebyshev(A, f, BOX, **kw)
+    return orc.sgmres_solve(A, f, k=2, **kw)
+
+
+@pytest.mark.parametrize("basis", ["arnoldi", "chebyshev"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_one_cycle_vs_fp64_oracle(sg, orc, basis, prec):
+    A = synth.convection_diffusion(80, (20.0, 20.0))
+    f = synth.rhs(A.n, 4)
+    d, s = 40, 90
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(f), x, d, 2, s, 5, 0.0, 0, precision=prec,
+                               cheb_box=BOX if basis == "chebyshev" else None)
+    rc_o, x_o, info_o = _oracle_solve(orc, basis, A, f, d=d, s=s, zeta=8, seed=5, tol=0.0, restarts=0)
+    err = np.linalg.norm(_np(x) - x_o) / np.linalg.norm(x_o)
+    rr = info["relres"] / info_o["relres"]
+    print(f"{basis} {prec} one cycle: |x - x64|/|x64| = {err:.3e}, relres ratio = {rr:.6f}", flush=True)
+    if prec == "fp32":
+        assert err <= 1e-4
+        assert abs(rr - 1.0) <= 1e-4
+    elif basis == "arnoldi":
+        assert abs(rr - 1.0) <= 0.1
+    else:
+        assert 0.5 <= rr <= 2.0
+
+
+@pytest.mark.parametrize("basis", ["arnoldi", "chebyshev"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_refinement_reaches_fp64_tolerance(sg, orc, basis, prec):
+    A = synth.convection_diffusion(96, (50.0, 20.0))
+    f = synth.rhs(A.n, 0)
+    dA = sg.DeviceCSR.from_host(A)
+    box = BOX if basis == "chebyshev" else None
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 2, 130, 0, 1e-10, 500, precision=prec, cheb_box=box)
+    x64 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc64, info64 = sg.sgmres_solve(dA, _t(f), x64, 60, 2, 130, 0, 1e-10, 500, cheb_box=box)
+    rc_o, x_o, info_o = _oracle_solve(orc, basis, A, f, d=60, s=130, zeta=8, seed=0, tol=1e-10, restarts=500)
+    assert rc == sg.OK and rc64 == sg.OK and rc_o == orc.OK
+    _, nrm = orc.residual(A, f, _np(x))
+    rel = nrm / np.linalg.norm(f)
+    err = np.linalg.norm(_np(x) - x_o) / np.linalg.norm(x_o)
+    print(f"{basis} {prec} refined: relres {rel:.3e}, cycles {info['cycles']} (fp64 {info64['cycles']}, "
+          f"oracle {info_o['cycles']}), |x - x64_oracle|/|x| = {err:.3e}", flush=True)
+    assert rel <= 1e-10
+    assert err <= 1e-6
+    assert info["cycles"] <= 2 * info64["cycles"] + 2
+
+
+def test_mixed_full_size_converges(sg, orc):
+    """n = 1,048,576: FP32 cycles (truncated Arnoldi and Chebyshev, cd1024,
+    d = 200, k = 4, s = 400) and bfloat16-basis cycles (the well-conditioned
+    random system rd1m, d = 100, k = 2, s = 200) with FP64 refinement reach
+    1e-10, confirmed by the oracle's residual."""
+    for wl, prec, box in (("cd1024", "fp32", None), ("cd1024", "fp32", BOX), ("rd1m", "bf16", None),
+                          ("rd1m", "fp32", None)):
+        A, f, p = synth.workload(wl)
+        dA = sg.DeviceCSR.from_host(A)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc, info = sg.sgmres_solve(dA, _t(f), x, p["d"], p["k"], p["s"], p["seed"], p["tol"], p["restarts"],
+                                   precision=prec, cheb_box=box)
+        _, nrm = orc.residual(A, f, _np(x))
+        print(f"full size {wl} {prec} {'chebyshev' if box else 'arnoldi'}: cycles {info['cycles']}, "
+              f"relres {nrm / np.linalg.norm(f):.3e}", flush=True)
+        assert rc == sg.OK
+        assert nrm / np.linalg.norm(f) <= 1e-10
+
+
+def test_bf16_basis_stalls_on_ill_conditioned_operator(sg, orc):
+    """The limit of a bfloat16 basis: on cd1024 (kappa(A) about 4e5) A times the
+    rounding error of a stored vector (2^-9 relative) outweighs A times its
+    smooth components, so refinement stalls near 1e-3.  The solve must say so
+    (SGMRES_NOT_CONVERGED, with the true residual reported), not return a
+    wrong answer as converged."""
+    A, f, p = synth.workload("cd1024")
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(f), x, p["d"], p["k"], p["s"], p["seed"], p["tol"],
+                               30, precision="bf16")
+    _, nrm = orc.residual(A, f, _np(x))
+    rel = nrm / np.linalg.norm(f)
+    print(f"bf16 cd1024 after 31 cycles: relres {rel:.3e}", flush=True)
+    assert rc == sg.NOT_CONVERGED
+    assert abs(info["relres"] - rel) <= 1e-6 * rel
+
+
+def test_precision_rejects_unknown_mode(sg):
+    A = synth.convection_diffusion(10)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    with pytest.raises(sg.SGMRESError) as e:
+        sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(synth.rhs(A.n)), x, 10, 2, 22, precision=7)
+    assert e.value.rc == -1
