@@ -115,6 +115,8 @@ typedef struct {
     double cheb_dx;     /* [cheb_c - cheb_dx, cheb_c + cheb_dx] x [-cheb_dy, cheb_dy] */
     double cheb_dy;     /* (Section 4.4); dx, dy >= 0, max(dx, dy) > 0; k is unused */
     int32_t precision;  /* SGMRES_PREC_* (0 = FP64) */
+    int32_t batch_eager; /* sgmres_solve_batched: launch each cycle's kernels directly
+                            instead of replaying the captured hipGraph */
 } sgmres_options_t;
 
 /*
@@ -232,6 +234,50 @@ int sgmres_csr_transpose(const sgmres_csr_t *A, int32_t *t_row_ptr, int32_t *t_c
  * -lambda_i x_j (and dL/db = lambda).  u, v: n entries; dval: nnz entries. */
 int sgmres_csr_outer_grad(const sgmres_csr_t *A, const double *u, const double *v, double alpha,
                           double *dval, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched solve: many independent systems A_i x_i = b_i of uneven sizes.
+ * ------------------------------------------------------------------------- */
+
+/* One system of a batch; the struct array is on the host, its arrays on the
+ * device.  Several systems may share A (blocks of right-hand sides). */
+typedef struct {
+    sgmres_csr_t A;
+    const double *b; /* n right-hand side */
+    double *x;       /* n; in: initial guess, out: approximate solution */
+} sgmres_system_t;
+
+/* Host-side result of one system. */
+typedef struct {
+    int32_t status; /* SGMRES_OK, SGMRES_NOT_CONVERGED or SGMRES_ENONFINITE */
+    int32_t cycles; /* basis cycles run */
+    int32_t steps;  /* basis columns built, summed */
+    int32_t flags;  /* OR of SGMRES_FLAG_* */
+    double relres;  /* final true relative residual |b - A x| / |b| */
+} sgmres_batch_result_t;
+
+/*
+ * Restarted sGMRES (Algorithm 1 with the restarts of Section 3.5) on each
+ * system independently, with the method of sgmres_solve_ex for truncated
+ * Arnoldi: the same sketch (keyed by seed, cycle and the row within the system)
+ * and the same stopping rule per system, so system i gets what sgmres_solve_ex
+ * gives for it alone, up to rounding.  All systems run in one persistent
+ * launch per cycle, one workgroup per system; each cycle's kernels are replayed
+ * from a captured hipGraph.  opts: zeta, kappa_max, precision (mixed precision
+ * with FP64 refinement as in sgmres_solve_ex), block_size / rows_per_thread
+ * (0 = 512 x 4 for batches under 2^20 rows, else chosen by timing the first
+ * cycle of each candidate; the choice is kept
+ * per problem class), batch_eager; other fields are ignored.
+ *   nsys     number of systems (0 returns SGMRES_OK)
+ *   systems  host array of nsys systems; every n >= d, 1 <= k <= 4
+ *   results  host array of nsys results, may be NULL
+ * Returns SGMRES_OK when every system converged, SGMRES_NOT_CONVERGED when some
+ * did not (results[i].status tells which), or an SGMRES_E* code for bad
+ * arguments (nothing is solved then).
+ */
+int sgmres_solve_batched(int nsys, const sgmres_system_t *systems, int d, int k, int s, uint64_t seed,
+                         double tol, int restarts, const sgmres_options_t *opts,
+                         sgmres_batch_result_t *results, void *stream);
 
 /* Frees the cached workspace of every device. */
 void sgmres_release_workspace(void);

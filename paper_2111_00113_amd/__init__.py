@@ -22,6 +22,7 @@ from .sgmres import (  # noqa: F401
     lib,
     sgmres_solve,
     sgmres_solve_transposed,
+    sgmres_solve_batched,
     sgmres_sketch_pattern,
     sgmres_sketch_apply,
     sgmres_residual,

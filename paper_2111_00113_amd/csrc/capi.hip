@@ -13,8 +13,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/sgmres.h"
 #include "internal.hpp"
@@ -42,6 +46,7 @@ struct DevScalars {
     int csr_bad;    // CSR validation failed
     int pad1[2];
     unsigned long long phase_ticks[8];  // basis-kernel phase timers (profile)
+    int batch_ctr[4];                   // batched solve: cycle, queue, active, active last cycle
 };
 
 struct Workspace {
@@ -76,6 +81,17 @@ struct Workspace {
     size_t colnorm_cap = 0;
     float* valf = nullptr;  // FP32 copy of A's values (mixed-precision cycles)
     size_t valf_cap = 0;
+    // batched solve: descriptors, states, order, and one arena for every
+    // system's basis, scratch vectors, sketch lists and small matrices
+    BatchSys* bt_sys = nullptr;
+    size_t bt_sys_cap = 0;
+    BatchState* bt_st = nullptr;
+    size_t bt_st_cap = 0;
+    int* bt_order = nullptr;
+    size_t bt_order_cap = 0;
+    unsigned char* bt_arena = nullptr;
+    size_t bt_arena_cap = 0;
+    hipStream_t capture_stream = nullptr;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
@@ -532,6 +548,249 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     return solve_impl(a, info);
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched solve: one workgroup per system and cycle (batched.hip), the
+// least squares as one workgroup per system, the cycle's kernels replayed from
+// a captured hipGraph.  The workgroup shape (rows per chunk) is picked by a
+// small autotuner that times the first cycle of each candidate and remembers
+// the winner per problem class.
+// ---------------------------------------------------------------------------
+struct BatchCand {
+    int block, R;
+};
+constexpr BatchCand kBatchCands[] = {{512, 4}, {256, 4}, {512, 2}, {1024, 2}, {1024, 4}, {1024, 1}};
+constexpr int kBatchMinChunk = 1024;  // smallest block * R among the candidates
+constexpr int kBatchMaxChunk = 4096;  // largest
+constexpr size_t kArenaAlign = 256;
+constexpr int64_t kBatchTuneRows = int64_t(1) << 20;  // smaller batches use 512 x 4
+
+using BatchKey = std::tuple<int, int, int, int, int, int, int>;
+std::map<BatchKey, BatchCand> g_batch_tuned;
+
+size_t align_up(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
+int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
+                     int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, hipStream_t st) {
+    const int zeta = (opts && opts->zeta) ? opts->zeta : 8;
+    const double kappa_max = (opts && opts->kappa_max > 0) ? opts->kappa_max : 1e14;
+    const int prec = opts ? opts->precision : SGMRES_PREC_FP64;
+    if (prec != SGMRES_PREC_FP64 && prec != SGMRES_PREC_FP32 && prec != SGMRES_PREC_BF16_BASIS) return SGMRES_EINVAL;
+    if (nsys < 0 || (nsys > 0 && !systems) || !(tol >= 0.0) || restarts < 0 || k > kBatchMaxK) return SGMRES_EINVAL;
+    for (int i = 0; i < nsys; ++i) {
+        const sgmres_system_t& y = systems[i];
+        if (!csr_ok(&y.A) || !y.b || !y.x || bad_sizes(y.A.n, d, k, s, zeta)) return SGMRES_EINVAL;
+    }
+    if (nsys == 0) return SGMRES_OK;
+
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* wsp = nullptr;
+    int rc = workspace(&wsp);
+    if (rc) return rc;
+    Workspace& ws = *wsp;
+
+    // CSR validation, one flag for the whole batch
+    SG_TRY(hipMemsetAsync(&ws.sc->csr_bad, 0, sizeof(int), st));
+    for (int i = 0; i < nsys; ++i)
+        SG_TRY(launch_csr_check(systems[i].A.n, systems[i].A.nnz, systems[i].A.row_ptr, systems[i].A.col_idx,
+                                &ws.sc->csr_bad, st));
+    rc = copy_scalars(ws, st);
+    if (rc) return rc;
+    if (ws.host_sc->csr_bad) return SGMRES_ECSR;
+
+    // arena layout (sized for every candidate chunk length)
+    const size_t eb = basis_elem_bytes(prec);
+    const size_t ec = (prec == SGMRES_PREC_FP64) ? 8 : 4;
+    std::vector<size_t> off(nsys + 1, 0);
+    auto sys_bytes = [&](const sgmres_system_t& y) {
+        const size_t n = static_cast<size_t>(y.A.n);
+        const size_t nch = n / kBatchMinChunk + 1;
+        size_t b = 0;
+        b += align_up(n * d * eb);                                            // B
+        b += 2 * align_up(n * ec);                                            // m, w
+        b += align_up(n * 8);                                                 // r
+        b += align_up(sizeof(uint16_t) * zeta * (n + kBatchMaxChunk));        // lists
+        b += align_up(sizeof(int) * nch * (s + 1));                           // list starts
+        b += align_up(8 * static_cast<size_t>(s) * d) + align_up(8 * s) + align_up(8 * d);  // SAB, g, y
+        if (prec != SGMRES_PREC_FP64) b += align_up(4 * static_cast<size_t>(y.A.nnz));      // FP32 values
+        return b;
+    };
+    for (int i = 0; i < nsys; ++i) off[i + 1] = off[i] + sys_bytes(systems[i]);
+    SG_TRY(ensure(ws.bt_arena, ws.bt_arena_cap, off[nsys]));
+    SG_TRY(ensure(ws.bt_sys, ws.bt_sys_cap, static_cast<size_t>(nsys)));
+    SG_TRY(ensure(ws.bt_st, ws.bt_st_cap, static_cast<size_t>(nsys)));
+    SG_TRY(ensure(ws.bt_order, ws.bt_order_cap, static_cast<size_t>(nsys)));
+
+    std::vector<BatchSys> desc(nsys);
+    int64_t total_rows = 0;
+    for (int i = 0; i < nsys; ++i) {
+        const sgmres_system_t& y = systems[i];
+        const size_t n = static_cast<size_t>(y.A.n);
+        const size_t nch = n / kBatchMinChunk + 1;
+        unsigned char* p = ws.bt_arena + off[i];
+        BatchSys& D = desc[i];
+        D.n = y.A.n;
+        D.rp = y.A.row_ptr;
+        D.ci = y.A.col_idx;
+        D.val = y.A.val;
+        D.b = y.b;
+        D.x = y.x;
+        D.B = p;
+        p += align_up(n * d * eb);
+        D.m = p;
+        p += align_up(n * ec);
+        D.w = p;
+        p += align_up(n * ec);
+        D.r = reinterpret_cast<double*>(p);
+        p += align_up(n * 8);
+        D.lists = reinterpret_cast<uint16_t*>(p);
+        p += align_up(sizeof(uint16_t) * zeta * (n + kBatchMaxChunk));
+        D.lstart = reinterpret_cast<int*>(p);
+        p += align_up(sizeof(int) * nch * (s + 1));
+        D.SAB = reinterpret_cast<double*>(p);
+        p += align_up(8 * static_cast<size_t>(s) * d);
+        D.g = reinterpret_cast<double*>(p);
+        p += align_up(8 * s);
+        D.y = reinterpret_cast<double*>(p);
+        p += align_up(8 * d);
+        D.valc = y.A.val;
+        if (prec != SGMRES_PREC_FP64) {
+            float* vf = reinterpret_cast<float*>(p);
+            SG_TRY(launch_to_f32(y.A.nnz, y.A.val, vf, st));
+            D.valc = vf;
+        }
+        total_rows += y.A.n;
+    }
+    // largest systems first
+    std::vector<int> order(nsys);
+    for (int i = 0; i < nsys; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return systems[a].A.n > systems[b].A.n; });
+    SG_TRY(hipMemcpyAsync(ws.bt_sys, desc.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+    SG_TRY(hipMemcpyAsync(ws.bt_order, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
+
+    int* ctr = ws.sc->batch_ctr;
+    BatchParams bp{};
+    bp.nsys = nsys;
+    bp.sys = ws.bt_sys;
+    bp.st = ws.bt_st;
+    bp.order = ws.bt_order;
+    bp.queue = ctr + 1;
+    bp.active = ctr + 2;
+    bp.cycle = ctr;
+    bp.d = d;
+    bp.k = k;
+    bp.s = s;
+    bp.zeta = zeta;
+    bp.restarts = restarts;
+    bp.seed = seed;
+    bp.tol = tol;
+
+    // workgroup shape: given, the default for small batches, remembered, or
+    // timed on the first cycle
+    BatchLaunch L{};
+    const int want_block = opts ? opts->block_size : 0;
+    const int want_R = opts ? opts->rows_per_thread : 0;
+    if (want_block || want_R || total_rows < kBatchTuneRows) {
+        if (batch_configure(want_block ? want_block : 512, want_R ? want_R : 4, d, s, zeta, prec, &L) != hipSuccess)
+            return SGMRES_EINVAL;
+    } else {
+        const BatchKey key{nsys, static_cast<int>(total_rows >> 16), d, k, s, zeta, prec};
+        auto it = g_batch_tuned.find(key);
+        if (it != g_batch_tuned.end()) {
+            SG_TRY(batch_configure(it->second.block, it->second.R, d, s, zeta, prec, &L));
+        } else {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            SG_TRY(hipEventCreate(&e0));
+            SG_TRY(hipEventCreate(&e1));
+            float best = 0.0f;
+            BatchCand win{0, 0};
+            for (const BatchCand& c : kBatchCands) {
+                BatchLaunch T{};
+                if (batch_configure(c.block, c.R, d, s, zeta, prec, &T) != hipSuccess) continue;
+                SG_TRY(launch_batch_reset(ws.bt_st, nsys, ctr, st));
+                SG_TRY(hipEventRecord(e0, st));
+                SG_TRY(batch_launch(T, bp, st));
+                SG_TRY(hipEventRecord(e1, st));
+                SG_TRY(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                SG_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (win.block == 0 || ms < best) {
+                    best = ms;
+                    win = c;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (win.block == 0) return SGMRES_EINVAL;
+            g_batch_tuned[key] = win;
+            SG_TRY(batch_configure(win.block, win.R, d, s, zeta, prec, &L));
+        }
+    }
+
+    SG_TRY(launch_batch_reset(ws.bt_st, nsys, ctr, st));
+    const bool eager = opts && opts->batch_eager;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (!eager) {
+        if (!ws.capture_stream) SG_TRY(hipStreamCreateWithFlags(&ws.capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = ws.capture_stream;
+        SG_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t e = batch_launch(L, bp, cs);
+        if (e == hipSuccess) e = launch_lsq_batched(nsys, s, ws.bt_sys, ws.bt_st, kappa_max, cs);
+        if (e == hipSuccess) e = launch_batch_advance(ctr, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return to_code(e);
+        }
+    }
+    int status = SGMRES_OK;
+    for (int c = 0; c <= restarts + 2; ++c) {
+        hipError_t e;
+        if (eager) {
+            e = batch_launch(L, bp, st);
+            if (e == hipSuccess) e = launch_lsq_batched(nsys, s, ws.bt_sys, ws.bt_st, kappa_max, st);
+            if (e == hipSuccess) e = launch_batch_advance(ctr, st);
+        } else {
+            e = hipGraphLaunch(exec, st);
+        }
+        if (e != hipSuccess) {
+            status = to_code(e);
+            break;
+        }
+        rc = copy_scalars(ws, st);
+        if (rc) {
+            status = rc;
+            break;
+        }
+        if (ws.host_sc->batch_ctr[3] == 0) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (status != SGMRES_OK) return status;
+
+    std::vector<BatchState> hs(nsys);
+    SG_TRY(hipMemcpyAsync(hs.data(), ws.bt_st, sizeof(BatchState) * nsys, hipMemcpyDeviceToHost, st));
+    SG_TRY(hipStreamSynchronize(st));
+    int all = SGMRES_OK;
+    for (int i = 0; i < nsys; ++i) {
+        const BatchState& t = hs[i];
+        const int code = t.status == 1 ? SGMRES_OK : (t.status == 3 ? SGMRES_ENONFINITE : SGMRES_NOT_CONVERGED);
+        if (code != SGMRES_OK) all = SGMRES_NOT_CONVERGED;
+        if (results) {
+            results[i].status = code;
+            results[i].cycles = t.cycles;
+            results[i].steps = t.steps;
+            results[i].flags = t.flags | t.lsq_flags;
+            results[i].relres = t.rho;
+        }
+    }
+    return all;
+}
+
 }  // namespace
 }  // namespace sg
 
@@ -745,7 +1004,9 @@ void sgmres_release_workspace(void) {
     for (auto& kv : g_ws) {
         (void)hipSetDevice(kv.first);
         Workspace& w = kv.second;
-        void* ptrs[] = {w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
+        if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
+        void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_order, w.bt_arena,
+                        w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
                         w.part_vec, w.part_nrm, w.colnorm, w.valf, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch};
         for (void* p : ptrs)
@@ -754,6 +1015,12 @@ void sgmres_release_workspace(void) {
     }
     g_ws.clear();
     (void)hipSetDevice(cur);
+}
+
+int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
+                         int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, void* stream) {
+    return batch_solve_impl(nsys, systems, d, k, s, seed, tol, restarts, opts, results,
+                            static_cast<hipStream_t>(stream));
 }
 
 const char* sgmres_version(void) { return "sgmres-gfx950 0.1.0"; }

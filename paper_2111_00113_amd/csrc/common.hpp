@@ -378,17 +378,17 @@ __device__ __forceinline__ double signed_val(const double* v, unsigned u) {
     return (u & 1u) ? -x : x;
 }
 
-// Block partial (unscaled) of S v over sketch rows [r0, r1) for vectors
-// v = v0 .. v0+nvec-1 staged in vals[v * RB + local]; entry (v, row) goes to
-// dst[(v * s + row) * G + blk].  Each list is cut into kSketchParts pieces,
-// each piece summed four entries at a time (independent loads), and the
-// pieces added in a fixed order.  sk_tmp: nvec * (r1 - r0) * kSketchParts
-// doubles.  Starts after the caller's __syncthreads() that published vals;
-// contains one __syncthreads().
-template <int BLOCK>
-__device__ __forceinline__ void sketch_lists_apply(int v0, int nvec, int r0, int r1, const double* vals, int RB,
-                                                   int s, const int* lstart, const uint16_t* lists, double* sk_tmp,
-                                                   double* dst, int G, int blk) {
+// Block share (unscaled) of S v over sketch rows [r0, r1) for vectors
+// v = v0 .. v0+nvec-1 staged in vals[v * RB + local].  Each list is cut into
+// kSketchParts pieces, each piece summed four entries at a time (independent
+// loads), and the pieces added in a fixed order; fin(v, row, value) receives
+// each sum once.  sk_tmp: nvec * (r1 - r0) * kSketchParts doubles.  Starts
+// after the caller's __syncthreads() that published vals; contains one
+// __syncthreads().
+template <int BLOCK, typename Fin>
+__device__ __forceinline__ void sketch_lists_reduce(int v0, int nvec, int r0, int r1, const double* vals, int RB,
+                                                    const int* lstart, const uint16_t* lists, double* sk_tmp,
+                                                    Fin fin) {
     const int tid = threadIdx.x;
     const int nrow = r1 - r0;
     const int tasks = nvec * nrow * kSketchParts;
@@ -420,9 +420,19 @@ __device__ __forceinline__ void sketch_lists_apply(int v0, int nvec, int r0, int
 #pragma unroll
         for (int part = 0; part < kSketchParts; ++part) a += sk_tmp[e * kSketchParts + part];
         const int v = e / nrow;
-        const int row = r0 + (e - v * nrow);
-        dst[static_cast<int64_t>((v0 + v) * s + row) * G + blk] = a;
+        fin(v0 + v, r0 + (e - v * nrow), a);
     }
+}
+
+// Block partial of S v written to dst[(v * s + row) * G + blk] (see
+// sketch_lists_reduce).
+template <int BLOCK>
+__device__ __forceinline__ void sketch_lists_apply(int v0, int nvec, int r0, int r1, const double* vals, int RB,
+                                                   int s, const int* lstart, const uint16_t* lists, double* sk_tmp,
+                                                   double* dst, int G, int blk) {
+    sketch_lists_reduce<BLOCK>(v0, nvec, r0, r1, vals, RB, lstart, lists, sk_tmp, [&](int v, int row, double a) {
+        dst[static_cast<int64_t>(v * s + row) * G + blk] = a;
+    });
 }
 
 // Blocks of a launch are dealt round-robin to the 8 XCDs; give each XCD a

@@ -109,6 +109,77 @@ size_t chebyshev_lds_bytes(int block, int R, int s, int zeta);
 hipError_t chebyshev_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
 hipError_t chebyshev_launch(const ArnoldiLaunch& L, ChebParams params, hipStream_t stream);
 
+// ---- batched solve (batched.hip) ------------------------------------------
+// One descriptor per system (device copy); the basis, scratch vectors and the
+// sketch lists of a system live at its own offsets in the batch workspace.
+struct BatchSys {
+    int64_t n;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;   // FP64 values (residual)
+    const void* valc;    // values in the cycle's arithmetic type
+    const double* b;
+    double* x;
+    void* B;             // n x d, storage type, leading dim n
+    void* m;             // n, arithmetic type: A b_j of the current step
+    void* w;             // n, arithmetic type: first Gram-Schmidt update
+    double* r;           // n: residual
+    uint16_t* lists;     // per chunk of CH rows: zeta * CH entries (sorted sketch lists)
+    int* lstart;         // per chunk: s + 1 list starts
+    double* SAB;         // s x d
+    double* g;           // s
+    double* y;           // d
+};
+
+// Per-system state, kept across the cycles of one batched solve.
+struct BatchState {
+    double nf;     // |b|
+    double beta;   // |r| of the last residual
+    double rho;    // |r| / |b|
+    double rest;   // least-squares residual estimate   (rest, kappa adjacent:
+    double kappa;  // diagonal ratio of T                 the LSQ writes both)
+    int d_eff;     // columns used by the least squares   (d_eff, lsq_flags
+    int lsq_flags; //                                       adjacent likewise)
+    int status;    // 0 active, 1 converged, 2 out of restarts, 3 non-finite
+    int dc;        // columns built in the last cycle
+    int flags;     // OR of breakdown flags
+    int cycles;    // basis cycles run
+    int steps;     // basis columns built, summed
+    int pad;
+};
+
+struct BatchParams {
+    int nsys;
+    const BatchSys* sys;
+    BatchState* st;
+    const int* order;   // systems in processing order (largest first)
+    int* queue;         // next position in `order` (zero at launch)
+    int* active;        // systems that built a basis this cycle
+    const int* cycle;   // device cycle counter (the counter array of launch_batch_advance)
+    int d, k, s, zeta;
+    int restarts;
+    uint64_t seed;
+    double tol;
+};
+
+struct BatchLaunch {
+    const void* fn;
+    int block, R, grid;
+    size_t lds;
+};
+constexpr int kBatchMaxK = 4;
+// chunk rows a kernel instance handles at a time
+inline int batch_chunk(const BatchLaunch& L) { return L.block * L.R; }
+hipError_t batch_configure(int block, int R, int d, int s, int zeta, int precision, BatchLaunch* out);
+hipError_t batch_launch(const BatchLaunch& L, const BatchParams& p, hipStream_t stream);
+// ctr (4 ints): [0] cycle, [1] queue position, [2] active systems, [3] active
+// systems of the cycle that just ended.  advance: end of a cycle; reset: start
+// of a solve (also clears every BatchState).
+hipError_t launch_batch_advance(int* ctr, hipStream_t stream);
+hipError_t launch_batch_reset(BatchState* st, int nsys, int* ctr, hipStream_t stream);
+hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
+                              hipStream_t stream);
+
 // ---- vector kernels (vec.hip) ----------------------------------------------
 constexpr int kVecBlock = 256;
 int vec_grid(int64_t n);  // blocks used by the partial-sum kernels (<= kMaxVecGrid)

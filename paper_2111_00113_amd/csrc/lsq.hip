@@ -19,16 +19,13 @@ constexpr int kLsqBlock = 1024;
 constexpr int kLsqWaves = kLsqBlock / kWave;
 constexpr int kZSlots = kLsqMaxCols / kWave;
 
-__global__ __launch_bounds__(kLsqBlock) void lsq_kernel(int s, const int* __restrict__ dc_dev, int dc_host,
-                                                        double* __restrict__ C, double* __restrict__ g,
-                                                        double kappa_max, double* __restrict__ y,
-                                                        double* __restrict__ dout, int* __restrict__ iout) {
-    extern __shared__ double v[];  // s doubles: tail of the current reflector
+// The whole solve on one workgroup of kLsqBlock threads; v: s doubles of LDS.
+__device__ void lsq_body(int s, int dc, double* __restrict__ C, double* __restrict__ g, double kappa_max,
+                         double* __restrict__ y, double* __restrict__ dout, int* __restrict__ iout, double* v) {
     __shared__ double tmp[kLsqWaves];
     __shared__ double red[1];
     __shared__ double bc[3];
     __shared__ int ibc[1];
-    const int dc = dc_dev ? *dc_dev : dc_host;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
@@ -138,6 +135,24 @@ __global__ __launch_bounds__(kLsqBlock) void lsq_kernel(int s, const int* __rest
     const double vals[1] = {t};
     block_sum<1>(vals, 1, tmp, red);
     if (tid == 0) dout[0] = sqrt(red[0]);
+}
+
+__global__ __launch_bounds__(kLsqBlock) void lsq_kernel(int s, const int* __restrict__ dc_dev, int dc_host,
+                                                        double* __restrict__ C, double* __restrict__ g,
+                                                        double kappa_max, double* __restrict__ y,
+                                                        double* __restrict__ dout, int* __restrict__ iout) {
+    extern __shared__ double v[];  // s doubles: tail of the current reflector
+    lsq_body(s, dc_dev ? *dc_dev : dc_host, C, g, kappa_max, y, dout, iout, v);
+}
+
+// One workgroup per system of a batch; systems no longer active are skipped.
+__global__ __launch_bounds__(kLsqBlock) void lsq_batched_kernel(int s, const BatchSys* __restrict__ sys,
+                                                                BatchState* __restrict__ st, double kappa_max) {
+    extern __shared__ double v[];
+    BatchState* t = st + blockIdx.x;
+    if (t->status != 0) return;
+    const BatchSys& S = sys[blockIdx.x];
+    lsq_body(s, t->dc, S.SAB, S.g, kappa_max, S.y, &t->rest, &t->d_eff, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,6 +455,13 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
 hipError_t launch_lsq(int s, const int* dc_dev, int dc_host, double* C, double* g, double kappa_max,
                       double* y, double* dout, int* iout, hipStream_t stream) {
     lsq_kernel<<<1, kLsqBlock, sizeof(double) * s, stream>>>(s, dc_dev, dc_host, C, g, kappa_max, y, dout, iout);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
+                              hipStream_t stream) {
+    if (nsys <= 0) return hipSuccess;
+    lsq_batched_kernel<<<nsys, kLsqBlock, sizeof(double) * s, stream>>>(s, sys, st, kappa_max);
     return hipGetLastError();
 }
 

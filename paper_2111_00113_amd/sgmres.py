@@ -85,6 +85,21 @@ class _Options(ctypes.Structure):
         ("cheb_dx", ctypes.c_double),
         ("cheb_dy", ctypes.c_double),
         ("precision", ctypes.c_int32),
+        ("batch_eager", ctypes.c_int32),
+    ]
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("A", _CSR), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
+class _BatchResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("cycles", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("relres", ctypes.c_double),
     ]
 
 
@@ -110,6 +125,8 @@ def lib():
     L.sgmres_residual.argtypes = [P(_CSR), vp, vp, vp, P(dbl), vp]
     L.sgmres_arnoldi_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, i32, u64, u32, vp, i64, vp, vp, vp, vp,
                                        P(i32), P(i32), vp]
+    L.sgmres_solve_batched.argtypes = [i32, P(_System), i32, i32, i32, u64, dbl, i32, P(_Options),
+                                       P(_BatchResult), vp]
     L.sgmres_chebyshev_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, u64, u32, dbl, dbl, dbl, vp, i64, vp, vp,
                                          vp, vp, vp]
     L.sgmres_sketched_lsq.argtypes = [i32, i32, vp, vp, dbl, vp, P(i32), P(dbl), P(dbl), P(i32), vp]
@@ -213,10 +230,38 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     basis, (cc, cdx, cdy) = (0, (0.0, 0.0, 0.0)) if cheb_box is None else (1, tuple(float(t) for t in cheb_box))
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
-                    barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec)
+                    barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec, 0)
     rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
                                ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     return _raise("sgmres_solve", rc), _info(info)
+
+
+def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
+                         precision="fp64", block_size=0, rows_per_thread=0, eager=False, stream=None):
+    """Restarted sGMRES on many independent systems in one launch per cycle.
+
+    systems: list of (DeviceCSR A, b, x) with b, x float64 GPU tensors (x is the
+    initial guess, updated in place); several systems may share one A.  Returns
+    (rc, results) with rc SGMRES_OK when all converged, SGMRES_NOT_CONVERGED
+    otherwise, and one dict per system (status, cycles, steps, flags, relres)."""
+    arr = (_System * max(len(systems), 1))()
+    keep = []
+    for i, (A, b, x) in enumerate(systems):
+        _check_dev(b, torch.float64, A.n)
+        _check_dev(x, torch.float64, A.n)
+        c = A._c()
+        keep.append(c)
+        arr[i] = _System(c, b.data_ptr(), x.data_ptr())
+    res = (_BatchResult * max(len(systems), 1))()
+    prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opts = _Options(zeta, kappa_max, 0, block_size, rows_per_thread, 0, 0, 0, 0, 0.0, 0.0, 0.0, prec,
+                    1 if eager else 0)
+    rc = lib().sgmres_solve_batched(len(systems), arr, d, k, s, seed, tol, restarts, ctypes.byref(opts), res,
+                                    _stream(stream))
+    _raise("sgmres_solve_batched", rc)
+    out = [dict(status=r.status, cycles=r.cycles, steps=r.steps, flags=r.flags, relres=r.relres)
+           for r in res[: len(systems)]]
+    return rc, out
 
 
 def sgmres_solve_transposed(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, stream=None):

@@ -11,6 +11,8 @@ from .problems import (  # noqa: F401
     random_dominant,
     rhs,
     batched_random_systems,
+    batch_workload,
+    block_rhs_workload,
     diagonal,
     WORKLOADS,
     workload,

@@ -111,15 +111,27 @@ def random_dominant(n: int, offdiag: int = 6, seed=0, dominance: float = 1.2) ->
         if not dup.any():
             break
         cols[dup] = rng.integers(0, n - 1, size=(int(dup.sum()), m), dtype=np.int64)
-    rows = np.repeat(np.arange(n, dtype=np.int64), m)
-    cols = cols.reshape(-1)
-    cols = cols + (cols >= rows)  # skip the diagonal
-    vals = rng.standard_normal(n * m)
-    diag = dominance * np.bincount(rows, weights=np.abs(vals), minlength=n)
-    diag[diag == 0] = 1.0
     ar = np.arange(n, dtype=np.int64)
-    return _csr_from_coo(
-        n, np.concatenate([rows, ar]), np.concatenate([cols, ar]), np.concatenate([vals, diag])
+    cols = cols + (cols >= ar[:, None])  # skip the diagonal
+    vals = rng.standard_normal(n * m).reshape(n, m)
+    diag = np.zeros(n)
+    for t in range(m):  # row sums in column order
+        diag += np.abs(vals[:, t])
+    diag *= dominance
+    diag[diag == 0] = 1.0
+    # every row holds m + 1 distinct columns: sort within rows (CSR order)
+    allc = np.concatenate([cols, ar[:, None]], axis=1)
+    allv = np.concatenate([vals, diag[:, None]], axis=1)
+    order = np.argsort(allc, axis=1, kind="stable")
+    allc = np.take_along_axis(allc, order, axis=1)
+    allv = np.take_along_axis(allv, order, axis=1)
+    if n * (m + 1) >= 2**31:
+        raise ValueError("nnz exceeds int32 range")
+    return CSR(
+        n=n,
+        row_ptr=(np.arange(n + 1, dtype=np.int64) * (m + 1)).astype(np.int32),
+        col_idx=allc.reshape(-1).astype(np.int32),
+        val=np.ascontiguousarray(allv.reshape(-1), dtype=np.float64),
     )
 
 
@@ -139,6 +151,20 @@ def batched_random_systems(count: int = 256, lo: int = 16384, hi: int = 262144, 
     """Sizes and generator seeds of the many-systems workload (uneven n)."""
     sizes = np.random.default_rng(seed).integers(lo, hi, endpoint=True, size=count)
     return [(int(n_i), [seed, i]) for i, n_i in enumerate(sizes)]
+
+
+def batch_workload(count: int = 256, lo: int = 16384, hi: int = 262144, seed: int = 4):
+    """The many-systems workload: system i is random_dominant(n_i, 6 off-diagonals,
+    seed [seed, i]) with b_i ~ N(0, I) from default_rng([0, i]).  Returns a list of
+    (A_i, b_i)."""
+    return [(random_dominant(n_i, offdiag=6, seed=sd), rhs(n_i, [0, i]))
+            for i, (n_i, sd) in enumerate(batched_random_systems(count, lo, hi, seed))]
+
+
+def block_rhs_workload(n: int = 1 << 20, nrhs: int = 32, seed: int = 2):
+    """One random_dominant(n, 6 off-diagonals, seed) matrix with nrhs right-hand
+    sides b_j ~ N(0, I) from default_rng([seed, j])."""
+    return random_dominant(n, offdiag=6, seed=seed), [rhs(n, [seed, j]) for j in range(nrhs)]
 
 
 # Named workloads: operator recipe + solver parameters.
