@@ -160,6 +160,95 @@ def grad_bench(args, A, f, p, sg, torch, np) -> int:
     return 0
 
 
+def batch_bench(args, sg, synth, torch, np) -> int:
+    """Many independent systems in one launch per cycle (one workgroup per
+    system), FP32 cycles with FP64 refinement, against FP64 sGMRES solving the
+    same systems one at a time on the same GPU."""
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    d, k, s, tol, restarts = 100, 2, 200, 1e-10, 50
+    log(f"generating {args.batch_count} systems")
+    W = synth.batch_workload(args.batch_count)
+    systems = [(sg.DeviceCSR.from_host(A, dev), torch.as_tensor(b, device=dev),
+                torch.zeros(A.n, dtype=torch.float64, device=dev)) for A, b in W]
+    rows = sum(A.n for A, _ in W)
+    nnz = sum(A.nnz for A, _ in W)
+    log(f"generating the block of {args.block_rhs} right-hand sides")
+    A1, B1 = synth.block_rhs_workload(1 << 20, args.block_rhs)
+    dA1 = sg.DeviceCSR.from_host(A1, dev)
+    block = [(dA1, torch.as_tensor(b, device=dev), torch.zeros(A1.n, dtype=torch.float64, device=dev)) for b in B1]
+    del W, B1
+
+    def batched(sysl, prec):
+        for _, _, x in sysl:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, res = sg.sgmres_solve_batched(sysl, d, k, s, 0, tol, restarts, precision=prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if rc != sg.OK or max(r["relres"] for r in res) > tol:
+            raise RuntimeError(f"batched solve ({prec}) did not converge")
+        return el, res
+
+    def one_at_a_time(sysl):
+        for _, _, x in sysl:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc = 0
+        for A, b, x in sysl:
+            rc, info = sg.sgmres_solve(A, b, x, d, k, s, 0, tol, restarts)
+            if rc != sg.OK:
+                raise RuntimeError("single solve did not converge")
+            cyc += info["cycles"]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, cyc
+
+    for prec in ("fp32", "fp64"):  # warm-up (also times the workgroup shapes once)
+        batched(systems, prec)
+        batched(block, prec)
+    one_at_a_time(systems[:4])
+    out = {}
+    for name, sysl in (("many", systems), ("block", block)):
+        t32 = t64 = None
+        for _ in range(args.steps):
+            e32, r32 = batched(sysl, "fp32")
+            e64, r64 = batched(sysl, "fp64")
+            t32 = e32 if t32 is None else min(t32, e32)
+            t64 = e64 if t64 is None else min(t64, e64)
+        tseq, cseq = one_at_a_time(sysl)
+        out[name] = dict(
+            systems=len(sysl), fp32_batched_s=t32, fp64_batched_s=t64, fp64_one_at_a_time_s=tseq,
+            fp32_batched_systems_per_s=len(sysl) / t32, fp64_batched_systems_per_s=len(sysl) / t64,
+            fp64_one_at_a_time_systems_per_s=len(sysl) / tseq,
+            speedup_fp32_batched_vs_fp64_one_at_a_time=tseq / t32,
+            cycles_fp32=sum(r["cycles"] for r in r32), cycles_fp64=sum(r["cycles"] for r in r64),
+            cycles_one_at_a_time=cseq, max_relres_fp32=max(r["relres"] for r in r32))
+        log(f"{name}: {out[name]}")
+    m = out["many"]
+    # whole-solve algorithmic bytes of the FP32 basis steps (per step and system:
+    # (4 + 4) nnz + 4n + 4n(k + 1)) over the FP32 batched solve time
+    algo = (8.0 * nnz + 4.0 * rows + 4.0 * rows * (k + 1)) * d * (m["cycles_fp32"] / len(systems))
+    achieved = algo / m["fp32_batched_s"] / 1e9
+    print(json.dumps({
+        "metric": (f"batched sGMRES systems/s at rel. residual 1e-10 ({len(systems)} random sparse systems, "
+                   f"n in [16384, 262144], d={d}, k={k}, s={s})"),
+        "value": m["fp32_batched_systems_per_s"], "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": m["fp32_batched_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 basis cycles, f64 refinement", "data": "synthetic",
+        "config": {"workload": (f"{len(systems)} systems random_dominant(n_i, 6 off-diagonals, seed [4, i]), "
+                                f"n_i = default_rng(4).integers(16384, 262144), total rows {rows}, nnz {nnz}; "
+                                f"block: n = 2^20 with {args.block_rhs} right-hand sides; d={d}, k={k}, s={s}, "
+                                f"zeta=8, tol=1e-10"), "rows": rows, "nnz": nnz},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "batched_cycle_kernel (whole solve: algorithmic basis bytes / solve time)"},
+        "many_systems": m, "rhs_block": out["block"],
+    }), flush=True)
+    return 0
+
+
 def cheb_launch_bytes(n: int, nnz: int, dc: float, prec: str = "fp64") -> float:
     """Algorithmic HBM bytes of one Chebyshev basis-kernel launch (dc steps).
 
@@ -186,8 +275,11 @@ def main() -> int:
     ap.add_argument("--cheb-box", default="4,4,0", help="c,dx,dy of the spectral box for --basis chebyshev")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="basis cycles in FP64, FP32, or FP32 with a bfloat16 basis (FP64 refinement)")
-    ap.add_argument("--mode", default="solve", choices=["solve", "grad"],
-                    help="solve: the sGMRES metric; grad: differentiable solve (forward + adjoint)")
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "batch"],
+                    help="solve: the sGMRES metric; grad: differentiable solve (forward + adjoint); "
+                         "batch: many systems per launch against one-at-a-time FP64 solves")
+    ap.add_argument("--batch-count", type=int, default=256, help="systems in the many-systems workload")
+    ap.add_argument("--block-rhs", type=int, default=32, help="right-hand sides of the n = 2^20 block")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -215,6 +307,9 @@ def main() -> int:
 
     import paper_2111_00113_amd as sg
     import synth
+
+    if args.mode == "batch":
+        return batch_bench(args, sg, synth, torch, np)
 
     log(f"building workload {args.workload}")
     A, f, p = synth.workload(args.workload)

@@ -1,22 +1,27 @@
 // Batched sGMRES: many independent systems per launch (arXiv:2111.00113,
 // Algorithm 1 with restarting, Section 3.5, applied to each system).
 //
-// One workgroup owns one system for a whole cycle, so every reduction of the
-// method is a workgroup reduction and no grid-wide synchronisation exists.
-// Persistent workgroups take systems from a queue (largest first).  A system's
-// rows are processed in chunks of CH = R * BLOCK (thread t owns rows
-// r * BLOCK + t of each chunk).  Per cycle and system:
+// Work unit: a part of a system, i.e. a range of whole chunks of CH = R * BLOCK
+// rows (thread t owns rows r * BLOCK + t of each chunk).  Small systems are one
+// part; large ones are split so that no workgroup carries much more than a
+// fixed number of rows.  Persistent workgroups take parts from a queue in which
+// the parts of a system are consecutive (largest systems first); the parts of a
+// system synchronise through a per-system counter (bounded waits), and a system
+// never has more parts than the grid has workgroups, so every part that waits
+// can count on the others being taken by free workgroups.
+//
+// Per cycle and system (each part on its rows; sums over the parts in fixed
+// part order, so every part sees the same bits and takes the same decisions):
 //   x += B y (previous cycle's least squares; FP64)
 //   r = b - A x (FP64), |r|; stop if |r|/|b| <= tol
 //   per chunk: sparse sign pattern of its rows, sorted by sketch row into
 //     lists (stored for the cycle), and the chunk's share of g = S r
 //   b_1 = r/|r|
-//   per step j (three passes over the chunks, k-truncated Arnoldi with two
-//   classical Gram-Schmidt passes, nu^2 = |w|^2 - |h2|^2):
-//     m = A b_j, <m,m>, W^T m, chunk shares of S m           -> h
-//     w = m - W h, <w,w>, W^T w                              -> h2, nu
-//     b_{j+1} = (w - W h2) / nu
-// S m_j is accumulated in LDS chunk by chunk in a fixed order (deterministic).
+//   per step j (k-truncated Arnoldi, two classical Gram-Schmidt passes,
+//   nu^2 = |w|^2 - |h2|^2; three group barriers):
+//     m = A b_j, <m,m>, W^T m, S m                      -> h, column j of S A B
+//     w = m - W h, <w,w>, W^T w                         -> h2, nu
+//     b_{j+1} = (w - W h2) / nu                         -> visible to all parts
 // The least squares runs afterwards as one workgroup per system (lsq.hip).
 #include "common.hpp"
 #include "internal.hpp"
@@ -24,8 +29,6 @@
 namespace sg {
 
 namespace {
-
-constexpr int kBRed = kBatchMaxK + 1;  // window dots + one norm per reduction
 
 __host__ __device__ constexpr int batch_vals_doubles(int CH, int zeta) {
     return (CH > (zeta * CH + 3) / 4) ? CH : (zeta * CH + 3) / 4;
@@ -42,14 +45,15 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
     //      (s+1) | counters (s) | lists (zeta CH)
     double* vals = smem;
     double* red_tmp = vals + batch_vals_doubles(CH, zeta);
-    double* red_out = red_tmp + NW * kBRed;
-    double* acc = red_out + kBRed;
+    double* red_out = red_tmp + NW * kBatchRed;
+    double* acc = red_out + kBatchRed;
     double* sk_tmp = acc + s;
     double* ylds = sk_tmp + s * kSketchParts;
     int* lstart = reinterpret_cast<int*>(ylds + d);
     int* lcount = lstart + (s + 1);
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
-    __shared__ int sys_sh;
+    __shared__ int task_sh;
+    __shared__ int fail_sh;
 
     const int tid = threadIdx.x;
     const double scale = 1.0 / sqrt(static_cast<double>(zeta));
@@ -62,60 +66,136 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
     for (;;) {
         if (tid == 0) {
             const int q = atomicAdd(p.queue, 1);
-            sys_sh = q < p.nsys ? p.order[q] : -1;
+            task_sh = q < p.ntask ? q : -1;
         }
         __syncthreads();
-        const int sid = sys_sh;
+        const int ti = task_sh;
         __syncthreads();
-        if (sid < 0) break;
+        if (ti < 0) break;
+        const BatchTask T = p.task[ti];
+        const int sid = T.sys, part = T.part, P = T.nparts;
         BatchState* st = p.st + sid;
-        if (st->status != 0) continue;
+        if (st->status != 0) continue;  // decided in an earlier cycle: the same for every part
         const BatchSys S = p.sys[sid];
         const int64_t n = S.n;
-        const int nch = static_cast<int>((n + CH - 1) / CH);
+        const int64_t r0 = T.r0, r1 = T.r1;
+        const int ch0 = static_cast<int>(r0 / CH);
+        const int nch = static_cast<int>((r1 - r0 + CH - 1) / CH);
         TS* Bs = static_cast<TS*>(S.B);
         const TC* Av = static_cast<const TC*>(S.valc);
         TC* Ms = static_cast<TC*>(S.m);
         TC* Ws = static_cast<TC*>(S.w);
+        double* red_slot = p.slots + p.slot_off[sid];    // [2][P][kBatchRed]
+        double* sk_slot = red_slot + 2 * P * kBatchRed;  // [P][s]
+        unsigned* cnt = p.gcnt + sid;
+        unsigned epoch = 0;
+        int nred = 0;
+        bool failed = false;
+        const bool lead = part == 0;
+
+        // barrier among the parts of this system (a workgroup barrier when P = 1)
+        auto gsync = [&]() {
+            if (P == 1) {
+                __syncthreads();
+                return;
+            }
+            ++epoch;
+            __syncthreads();
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned target = epoch * static_cast<unsigned>(P);
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                int f = 0;
+                while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (__hip_atomic_load(p.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        f = 1;
+                        break;
+                    }
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > p.spin_limit) {
+                        __hip_atomic_store(p.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        f = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                fail_sh = f;
+            }
+            __syncthreads();
+            failed = failed || (fail_sh != 0);
+        };
+        // red_out[0..nv) (this part's workgroup sums) -> sums over all parts.
+        // With sketch != null also the parts' sketch accumulators are exchanged
+        // (one barrier for both) and the lead part writes dst = scale * sum.
+        auto group_sum = [&](int nv, double* dst) {
+            if (P == 1) {
+                if (dst)
+                    for (int e = tid; e < s; e += BLOCK) dst[e] = acc[e] * scale;
+                return;
+            }
+            double* sl = red_slot + (nred & 1) * P * kBatchRed;
+            ++nred;
+            if (tid < nv) sl[part * kBatchRed + tid] = red_out[tid];
+            if (dst)
+                for (int e = tid; e < s; e += BLOCK) sk_slot[static_cast<int64_t>(part) * s + e] = acc[e];
+            gsync();
+            if (tid < nv) {
+                double a = 0.0;
+                for (int q = 0; q < P; ++q) a += sl[q * kBatchRed + tid];
+                red_out[tid] = a;
+            }
+            if (dst && lead)
+                for (int e = tid; e < s; e += BLOCK) {
+                    double a = 0.0;
+                    for (int q = 0; q < P; ++q) a += sk_slot[static_cast<int64_t>(q) * s + e];
+                    dst[e] = a * scale;
+                }
+            __syncthreads();
+        };
+        auto decide = [&](int code) {
+            if (lead && tid == 0) st->next = code;
+        };
 
         // ---- x += B y from the previous cycle --------------------------------
         if (combine) {
             const int de = min(st->d_eff, d);
             for (int c = tid; c < de; c += BLOCK) ylds[c] = S.y[c];
             __syncthreads();
-            for (int ch = 0; ch < nch; ++ch) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t row = static_cast<int64_t>(ch) * CH + r * BLOCK + tid;
-                    if (row < n) {
-                        double a = 0.0;
-                        for (int c = 0; c < de; ++c) a += from_basis<double>(Bs[c * n + row]) * ylds[c];
-                        S.x[row] += a;
-                    }
-                }
+            for (int64_t row = r0 + tid; row < r1; row += BLOCK) {
+                double a = 0.0;
+                for (int c = 0; c < de; ++c) a += from_basis<double>(Bs[c * n + row]) * ylds[c];
+                S.x[row] += a;
             }
-            __syncthreads();  // x complete before the residual gathers it
+            gsync();  // x complete before the residual gathers it
+            if (failed) {
+                decide(4);
+                continue;
+            }
         }
 
         // ---- |b| on the first cycle ---------------------------------------
         double nf;
         if (cycle == 0) {
             double t = 0.0;
-            for (int64_t row = tid; row < n; row += BLOCK) t += S.b[row] * S.b[row];
+            for (int64_t row = r0 + tid; row < r1; row += BLOCK) t += S.b[row] * S.b[row];
             const double v1[1] = {t};
             block_sum<1>(v1, 1, red_tmp, red_out);
+            group_sum(1, nullptr);
+            if (failed) {
+                decide(4);
+                continue;
+            }
             nf = sqrt(red_out[0]);
-            if (tid == 0) st->nf = nf;
+            if (lead && tid == 0) st->nf = nf;
             if (!(nf < INFINITY)) {
-                if (tid == 0) st->status = 3;
+                decide(3);
                 continue;
             }
             if (nf == 0.0) {
-                for (int64_t row = tid; row < n; row += BLOCK) S.x[row] = 0.0;
-                if (tid == 0) {
-                    st->rho = 0.0;
-                    st->status = 1;
-                }
+                for (int64_t row = r0 + tid; row < r1; row += BLOCK) S.x[row] = 0.0;
+                if (lead && tid == 0) st->rho = 0.0;
+                decide(1);
                 continue;
             }
         } else {
@@ -125,14 +205,15 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
         // ---- residual, sketch lists, g = S r -------------------------------
         for (int e = tid; e < s; e += BLOCK) acc[e] = 0.0;
         double rr = 0.0;
-        for (int ch = 0; ch < nch; ++ch) {
+        for (int c = 0; c < nch; ++c) {
+            const int ch = ch0 + c;
             const int64_t base = static_cast<int64_t>(ch) * CH + tid;
             double rv[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + r * BLOCK;
                 rv[r] = 0.0;
-                if (row < n) {
+                if (row < r1) {
                     double ax = 0.0;
                     const int q1 = S.rp[row + 1];
                     for (int q = S.rp[row]; q < q1; ++q) ax += S.val[q] * S.x[S.ci[q]];
@@ -143,11 +224,11 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
             }
             if (build) {
                 __syncthreads();  // the previous chunk's lists and vals are consumed
-                sketch_lists_build<R, BLOCK>(p.seed, static_cast<uint32_t>(cycle), base, n, s, zeta,
+                sketch_lists_build<R, BLOCK>(p.seed, static_cast<uint32_t>(cycle), base, r1, s, zeta,
                                              reinterpret_cast<uint16_t*>(vals), lstart, lcount, lists);
-                const int cnt = lstart[s];
+                const int cntl = lstart[s];
                 for (int e = tid; e <= s; e += BLOCK) S.lstart[static_cast<int64_t>(ch) * (s + 1) + e] = lstart[e];
-                for (int q = tid; q < cnt; q += BLOCK) S.lists[static_cast<int64_t>(ch) * lstride + q] = lists[q];
+                for (int q = tid; q < cntl; q += BLOCK) S.lists[static_cast<int64_t>(ch) * lstride + q] = lists[q];
 #pragma unroll
                 for (int r = 0; r < R; ++r) vals[r * BLOCK + tid] = rv[r];
                 __syncthreads();
@@ -159,31 +240,39 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
             const double v1[1] = {rr};
             block_sum<1>(v1, 1, red_tmp, red_out);
         }
+        group_sum(1, build ? S.g : nullptr);
+        if (failed) {
+            decide(4);
+            continue;
+        }
         const double beta = sqrt(red_out[0]);
         const double rho = beta / nf;
-        if (tid == 0) {
+        if (lead && tid == 0) {
             st->beta = beta;
             st->rho = rho;
         }
         if (!(rho < INFINITY)) {
-            if (tid == 0) st->status = 3;
+            decide(3);
             continue;
         }
         if (rho <= p.tol) {
-            if (tid == 0) st->status = 1;
+            decide(1);
             continue;
         }
         if (!build) {
-            if (tid == 0) st->status = 2;
+            decide(2);
             continue;
         }
-        if (tid == 0) atomicAdd(p.active, 1);
-        for (int e = tid; e < s; e += BLOCK) S.g[e] = acc[e] * scale;
+        if (lead && tid == 0) atomicAdd(p.active, 1);
 
         // ---- b_1 = r / |r| ------------------------------------------------
-        for (int64_t row = tid; row < n; row += BLOCK)
+        for (int64_t row = r0 + tid; row < r1; row += BLOCK)
             Bs[row] = to_basis<TS>(static_cast<TC>(S.r[row] / beta));
-        __syncthreads();
+        gsync();
+        if (failed) {
+            decide(4);
+            continue;
+        }
 
         // ---- basis steps ---------------------------------------------------
         int dc = d;
@@ -195,17 +284,18 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
 
             // pass 1: m = A b_j, <m,m>, W^T m, S m
             for (int e = tid; e < s; e += BLOCK) acc[e] = 0.0;
-            double dm[kBRed];
+            double dm[kBatchRed];
 #pragma unroll
-            for (int q = 0; q < kBRed; ++q) dm[q] = 0.0;
-            for (int ch = 0; ch < nch; ++ch) {
+            for (int q = 0; q < kBatchRed; ++q) dm[q] = 0.0;
+            for (int c = 0; c < nch; ++c) {
+                const int ch = ch0 + c;
                 const int64_t base = static_cast<int64_t>(ch) * CH + tid;
                 TC mv[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int64_t row = base + r * BLOCK;
                     TC am = TC(0);
-                    if (row < n) {
+                    if (row < r1) {
                         const int q1 = S.rp[row + 1];
                         for (int q = S.rp[row]; q < q1; ++q) am += Av[q] * from_basis<TC>(bj[S.ci[q]]);
                         Ms[row] = am;
@@ -219,27 +309,28 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                 __syncthreads();  // the previous chunk's lists and vals are consumed
                 const int64_t lo = static_cast<int64_t>(ch) * (s + 1);
                 for (int e = tid; e <= s; e += BLOCK) lstart[e] = S.lstart[lo + e];
-                const int cnt = S.lstart[lo + s];
-                for (int q = tid; q < cnt; q += BLOCK) lists[q] = S.lists[static_cast<int64_t>(ch) * lstride + q];
+                const int cntl = S.lstart[lo + s];
+                for (int q = tid; q < cntl; q += BLOCK) lists[q] = S.lists[static_cast<int64_t>(ch) * lstride + q];
 #pragma unroll
                 for (int r = 0; r < R; ++r) vals[r * BLOCK + tid] = static_cast<double>(mv[r]);
                 __syncthreads();
                 sketch_lists_reduce<BLOCK>(0, 1, 0, s, vals, CH, lstart, lists, sk_tmp,
                                            [&](int, int row, double a) { acc[row] += a; });
             }
-            block_sum<kBRed>(dm, kw + 1, red_tmp, red_out);
+            block_sum<kBatchRed>(dm, kw + 1, red_tmp, red_out);
+            group_sum(kw + 1, S.SAB + static_cast<int64_t>(j) * s);
+            if (failed) break;
             const double mm = red_out[0];
             double h[kBatchMaxK];
 #pragma unroll
             for (int a = 0; a < kBatchMaxK; ++a) h[a] = (a < kw) ? red_out[1 + a] : 0.0;
-            for (int e = tid; e < s; e += BLOCK) S.SAB[static_cast<int64_t>(j) * s + e] = acc[e] * scale;
             if (j == d - 1) break;
 
             // pass 2: w = m - W h, <w,w>, W^T w
-            double dw[kBRed];
+            double dw[kBatchRed];
 #pragma unroll
-            for (int q = 0; q < kBRed; ++q) dw[q] = 0.0;
-            for (int64_t row = tid; row < n; row += BLOCK) {
+            for (int q = 0; q < kBatchRed; ++q) dw[q] = 0.0;
+            for (int64_t row = r0 + tid; row < r1; row += BLOCK) {
                 TC wv = Ms[row];
 #pragma unroll
                 for (int a = 0; a < kBatchMaxK; ++a)
@@ -250,7 +341,9 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                 for (int a = 0; a < kBatchMaxK; ++a)
                     if (a < kw) dw[1 + a] += static_cast<double>(Wv(a, row) * wv);
             }
-            block_sum<kBRed>(dw, kw + 1, red_tmp, red_out);
+            block_sum<kBatchRed>(dw, kw + 1, red_tmp, red_out);
+            group_sum(kw + 1, nullptr);
+            if (failed) break;
             double h2[kBatchMaxK];
             double h2sq = 0.0;
 #pragma unroll
@@ -268,16 +361,21 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
 
             // pass 3: b_{j+1} = (w - W h2) / nu
             TS* bn = Bs + static_cast<int64_t>(j + 1) * n;
-            for (int64_t row = tid; row < n; row += BLOCK) {
+            for (int64_t row = r0 + tid; row < r1; row += BLOCK) {
                 TC bv = Ws[row];
 #pragma unroll
                 for (int a = 0; a < kBatchMaxK; ++a)
                     if (a < kw) bv -= static_cast<TC>(h2[a]) * Wv(a, row);
                 bn[row] = to_basis<TS>(bv / nu);
             }
-            __syncthreads();  // b_{j+1} complete before the next step gathers it
+            gsync();  // b_{j+1} complete before the next step gathers it
+            if (failed) break;
         }
-        if (tid == 0) {
+        if (failed) {
+            decide(4);
+            continue;
+        }
+        if (lead && tid == 0) {
             st->dc = dc;
             st->flags |= flags;
             st->cycles += 1;
@@ -288,9 +386,15 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
 }
 
 // ctr: [0] cycle, [1] queue position, [2] systems active this cycle, [3] the
-// count of the cycle that just ended (what the host reads)
-__global__ void batch_advance_kernel(int* ctr) {
-    if (threadIdx.x == 0) {
+// count of the cycle that just ended (what the host reads).  Each system's
+// status takes the value decided during the cycle; group counters restart.
+__global__ void batch_advance_kernel(int* ctr, BatchState* st, unsigned* gcnt, int nsys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nsys) {
+        if (st[i].status == 0) st[i].status = st[i].next;
+        gcnt[i] = 0u;
+    }
+    if (i == 0) {
         ctr[3] = ctr[2];
         ctr[2] = 0;
         ctr[1] = 0;
@@ -298,9 +402,12 @@ __global__ void batch_advance_kernel(int* ctr) {
     }
 }
 
-__global__ void batch_reset_kernel(BatchState* st, int nsys, int* ctr) {
+__global__ void batch_reset_kernel(BatchState* st, unsigned* gcnt, int nsys, int* ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nsys) st[i] = BatchState{};
+    if (i < nsys) {
+        st[i] = BatchState{};
+        gcnt[i] = 0u;
+    }
     if (i < 4) ctr[i] = 0;
 }
 
@@ -330,8 +437,8 @@ hipError_t batch_configure(int block, int R, int d, int s, int zeta, int precisi
     KernelFn fn = pick_kernel(block, R, precision);
     if (!fn) return hipErrorInvalidValue;
     const int CH = block * R;
-    const size_t lds = sizeof(double) * static_cast<size_t>(batch_vals_doubles(CH, zeta) + (block / kWave) * kBRed +
-                                                            kBRed + s + s * kSketchParts + d) +
+    const size_t lds = sizeof(double) * static_cast<size_t>(batch_vals_doubles(CH, zeta) + (block / kWave) * kBatchRed +
+                                                            kBatchRed + s + s * kSketchParts + d) +
                        sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * CH;
     int device = 0;
     hipError_t err = hipGetDevice(&device);
@@ -363,14 +470,15 @@ hipError_t batch_launch(const BatchLaunch& L, const BatchParams& p, hipStream_t 
     return hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, L.lds, stream);
 }
 
-hipError_t launch_batch_advance(int* ctr, hipStream_t stream) {
-    batch_advance_kernel<<<1, 64, 0, stream>>>(ctr);
+hipError_t launch_batch_advance(int* ctr, BatchState* st, unsigned* gcnt, int nsys, hipStream_t stream) {
+    const int n = nsys > 1 ? nsys : 1;
+    batch_advance_kernel<<<(n + 255) / 256, 256, 0, stream>>>(ctr, st, gcnt, nsys);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_reset(BatchState* st, int nsys, int* ctr, hipStream_t stream) {
+hipError_t launch_batch_reset(BatchState* st, unsigned* gcnt, int nsys, int* ctr, hipStream_t stream) {
     const int n = nsys > 4 ? nsys : 4;
-    batch_reset_kernel<<<(n + 255) / 256, 256, 0, stream>>>(st, nsys, ctr);
+    batch_reset_kernel<<<(n + 255) / 256, 256, 0, stream>>>(st, gcnt, nsys, ctr);
     return hipGetLastError();
 }
 

@@ -87,8 +87,14 @@ struct Workspace {
     size_t bt_sys_cap = 0;
     BatchState* bt_st = nullptr;
     size_t bt_st_cap = 0;
-    int* bt_order = nullptr;
-    size_t bt_order_cap = 0;
+    BatchTask* bt_task = nullptr;
+    size_t bt_task_cap = 0;
+    double* bt_slots = nullptr;
+    size_t bt_slots_cap = 0;
+    int64_t* bt_slot_off = nullptr;
+    size_t bt_slot_off_cap = 0;
+    unsigned* bt_gcnt = nullptr;
+    size_t bt_gcnt_cap = 0;
     unsigned char* bt_arena = nullptr;
     size_t bt_arena_cap = 0;
     hipStream_t capture_stream = nullptr;
@@ -564,6 +570,8 @@ constexpr int kBatchMinChunk = 1024;  // smallest block * R among the candidates
 constexpr int kBatchMaxChunk = 4096;  // largest
 constexpr size_t kArenaAlign = 256;
 constexpr int64_t kBatchTuneRows = int64_t(1) << 20;  // smaller batches use 512 x 4
+constexpr int64_t kBatchPartRows = 16384;              // rows per part of a large system
+constexpr int kBatchMaxParts = 64;
 
 using BatchKey = std::tuple<int, int, int, int, int, int, int>;
 std::map<BatchKey, BatchCand> g_batch_tuned;
@@ -619,7 +627,6 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
     SG_TRY(ensure(ws.bt_arena, ws.bt_arena_cap, off[nsys]));
     SG_TRY(ensure(ws.bt_sys, ws.bt_sys_cap, static_cast<size_t>(nsys)));
     SG_TRY(ensure(ws.bt_st, ws.bt_st_cap, static_cast<size_t>(nsys)));
-    SG_TRY(ensure(ws.bt_order, ws.bt_order_cap, static_cast<size_t>(nsys)));
 
     std::vector<BatchSys> desc(nsys);
     int64_t total_rows = 0;
@@ -661,23 +668,59 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
         }
         total_rows += y.A.n;
     }
-    // largest systems first
+    // largest systems first; each system split into parts of whole chunks
     std::vector<int> order(nsys);
     for (int i = 0; i < nsys; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return systems[a].A.n > systems[b].A.n; });
+    std::vector<int64_t> slot_off(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i) {
+        const int64_t pm = std::min<int64_t>(kBatchMaxParts, (systems[i].A.n + kBatchPartRows - 1) / kBatchPartRows);
+        slot_off[i + 1] = slot_off[i] + (2 * kBatchRed + s) * std::max<int64_t>(pm, 1);
+    }
+    SG_TRY(ensure(ws.bt_slots, ws.bt_slots_cap, static_cast<size_t>(slot_off[nsys])));
+    SG_TRY(ensure(ws.bt_slot_off, ws.bt_slot_off_cap, static_cast<size_t>(nsys)));
+    SG_TRY(ensure(ws.bt_gcnt, ws.bt_gcnt_cap, static_cast<size_t>(nsys)));
+    SG_TRY(ensure(ws.bt_task, ws.bt_task_cap, static_cast<size_t>(nsys) * kBatchMaxParts));
     SG_TRY(hipMemcpyAsync(ws.bt_sys, desc.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
-    SG_TRY(hipMemcpyAsync(ws.bt_order, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
+    SG_TRY(hipMemcpyAsync(ws.bt_slot_off, slot_off.data(), sizeof(int64_t) * nsys, hipMemcpyHostToDevice, st));
+    std::vector<BatchTask> tasks;
+    // parts for chunks of CH rows on a grid of G workgroups (a system never has
+    // more parts than the grid has workgroups)
+    auto make_tasks = [&](int CH, int G) {
+        tasks.clear();
+        for (int i : order) {
+            const int64_t n = systems[i].A.n;
+            const int64_t nchs = (n + CH - 1) / CH;
+            int64_t P = (n + kBatchPartRows - 1) / kBatchPartRows;
+            P = std::max<int64_t>(1, std::min<int64_t>({P, nchs, static_cast<int64_t>(kBatchMaxParts),
+                                                        static_cast<int64_t>(G)}));
+            for (int64_t q = 0; q < P; ++q) {
+                BatchTask t{};
+                t.sys = i;
+                t.part = static_cast<int>(q);
+                t.nparts = static_cast<int>(P);
+                t.r0 = (q * nchs / P) * CH;
+                t.r1 = std::min<int64_t>(n, ((q + 1) * nchs / P) * CH);
+                tasks.push_back(t);
+            }
+        }
+        return hipMemcpyAsync(ws.bt_task, tasks.data(), sizeof(BatchTask) * tasks.size(), hipMemcpyHostToDevice, st);
+    };
 
     int* ctr = ws.sc->batch_ctr;
     BatchParams bp{};
-    bp.nsys = nsys;
+    bp.task = ws.bt_task;
     bp.sys = ws.bt_sys;
     bp.st = ws.bt_st;
-    bp.order = ws.bt_order;
+    bp.slots = ws.bt_slots;
+    bp.slot_off = ws.bt_slot_off;
+    bp.gcnt = ws.bt_gcnt;
     bp.queue = ctr + 1;
     bp.active = ctr + 2;
     bp.cycle = ctr;
+    bp.abort = &ws.sc->abort;
+    bp.spin_limit = kSpinLimitTicks;
     bp.d = d;
     bp.k = k;
     bp.s = s;
@@ -685,6 +728,7 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
     bp.restarts = restarts;
     bp.seed = seed;
     bp.tol = tol;
+    SG_TRY(hipMemsetAsync(&ws.sc->abort, 0, sizeof(int), st));
 
     // workgroup shape: given, the default for small batches, remembered, or
     // timed on the first cycle
@@ -708,7 +752,9 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
             for (const BatchCand& c : kBatchCands) {
                 BatchLaunch T{};
                 if (batch_configure(c.block, c.R, d, s, zeta, prec, &T) != hipSuccess) continue;
-                SG_TRY(launch_batch_reset(ws.bt_st, nsys, ctr, st));
+                SG_TRY(make_tasks(batch_chunk(T), T.grid));
+                bp.ntask = static_cast<int>(tasks.size());
+                SG_TRY(launch_batch_reset(ws.bt_st, ws.bt_gcnt, nsys, ctr, st));
                 SG_TRY(hipEventRecord(e0, st));
                 SG_TRY(batch_launch(T, bp, st));
                 SG_TRY(hipEventRecord(e1, st));
@@ -727,8 +773,10 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
             SG_TRY(batch_configure(win.block, win.R, d, s, zeta, prec, &L));
         }
     }
+    SG_TRY(make_tasks(batch_chunk(L), L.grid));
+    bp.ntask = static_cast<int>(tasks.size());
 
-    SG_TRY(launch_batch_reset(ws.bt_st, nsys, ctr, st));
+    SG_TRY(launch_batch_reset(ws.bt_st, ws.bt_gcnt, nsys, ctr, st));
     const bool eager = opts && opts->batch_eager;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -738,7 +786,7 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
         SG_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t e = batch_launch(L, bp, cs);
         if (e == hipSuccess) e = launch_lsq_batched(nsys, s, ws.bt_sys, ws.bt_st, kappa_max, cs);
-        if (e == hipSuccess) e = launch_batch_advance(ctr, cs);
+        if (e == hipSuccess) e = launch_batch_advance(ctr, ws.bt_st, ws.bt_gcnt, nsys, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -753,7 +801,7 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
         if (eager) {
             e = batch_launch(L, bp, st);
             if (e == hipSuccess) e = launch_lsq_batched(nsys, s, ws.bt_sys, ws.bt_st, kappa_max, st);
-            if (e == hipSuccess) e = launch_batch_advance(ctr, st);
+            if (e == hipSuccess) e = launch_batch_advance(ctr, ws.bt_st, ws.bt_gcnt, nsys, st);
         } else {
             e = hipGraphLaunch(exec, st);
         }
@@ -766,7 +814,7 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
             status = rc;
             break;
         }
-        if (ws.host_sc->batch_ctr[3] == 0) break;
+        if (ws.host_sc->batch_ctr[3] == 0 || ws.host_sc->abort) break;
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -775,6 +823,7 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
     std::vector<BatchState> hs(nsys);
     SG_TRY(hipMemcpyAsync(hs.data(), ws.bt_st, sizeof(BatchState) * nsys, hipMemcpyDeviceToHost, st));
     SG_TRY(hipStreamSynchronize(st));
+    if (ws.host_sc->abort) return SGMRES_ETIMEOUT;
     int all = SGMRES_OK;
     for (int i = 0; i < nsys; ++i) {
         const BatchState& t = hs[i];
@@ -1005,7 +1054,7 @@ void sgmres_release_workspace(void) {
         (void)hipSetDevice(kv.first);
         Workspace& w = kv.second;
         if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
-        void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_order, w.bt_arena,
+        void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_task, w.bt_slots, w.bt_slot_off, w.bt_gcnt, w.bt_arena,
                         w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
                         w.part_vec, w.part_nrm, w.colnorm, w.valf, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch};

@@ -133,29 +133,46 @@ struct BatchSys {
 
 // Per-system state, kept across the cycles of one batched solve.
 struct BatchState {
-    double nf;     // |b|
-    double beta;   // |r| of the last residual
-    double rho;    // |r| / |b|
-    double rest;   // least-squares residual estimate   (rest, kappa adjacent:
-    double kappa;  // diagonal ratio of T                 the LSQ writes both)
-    int d_eff;     // columns used by the least squares   (d_eff, lsq_flags
-    int lsq_flags; //                                       adjacent likewise)
-    int status;    // 0 active, 1 converged, 2 out of restarts, 3 non-finite
-    int dc;        // columns built in the last cycle
-    int flags;     // OR of breakdown flags
-    int cycles;    // basis cycles run
-    int steps;     // basis columns built, summed
+    double nf;      // |b|
+    double beta;    // |r| of the last residual
+    double rho;     // |r| / |b|
+    double rest;    // least-squares residual estimate   (rest, kappa adjacent:
+    double kappa;   // diagonal ratio of T                 the LSQ writes both)
+    int d_eff;      // columns used by the least squares   (d_eff, lsq_flags
+    int lsq_flags;  //                                       adjacent likewise)
+    int status;     // as of the start of the cycle: 0 active, 1 converged,
+                    // 2 out of restarts, 3 non-finite, 4 wait limit hit
+    int next;       // status decided during the cycle (copied at its end)
+    int dc;         // columns built in the last cycle
+    int flags;      // OR of breakdown flags
+    int cycles;     // basis cycles run
+    int steps;      // basis columns built, summed
+};
+
+// A unit of work: rows [r0, r1) (whole chunks) of one system; the nparts parts
+// of a system are consecutive in the task list and synchronise with each
+// other through the system's counter.
+struct BatchTask {
+    int sys;
+    int part;
+    int nparts;
     int pad;
+    int64_t r0, r1;
 };
 
 struct BatchParams {
-    int nsys;
+    int ntask;
+    const BatchTask* task;
     const BatchSys* sys;
     BatchState* st;
-    const int* order;   // systems in processing order (largest first)
-    int* queue;         // next position in `order` (zero at launch)
-    int* active;        // systems that built a basis this cycle
-    const int* cycle;   // device cycle counter (the counter array of launch_batch_advance)
+    double* slots;       // per system: 2 x nparts x kBatchRed reduction slots, then nparts x s sketch slots
+    const int64_t* slot_off;  // per system: offset of its slots (doubles)
+    unsigned* gcnt;      // per system: arrivals at the group barrier this cycle
+    int* queue;          // next task (zero at launch)
+    int* active;         // systems that built a basis this cycle
+    const int* cycle;    // device cycle counter (the counter array of launch_batch_advance)
+    int* abort;          // raised when a group wait exceeds its limit
+    uint64_t spin_limit;
     int d, k, s, zeta;
     int restarts;
     uint64_t seed;
@@ -168,15 +185,17 @@ struct BatchLaunch {
     size_t lds;
 };
 constexpr int kBatchMaxK = 4;
+constexpr int kBatchRed = kBatchMaxK + 1;  // values per group reduction (window dots + a norm)
 // chunk rows a kernel instance handles at a time
 inline int batch_chunk(const BatchLaunch& L) { return L.block * L.R; }
 hipError_t batch_configure(int block, int R, int d, int s, int zeta, int precision, BatchLaunch* out);
 hipError_t batch_launch(const BatchLaunch& L, const BatchParams& p, hipStream_t stream);
 // ctr (4 ints): [0] cycle, [1] queue position, [2] active systems, [3] active
-// systems of the cycle that just ended.  advance: end of a cycle; reset: start
-// of a solve (also clears every BatchState).
-hipError_t launch_batch_advance(int* ctr, hipStream_t stream);
-hipError_t launch_batch_reset(BatchState* st, int nsys, int* ctr, hipStream_t stream);
+// systems of the cycle that just ended.  advance: end of a cycle (also moves
+// each system's decided status into place and clears the group counters);
+// reset: start of a solve (clears every BatchState and counter).
+hipError_t launch_batch_advance(int* ctr, BatchState* st, unsigned* gcnt, int nsys, hipStream_t stream);
+hipError_t launch_batch_reset(BatchState* st, unsigned* gcnt, int nsys, int* ctr, hipStream_t stream);
 hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
                               hipStream_t stream);
 

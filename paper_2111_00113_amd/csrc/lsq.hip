@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kLsqBlock) void lsq_batched_kernel(int s, const Bat
                                                                 BatchState* __restrict__ st, double kappa_max) {
     extern __shared__ double v[];
     BatchState* t = st + blockIdx.x;
-    if (t->status != 0) return;
+    if (t->status != 0 || t->next != 0) return;  // only systems that built a basis this cycle
     const BatchSys& S = sys[blockIdx.x];
     lsq_body(s, t->dc, S.SAB, S.g, kappa_max, S.y, &t->rest, &t->d_eff, v);
 }

@@ -84,6 +84,28 @@ def test_batched_restarted_parity(sg, orc):
         assert np.linalg.norm(x - x_o) <= 1e-8 * np.linalg.norm(x_o)
 
 
+def test_batched_multipart_parity(sg, orc):
+    # systems above 16384 rows are split over several workgroups that
+    # synchronise per step; results must match the oracle as for one part
+    d, k, s = 40, 2, 90
+    mats = [synth.random_dominant(70001, offdiag=6, seed=[6, 0]), synth.convection_diffusion(200, (50.0, 20.0)),
+            synth.random_dominant(17000, offdiag=6, seed=[6, 2]), synth.random_dominant(3000, offdiag=6, seed=[6, 3])]
+    batch = [(A, synth.rhs(A.n, [1, i])) for i, A in enumerate(mats)]
+    for tol, restarts in ((0.0, 0), (1e-10, 200)):
+        rc, res, xs = _run(sg, batch, d, k, s, tol, restarts)
+        for (A, b), r, x in zip(batch, res, xs):
+            rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=tol, restarts=restarts)
+            print(f"n={A.n} tol={tol}: cycles {r['cycles']} (oracle {info_o['cycles']}), relres {r['relres']:.3e} "
+                  f"(oracle {info_o['relres']:.3e})", flush=True)
+            assert abs(r["cycles"] - info_o["cycles"]) <= 1
+            if tol == 0.0:
+                assert np.linalg.norm(x - x_o) <= 1e-8 * np.linalg.norm(x_o)
+                assert abs(r["relres"] - info_o["relres"]) <= 1e-10
+            else:
+                _, nrm = orc.residual(A, b, x)
+                assert nrm / np.linalg.norm(b) <= 1e-10
+
+
 def test_batched_graph_replays_match_eager(sg, orc):
     # the captured cycle graph, replayed once per cycle, against launching the
     # same kernels directly: bitwise identical after several cycles
