@@ -373,6 +373,36 @@ int prepare_cheb(Workspace& ws, int64_t n, int d, int s, int zeta, int block, in
     return SGMRES_OK;
 }
 
+int batch_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
+                       int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, hipStream_t st,
+                       BatchState* st_out);
+
+// A system too large for the resident basis kernel (truncated Arnoldi, k <= 4):
+// the part-split kernel of the batched solve, as a batch of one.
+int solve_large(const SolveArgs& a, sgmres_info_t* info) {
+    sgmres_system_t sys{a.A, a.b, a.x};
+    sgmres_options_t o{};
+    o.zeta = a.zeta;
+    o.kappa_max = a.kappa_max;
+    o.precision = a.precision;
+    sgmres_batch_result_t r{};
+    BatchState t{};
+    const int rc = batch_solve_locked(1, &sys, a.d, a.k, a.s, a.seed, a.tol, a.restarts, &o, &r, a.stream, &t);
+    if (rc < 0) return rc;
+    if (info) {
+        sgmres_info_t rep{};
+        rep.cycles = r.cycles;
+        rep.steps = r.steps;
+        rep.d_eff_last = t.d_eff;
+        rep.flags = r.flags;
+        rep.relres = r.relres;
+        rep.rest_est = t.nf > 0 ? t.rest / t.nf : 0.0;
+        rep.kappa_est = t.kappa;
+        *info = rep;
+    }
+    return r.status;
+}
+
 int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     std::lock_guard<std::mutex> lock(g_mutex);
     Workspace* wsp = nullptr;
@@ -383,6 +413,18 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     const int kk = (a.k > a.d - 1) ? (a.d > 1 ? a.d - 1 : 1) : a.k;
     hipStream_t st = a.stream;
 
+    const bool cheb = a.basis == SGMRES_BASIS_CHEBYSHEV;
+    ChebCoef cf{};
+    if (cheb && !cheb_coefficients(a.cheb_c, a.cheb_dx, a.cheb_dy, &cf)) return SGMRES_EINVAL;
+    ArnoldiLaunch L{};
+    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L, a.precision)
+              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0, a.precision);
+    if (rc == SGMRES_EINVAL && !cheb && kk <= kBatchMaxK && !a.block && !a.rows_per_thread) {
+        SolveArgs b = a;
+        b.k = kk;
+        return solve_large(b, info);
+    }
+    if (rc) return rc;
     SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
     // B in the basis storage type (allocated in doubles)
     SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(n) * a.d * basis_elem_bytes(a.precision) + 7) / 8));
@@ -392,14 +434,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     SG_TRY(ensure(ws.g, ws.g_cap, static_cast<size_t>(a.s)));
     SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(a.d)));
     SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
-    const bool cheb = a.basis == SGMRES_BASIS_CHEBYSHEV;
-    ChebCoef cf{};
-    if (cheb && !cheb_coefficients(a.cheb_c, a.cheb_dx, a.cheb_dy, &cf)) return SGMRES_EINVAL;
     if (cheb) SG_TRY(ensure(ws.colnorm, ws.colnorm_cap, static_cast<size_t>(a.d)));
-    ArnoldiLaunch L{};
-    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L, a.precision)
-              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0, a.precision);
-    if (rc) return rc;
     rc = check_csr(ws, a.A, st);
     if (rc) return rc;
     // the basis cycles of the mixed-precision modes read an FP32 copy of A's values
@@ -571,15 +606,18 @@ constexpr int kBatchMaxChunk = 4096;  // largest
 constexpr size_t kArenaAlign = 256;
 constexpr int64_t kBatchTuneRows = int64_t(1) << 20;  // smaller batches use 512 x 4
 constexpr int64_t kBatchPartRows = 16384;              // rows per part of a large system
-constexpr int kBatchMaxParts = 64;
+constexpr int kBatchMaxParts = 256;
 
 using BatchKey = std::tuple<int, int, int, int, int, int, int>;
 std::map<BatchKey, BatchCand> g_batch_tuned;
 
 size_t align_up(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
 
-int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
-                     int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, hipStream_t st) {
+// Caller holds g_mutex.  st_out (nullable, nsys entries) receives the final
+// per-system states.
+int batch_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
+                       int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, hipStream_t st,
+                       BatchState* st_out = nullptr) {
     const int zeta = (opts && opts->zeta) ? opts->zeta : 8;
     const double kappa_max = (opts && opts->kappa_max > 0) ? opts->kappa_max : 1e14;
     const int prec = opts ? opts->precision : SGMRES_PREC_FP64;
@@ -591,7 +629,6 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
     }
     if (nsys == 0) return SGMRES_OK;
 
-    std::lock_guard<std::mutex> lock(g_mutex);
     Workspace* wsp = nullptr;
     int rc = workspace(&wsp);
     if (rc) return rc;
@@ -824,6 +861,7 @@ int batch_solve_impl(int nsys, const sgmres_system_t* systems, int d, int k, int
     SG_TRY(hipMemcpyAsync(hs.data(), ws.bt_st, sizeof(BatchState) * nsys, hipMemcpyDeviceToHost, st));
     SG_TRY(hipStreamSynchronize(st));
     if (ws.host_sc->abort) return SGMRES_ETIMEOUT;
+    if (st_out) std::copy(hs.begin(), hs.end(), st_out);
     int all = SGMRES_OK;
     for (int i = 0; i < nsys; ++i) {
         const BatchState& t = hs[i];
@@ -1068,8 +1106,9 @@ void sgmres_release_workspace(void) {
 
 int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
                          int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, void* stream) {
-    return batch_solve_impl(nsys, systems, d, k, s, seed, tol, restarts, opts, results,
-                            static_cast<hipStream_t>(stream));
+    std::lock_guard<std::mutex> lock(g_mutex);
+    return batch_solve_locked(nsys, systems, d, k, s, seed, tol, restarts, opts, results,
+                              static_cast<hipStream_t>(stream));
 }
 
 const char* sgmres_version(void) { return "sgmres-gfx950 0.1.0"; }
