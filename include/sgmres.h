@@ -117,6 +117,9 @@ typedef struct {
     int32_t precision;  /* SGMRES_PREC_* (0 = FP64) */
     int32_t batch_eager; /* sgmres_solve_batched: launch each cycle's kernels directly
                             instead of replaying the captured hipGraph */
+    int32_t halo_off;   /* truncated Arnoldi: nonzero keeps three grid barriers per step;
+                           0 uses two when at most a quarter of the nonzeros reach outside
+                           their row's block of the basis kernel (results are bit-identical) */
 } sgmres_options_t;
 
 /*

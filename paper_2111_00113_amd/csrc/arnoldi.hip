@@ -11,8 +11,15 @@ namespace {
 using KernelFn = void (*)(ArnoldiParams);
 
 // FP64 solve instances live here; the others in their own translation units
-KernelFn pick_kernel(int block, int R, int KW, bool sketch_basis, int precision) {
+KernelFn pick_kernel(int block, int R, int KW, bool sketch_basis, int precision, bool halo) {
     const void* f = nullptr;
+    if (halo) {
+        if (sketch_basis) return nullptr;
+        if (precision == SGMRES_PREC_FP64) f = arnoldi_pick_halo_f64(block, R, KW);
+        else if (precision == SGMRES_PREC_FP32) f = arnoldi_pick_halo_f32(block, R, KW);
+        else if (precision == SGMRES_PREC_BF16_BASIS) f = arnoldi_pick_halo_bf16(block, R, KW);
+        return reinterpret_cast<KernelFn>(const_cast<void*>(f));
+    }
     if (precision == SGMRES_PREC_FP32) f = sketch_basis ? nullptr : arnoldi_pick_f32(block, R, KW);
     else if (precision == SGMRES_PREC_BF16_BASIS) f = sketch_basis ? nullptr : arnoldi_pick_bf16(block, R, KW);
     else if (precision == SGMRES_PREC_FP64)
@@ -25,7 +32,7 @@ KernelFn pick_kernel(int block, int R, int KW, bool sketch_basis, int precision)
 size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta) {
     const int nw = block / kWave;
     const int RB = R * block;
-    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw * kRedSlots + kRedSlots + 2 * k + 2 +
+    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw * kRedSlots + kRedSlots + 2 * k + 3 +
                                                 2 * s * kSketchParts) +
            sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
 }
@@ -59,7 +66,7 @@ hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {
                 if (shape.force_global_window) KW = 0;
                 const size_t lds = arnoldi_lds_bytes(block, R, shape.s, shape.k, shape.zeta);
                 if (lds > static_cast<size_t>(lds_max)) continue;
-                KernelFn fn = pick_kernel(block, R, KW, shape.sketch_basis != 0, shape.precision);
+                KernelFn fn = pick_kernel(block, R, KW, shape.sketch_basis != 0, shape.precision, shape.halo != 0);
                 if (!fn) continue;
                 err = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));

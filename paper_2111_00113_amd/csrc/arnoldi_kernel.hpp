@@ -41,10 +41,22 @@ namespace arnoldi_detail {
 constexpr int kChunk = 8;     // reduction values per block_sum pass (global window)
 constexpr int kRedSlots = 9;  // max values per block_sum: window of 8 plus a norm
 
+// x - h * v as one fused multiply-add, the same instruction wherever the new
+// basis column is formed (its owner, and blocks recomputing it for their halo)
+__device__ __forceinline__ double gs_sub(double x, double h, double v) { return __builtin_fma(-h, v, x); }
+__device__ __forceinline__ float gs_sub(float x, float h, float v) { return __builtin_fmaf(-h, v, x); }
+
 // SKB: also form S b_j (SB); the solve needs only S m_j.  TC: per-row
 // arithmetic type (A's values are read in TC); TS: storage type of B.  Sums of
 // block partials, H and the sketch sums are FP64 in every variant.
-template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS>
+// HALO: two grid barriers per step instead of three.  The new column b_{j+1}
+// is not published by a third barrier: each block keeps its own rows of it in
+// LDS and recomputes the entries its SpMV needs from other blocks' rows as
+// (w - W h2) / nu from w (written to HBM before the second barrier) and the
+// window columns, with the owner's operations in the owner's order, so the
+// values are the owner's bits.  Chosen when few nonzeros reach outside their
+// block (requires SKB = false and the row-per-thread SpMV).
+template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO = false>
 __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
@@ -57,8 +69,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     double* vals = smem;
     double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
     double* red_out = red_tmp + NW * kRedSlots;
-    double* coef = red_out + kRedSlots;  // [0] <m,m>, [1..k] h ; [k+1] <w,w>, [k+2..2k+1] h2
-    double* sk_tmp = coef + 2 * p.k + 2;  // 2s x kSketchParts partial sums
+    double* coef = red_out + kRedSlots;  // [0] <m,m>, [1..k] h ; [k+1] <w,w>, [k+2..2k+1] h2 ; [2k+2] nu
+    double* sk_tmp = coef + 2 * p.k + 3;  // 2s x kSketchParts partial sums
     int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
     int* lcount = lstart + (s + 1);
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
@@ -75,6 +87,11 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     const TC* Av = static_cast<const TC*>(p.val);
     TS* Bs = static_cast<TS*>(p.B);
     constexpr double uround = BasisPrec<TC>::unit_roundoff;
+    static_assert(!HALO || !SKB, "the halo mode keeps b_{j+1} where S b_j would be staged");
+    TC* bst = reinterpret_cast<TC*>(vals);  // HALO: own rows of the current column
+    TC* wbuf = static_cast<TC*>(p.wbuf);
+    const int64_t row_lo = static_cast<int64_t>(blk) * RB;
+    const int64_t row_hi = min(n, row_lo + RB);
 
     GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
@@ -113,9 +130,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     auto block_sketch = [&](int r0, int r1, double* dst) {
         sketch_lists_apply<BLOCK>(sk_v0, sk_nv, r0, r1, vals, RB, s, lstart, lists, sk_tmp, dst, G, blk);
     };
-    // the sketch of one step is spread over the three barrier windows
-    const int sk_cut1 = s / 3;
-    const int sk_cut2 = (2 * s) / 3;
+    // the sketch of one step is spread over the barrier windows (three, or two
+    // in the halo mode)
+    const int sk_cut1 = HALO ? s / 2 : s / 3;
+    const int sk_cut2 = HALO ? s : (2 * s) / 3;
 
     // ---- init: g partial (S r), b_1 = r/|r| ----------------------------------
     const double beta = *p.beta;
@@ -140,6 +158,11 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     sketch_lists_apply<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, sk_tmp,
                               p.part_sk + static_cast<int64_t>(p.d) * slab, G, blk);  // g partials after the d step slabs
     bar.sync();  // B[:,0] and the g partials are complete
+    if constexpr (HALO) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) bst[r * BLOCK + tid] = win[0][r];
+        __syncthreads();
+    }
 
     // window entry a (0 = newest) of own row r at step j
     auto Wg = [&](int j, int a, int r) -> TC {
@@ -228,6 +251,33 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 }
                 m[r] = am;
             }
+        } else if constexpr (HALO) {
+            // own rows from LDS; other blocks' rows of b_j recomputed from w and
+            // the window of step j-1 (b_1 is in HBM, published at init)
+            const int kwp = min(j, p.k);
+            const TC nup = static_cast<TC>(coef[2 * p.k + 2]);
+            const double* h2p = coef + p.k + 2;
+            const TS* Bp = Bs + static_cast<int64_t>(j > 0 ? j - 1 : 0) * p.ldb;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                TC am = TC(0);
+                for (int q = 0; q < rlen[r]; ++q) {
+                    const int c = p.ci[rbeg[r] + q];
+                    TC bv;
+                    if (c >= row_lo && c < row_hi) {
+                        bv = bst[c - row_lo];
+                    } else if (j == 0) {
+                        bv = from_basis<TC>(bj[c]);
+                    } else {
+                        TC t = wbuf[c];
+                        for (int a = 0; a < kwp; ++a)
+                            t = gs_sub(t, static_cast<TC>(h2p[a]), from_basis<TC>(Bp[c - static_cast<int64_t>(a) * p.ldb]));
+                        bv = from_basis<TC>(to_basis<TS>(t / nup));
+                    }
+                    am += Av[rbeg[r] + q] * bv;
+                }
+                m[r] = am;
+            }
         } else {
             // one row per thread, nonzeros in order
 #pragma unroll
@@ -283,6 +333,13 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 for (int r = 0; r < R; ++r) w[r] -= h * Wg(j, a, r);
             }
         }
+        if constexpr (HALO) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+                if (row < n) wbuf[row] = w[r];
+            }
+        }
         dots_to_partials(w, j, kw, p.part_b);
         tick(3);
         bar.arrive();
@@ -307,7 +364,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             p.H[static_cast<int64_t>(j) * (p.k + 1) + tid] = hv;
         }
         if (breakdown) {
-            block_sketch(sk_cut2, s, sk_dst);
+            if constexpr (!HALO) block_sketch(sk_cut2, s, sk_dst);
             dc = j + 1;
             flags |= SGMRES_FLAG_BREAKDOWN;
             break;
@@ -322,14 +379,14 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 if (a < kw) {
                     const TC h = static_cast<TC>(c2[1 + a]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) bnew[r] -= h * win[a][r];
+                    for (int r = 0; r < R; ++r) bnew[r] = gs_sub(bnew[r], h, win[a][r]);
                 }
             }
         } else {
             for (int a = 0; a < kw; ++a) {
                 const TC h = static_cast<TC>(c2[1 + a]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) bnew[r] -= h * Wg(j, a, r);
+                for (int r = 0; r < R; ++r) bnew[r] = gs_sub(bnew[r], h, Wg(j, a, r));
             }
         }
         const TC nu_t = static_cast<TC>(nu);
@@ -349,9 +406,18 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             for (int r = 0; r < R; ++r) win[0][r] = bnew[r];
         }
         tick(5);
-        bar.arrive();
-        block_sketch(sk_cut2, s, sk_dst);  // last third
-        bar.wait();
+        if constexpr (HALO) {
+            // no third barrier: stage the own rows of b_{j+1}; keep nu for the
+            // recomputation of other blocks' rows in the next step
+#pragma unroll
+            for (int r = 0; r < R; ++r) bst[r * BLOCK + tid] = bnew[r];
+            if (tid == 0) coef[2 * p.k + 2] = nu;
+            __syncthreads();
+        } else {
+            bar.arrive();
+            block_sketch(sk_cut2, s, sk_dst);  // last third
+            bar.wait();
+        }
         tick(6);
     }
 
@@ -391,10 +457,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 
 // Kernel instance for (BLOCK, R, KW); (R, KW) = (8, 8) is never selected
 // (the register window is capped at 32 doubles per thread).
-template <bool SKB, typename TC, typename TS, int BLOCK>
+template <bool SKB, typename TC, typename TS, int BLOCK, bool HALO>
 const void* pick_rows(int R, int KW) {
 #define SG_CASE(RR, KK) \
-    if (R == RR && KW == KK) return reinterpret_cast<const void*>(arnoldi_kernel<RR, KK, BLOCK, SKB, TC, TS>);
+    if (R == RR && KW == KK) return reinterpret_cast<const void*>(arnoldi_kernel<RR, KK, BLOCK, SKB, TC, TS, HALO>);
     SG_CASE(1, 0) SG_CASE(1, 4) SG_CASE(1, 8)
     SG_CASE(2, 0) SG_CASE(2, 4) SG_CASE(2, 8)
     SG_CASE(4, 0) SG_CASE(4, 4) SG_CASE(4, 8)
@@ -403,12 +469,12 @@ const void* pick_rows(int R, int KW) {
     return nullptr;
 }
 
-template <bool SKB, typename TC, typename TS>
+template <bool SKB, typename TC, typename TS, bool HALO = false>
 const void* arnoldi_pick(int block, int R, int KW) {
     switch (block) {
-        case 256: return pick_rows<SKB, TC, TS, 256>(R, KW);
-        case 512: return pick_rows<SKB, TC, TS, 512>(R, KW);
-        case 1024: return pick_rows<SKB, TC, TS, 1024>(R, KW);
+        case 256: return pick_rows<SKB, TC, TS, 256, HALO>(R, KW);
+        case 512: return pick_rows<SKB, TC, TS, 512, HALO>(R, KW);
+        case 1024: return pick_rows<SKB, TC, TS, 1024, HALO>(R, KW);
         default: return nullptr;
     }
 }

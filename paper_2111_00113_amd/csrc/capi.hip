@@ -47,6 +47,7 @@ struct DevScalars {
     int pad1[2];
     unsigned long long phase_ticks[8];  // basis-kernel phase timers (profile)
     int batch_ctr[4];                   // batched solve: cycle, queue, active, active last cycle
+    unsigned long long offblock;        // nonzeros reaching outside their row's block
 };
 
 struct Workspace {
@@ -81,6 +82,8 @@ struct Workspace {
     size_t colnorm_cap = 0;
     float* valf = nullptr;  // FP32 copy of A's values (mixed-precision cycles)
     size_t valf_cap = 0;
+    double* wbuf = nullptr;  // two-barrier Arnoldi: w of the current step (n)
+    size_t wbuf_cap = 0;
     // batched solve: descriptors, states, order, and one arena for every
     // system's basis, scratch vectors, sketch lists and small matrices
     BatchSys* bt_sys = nullptr;
@@ -189,6 +192,7 @@ struct SolveArgs {
     int basis;  // SGMRES_BASIS_*
     double cheb_c, cheb_dx, cheb_dy;
     int precision;  // SGMRES_PREC_*
+    int halo_off;   // nonzero: three grid barriers per Arnoldi step always
     hipStream_t stream;
 };
 
@@ -282,6 +286,7 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
     p.spin_limit = kSpinLimitTicks;
     p.phase_ticks = phase_timing ? ws.sc->phase_ticks : nullptr;
     p.spmv_mode = spmv_mode;
+    p.wbuf = ws.wbuf;
     SG_TRY(arnoldi_launch(L, p, stream));
     return SGMRES_OK;
 }
@@ -356,7 +361,7 @@ int check_csr(Workspace& ws, const sgmres_csr_t& A, hipStream_t st) {
 // entry point); the solve uses S A B and g only.
 int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int block, int rpt,
                     ArnoldiLaunch* L, int sketch_basis, int precision = SGMRES_PREC_FP64) {
-    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis, precision};
+    ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis, precision, 0};
     if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
     SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(k + 1) * L->grid));
     SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
@@ -366,7 +371,7 @@ int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int
 
 int prepare_cheb(Workspace& ws, int64_t n, int d, int s, int zeta, int block, int rpt, ArnoldiLaunch* L,
                  int precision = SGMRES_PREC_FP64) {
-    ArnoldiShape shape{n, d, 1, s, zeta, block, rpt, 0, 0, 0, precision};
+    ArnoldiShape shape{n, d, 1, s, zeta, block, rpt, 0, 0, 0, precision, 0};
     if (chebyshev_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
     SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
     SG_TRY(ensure(ws.part_nrm, ws.part_nrm_cap, static_cast<size_t>(d) * L->grid));
@@ -425,6 +430,26 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         return solve_large(b, info);
     }
     if (rc) return rc;
+    rc = check_csr(ws, a.A, st);
+    if (rc) return rc;
+    // Two grid barriers per Arnoldi step when at most a quarter of the
+    // nonzeros reach outside their row's block (their b_j entries are then
+    // recomputed by the block that needs them).
+    if (!cheb && !a.halo_off && a.spmv_mode == 0) {
+        SG_TRY(hipMemsetAsync(&ws.sc->offblock, 0, sizeof(unsigned long long), st));
+        SG_TRY(launch_offblock_count(n, a.A.row_ptr, a.A.col_idx, static_cast<int64_t>(L.R) * L.block,
+                                     &ws.sc->offblock, st));
+        rc = copy_scalars(ws, st);
+        if (rc) return rc;
+        if (4 * ws.host_sc->offblock <= static_cast<unsigned long long>(a.A.nnz)) {
+            ArnoldiShape hs{n, a.d, kk, a.s, a.zeta, L.block, L.R, L.KW == 0, 0, 0, a.precision, 1};
+            ArnoldiLaunch H{};
+            if (arnoldi_configure(hs, &H) == hipSuccess && H.R == L.R && H.block == L.block && H.KW == L.KW) {
+                SG_TRY(ensure(ws.wbuf, ws.wbuf_cap, (static_cast<size_t>(n) * 8 + 7) / 8));
+                L = H;
+            }
+        }
+    }
     SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
     // B in the basis storage type (allocated in doubles)
     SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(n) * a.d * basis_elem_bytes(a.precision) + 7) / 8));
@@ -435,8 +460,6 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(a.d)));
     SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
     if (cheb) SG_TRY(ensure(ws.colnorm, ws.colnorm_cap, static_cast<size_t>(a.d)));
-    rc = check_csr(ws, a.A, st);
-    if (rc) return rc;
     // the basis cycles of the mixed-precision modes read an FP32 copy of A's values
     const void* cyc_val = a.A.val;
     if (a.precision != SGMRES_PREC_FP64) {
@@ -555,6 +578,7 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     a.spmv_mode = opts ? opts->spmv_mode : 0;
     a.basis = opts ? opts->basis : SGMRES_BASIS_ARNOLDI;
     a.precision = opts ? opts->precision : SGMRES_PREC_FP64;
+    a.halo_off = opts ? opts->halo_off : 0;
     if (a.precision != SGMRES_PREC_FP64 && a.precision != SGMRES_PREC_FP32 && a.precision != SGMRES_PREC_BF16_BASIS)
         return SGMRES_EINVAL;
     if (a.basis != SGMRES_BASIS_ARNOLDI && a.basis != SGMRES_BASIS_CHEBYSHEV) return SGMRES_EINVAL;
@@ -1094,7 +1118,7 @@ void sgmres_release_workspace(void) {
         if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
         void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_task, w.bt_slots, w.bt_slot_off, w.bt_gcnt, w.bt_arena,
                         w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
-                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
+                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);

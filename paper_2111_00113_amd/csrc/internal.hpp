@@ -36,6 +36,7 @@ struct ArnoldiParams {
     uint64_t spin_limit;
     unsigned long long* phase_ticks;  // null, or 8 accumulators (block 0's time per phase)
     int spmv_mode;                    // 0 row per thread, 1 CSR-stream through LDS
+    void* wbuf;                       // halo mode: n entries (arithmetic type), w of the current step
 };
 
 struct ArnoldiShape {
@@ -47,6 +48,7 @@ struct ArnoldiShape {
     int per_block_release;
     int sketch_basis;  // nonzero: the instance that also forms S b_j
     int precision;     // SGMRES_PREC_*
+    int halo;          // nonzero: the two-barrier (halo) instance
 };
 
 struct ArnoldiLaunch {
@@ -70,6 +72,10 @@ const void* arnoldi_pick_sb(int block, int R, int KW);
 // FP32 arithmetic with an FP32 / bfloat16 basis (arnoldi_f32.hip, arnoldi_bf16.hip)
 const void* arnoldi_pick_f32(int block, int R, int KW);
 const void* arnoldi_pick_bf16(int block, int R, int KW);
+// two-barrier (halo) solve instances (arnoldi_halo_*.hip)
+const void* arnoldi_pick_halo_f64(int block, int R, int KW);
+const void* arnoldi_pick_halo_f32(int block, int R, int KW);
+const void* arnoldi_pick_halo_bf16(int block, int R, int KW);
 // bytes of one stored basis entry for SGMRES_PREC_*
 inline size_t basis_elem_bytes(int precision) { return precision == 1 ? 4 : (precision == 2 ? 2 : 8); }
 
@@ -214,6 +220,10 @@ hipError_t launch_norm_finish(const double* part, int G, double* out, const doub
 // bad[0] |= 1 when the CSR arrays are malformed
 hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int* bad,
                             hipStream_t stream);
+// out[0] += nonzeros (i, c) of A with c / RB != i / RB (columns outside the
+// row's block of RB rows)
+hipError_t launch_offblock_count(int64_t n, const int32_t* rp, const int32_t* ci, int64_t RB,
+                                 unsigned long long* out, hipStream_t stream);
 // dval[q] = alpha * u[row(q)] * v[col(q)] on the sparsity pattern of A
 hipError_t launch_csr_outer(int64_t n, const int32_t* rp, const int32_t* ci, const double* u, const double* v,
                             double alpha, double* dval, hipStream_t stream);

@@ -186,6 +186,27 @@ hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B,
     return hipGetLastError();
 }
 
+__global__ void offblock_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                int64_t RB, unsigned long long* __restrict__ out) {
+    __shared__ double tmp[kVecBlock / kWave];
+    __shared__ double sum[1];
+    double cnt = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t b = i / RB;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) cnt += (ci[q] / RB != b) ? 1.0 : 0.0;
+    }
+    const double v[1] = {cnt};
+    block_sum<1>(v, 1, tmp, sum);
+    if (threadIdx.x == 0) atomicAdd(out, static_cast<unsigned long long>(sum[0]));
+}
+
+hipError_t launch_offblock_count(int64_t n, const int32_t* rp, const int32_t* ci, int64_t RB,
+                                 unsigned long long* out, hipStream_t stream) {
+    offblock_kernel<<<vec_grid(n), kVecBlock, 0, stream>>>(n, rp, ci, RB, out);
+    return hipGetLastError();
+}
+
 __global__ void to_f32_kernel(int64_t count, const double* __restrict__ in, float* __restrict__ out) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)

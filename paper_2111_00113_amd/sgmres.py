@@ -86,6 +86,7 @@ class _Options(ctypes.Structure):
         ("cheb_dy", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("batch_eager", ctypes.c_int32),
+        ("halo_off", ctypes.c_int32),
     ]
 
 
@@ -215,14 +216,16 @@ def _raise(fn, rc):
 
 def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
                  transposed=False, block_size=0, rows_per_thread=0, profile=False, barrier_mode=0,
-                 spmv_mode=0, cheb_box=None, precision="fp64", stream=None):
+                 spmv_mode=0, cheb_box=None, precision="fp64", halo_off=False, stream=None):
     """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
 
     cheb_box=(c, dx, dy) selects the Chebyshev basis for a spectrum inside
     [c - dx, c + dx] x [-dy, dy] (k is then unused); None selects k-truncated
     Arnoldi.  precision: "fp64", "fp32" (basis cycles in FP32) or "bf16" (FP32
     arithmetic, basis stored in bfloat16); the residual, least squares and x stay
-    FP64, so restarting refines to FP64 accuracy.  Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED
+    FP64, so restarting refines to FP64 accuracy.  halo_off=True keeps three grid
+    barriers per truncated-Arnoldi step (the default uses two when few
+    nonzeros reach outside their block; results are bit-identical).  Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED
     (1); raises SGMRESError on the negative error codes."""
     _check_dev(b, torch.float64, A.n)
     _check_dev(x, torch.float64, A.n)
@@ -230,7 +233,7 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     basis, (cc, cdx, cdy) = (0, (0.0, 0.0, 0.0)) if cheb_box is None else (1, tuple(float(t) for t in cheb_box))
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
-                    barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec, 0)
+                    barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec, 0, 1 if halo_off else 0)
     rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
                                ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     return _raise("sgmres_solve", rc), _info(info)
@@ -255,7 +258,7 @@ def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, z
     res = (_BatchResult * max(len(systems), 1))()
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 0, block_size, rows_per_thread, 0, 0, 0, 0, 0.0, 0.0, 0.0, prec,
-                    1 if eager else 0)
+                    1 if eager else 0, 0)
     rc = lib().sgmres_solve_batched(len(systems), arr, d, k, s, seed, tol, restarts, ctypes.byref(opts), res,
                                     _stream(stream))
     _raise("sgmres_solve_batched", rc)

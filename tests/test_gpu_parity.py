@@ -271,6 +271,27 @@ def test_barrier_modes_bit_identical(sg, orc):
         assert o[1] == outs[0][1]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_barrier_mode_bit_identical(sg, orc, prec):
+    # With few nonzeros outside their row's block the Arnoldi kernel runs two
+    # grid barriers per step: each block recomputes the entries of b_{j+1} it
+    # needs from other blocks as (w - W h2)/nu with the owner's operations, so
+    # the solve must reproduce the three-barrier run bit for bit.
+    A = synth.convection_diffusion(256, (50.0, 20.0))  # n = 65536: about 10% of nonzeros off-block
+    f = _t(synth.rhs(A.n, 0))
+    dA = sg.DeviceCSR.from_host(A)
+    outs = []
+    for halo_off in (False, True, False):
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc, info = sg.sgmres_solve(dA, f, x, 60, 4, 120, 3, 1e-10, 20, halo_off=halo_off, precision=prec)
+        outs.append((_np(x), info["relres"], info["cycles"]))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert o[1] == outs[0][1] and o[2] == outs[0][2]
+    _, nrm = orc.residual(A, _np(f), outs[0][0])
+    assert nrm / np.linalg.norm(_np(f)) <= 1e-10
+
+
 def test_solve_edge_cases(sg, orc):
     A = synth.convection_diffusion(12)
     dA = sg.DeviceCSR.from_host(A)
