@@ -107,9 +107,9 @@ typedef struct {
     int32_t barrier_mode; /* basis-kernel grid barrier: 0 one L2 write-back per XCD
                              (default), 1 one per workgroup (reference protocol;
                              results are bit-identical) */
-    int32_t spmv_mode;  /* basis-kernel SpMV: 0 one row per thread (default), 1
-                           nonzeros streamed through LDS in BLOCK-row chunks; both
-                           sum each row in nonzero order (Arnoldi basis only) */
+    int32_t spmv_mode;  /* must be 0: the basis kernels read A through a sliced
+                           ELL copy (slices of 64 rows, one wavefront each), built
+                           per call, summing each row in CSR order */
     int32_t basis;      /* SGMRES_BASIS_ARNOLDI (default) or SGMRES_BASIS_CHEBYSHEV */
     double cheb_c;      /* Chebyshev basis: the spectrum of A lies in the box */
     double cheb_dx;     /* [cheb_c - cheb_dx, cheb_c + cheb_dx] x [-cheb_dy, cheb_dy] */

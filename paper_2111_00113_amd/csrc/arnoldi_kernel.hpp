@@ -1,17 +1,17 @@
 // spmv_truncarnoldi: one cycle of k-truncated Arnoldi basis generation fused
-// with CSR SpMV and sparse-sign sketching, as a single persistent cooperative
+// with SpMV and sparse-sign sketching, as a single persistent cooperative
 // launch (arXiv:2111.00113, Algorithm 1 basis loop; truncated-Arnoldi
 // recurrence of Section 1.2.2; two classical Gram-Schmidt passes).
 //
 // Work decomposition.  Logical block b owns rows [b*R*BLOCK, (b+1)*R*BLOCK);
-// thread t of it owns rows b*R*BLOCK + r*BLOCK + t, r < R (coalesced across
-// lanes).  What a row needs between steps stays on chip for the whole cycle:
-// its row-pointer range and the last KW basis entries (registers), m_j = A b_j
-// and w (registers).  The SpMV streams each BLOCK-row chunk's nonzeros with
-// coalesced loads into an LDS product buffer and every thread then sums its
-// row in nonzero order.  Per step the kernel moves the CSR column indices and
-// values, the gathered b_j and the written b_{j+1} through HBM, plus per-block
-// partial sums.
+// thread t of it owns rows b*R*BLOCK + r*BLOCK + t, r < R, so the 64 rows of a
+// wavefront in chunk r are one slice of the sliced ELL copy of A (sell.hip):
+// the SpMV reads the k-th nonzero of the wavefront's rows with one contiguous
+// load of values and one of columns, and sums each row in CSR order.  What a
+// row needs between steps stays on chip for the whole cycle: its slice
+// position and the last KW basis entries (registers), m_j = A b_j and w
+// (registers).  Per step the kernel moves A's values and columns, the gathered
+// b_j and the written b_{j+1} through HBM, plus per-block partial sums.
 //
 // Sketch.  The pattern of S restricted to the block's rows is generated once
 // per cycle and sorted by sketch row into LDS lists.  Each step stages m_j (and
@@ -20,16 +20,18 @@
 // so the result is bitwise reproducible).  The block partials of all steps are
 // kept and summed across blocks once, at the end of the cycle.
 //
-// Per step j (three split-phase grid barriers, the first two carrying a
-// reduction; a third of the block's sketch work fills each barrier wait):
+// Per step j (split-phase grid barriers, the first two carrying a reduction;
+// the block's sketch work fills the barrier waits):
 //   phase 1  m = A b_j; partial <m,m>, W^T m           -- arrive --
-//            stage b_j, m in LDS; sketch rows [0, s/3)   -- wait --
+//            stage m in LDS; sketch rows [0, s/3)        -- wait --
 //   phase 2  h = W^T m (grid sum); w = m - W h; partial <w,w>, W^T w
 //                                                        -- arrive --
 //            sketch rows [s/3, 2s/3)                     -- wait --
 //   phase 3  h2 = W^T w; |w - W h2|^2 = <w,w> - |h2|^2 (window orthonormal to
 //            rounding); b_{j+1} = (w - W h2)/nu; H column j  -- arrive --
 //            sketch rows [2s/3, s)                       -- wait --
+// In the halo mode (see the kernel) the third barrier is dropped and the sketch
+// is split over the first two waits.
 #pragma once
 
 #include "common.hpp"
@@ -55,7 +57,7 @@ __device__ __forceinline__ float gs_sub(float x, float h, float v) { return __bu
 // (w - W h2) / nu from w (written to HBM before the second barrier) and the
 // window columns, with the owner's operations in the owner's order, so the
 // values are the owner's bits.  Chosen when few nonzeros reach outside their
-// block (requires SKB = false and the row-per-thread SpMV).
+// block (requires SKB = false).
 template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO = false>
 __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     extern __shared__ double smem[];
@@ -97,27 +99,25 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                  p.per_block_release != 0};
     bar.setup(sync_lds);
 
-    // ---- per-row CSR structure, held for the cycle ---------------------------
-    // rbeg/rlen of own rows in registers; chunk r of the block (rows
-    // [b*RB + r*BLOCK, +BLOCK)) spans nonzeros [cq[r], cq[r+1]).
-    int rbeg[R], rlen[R];
-    __shared__ int cq[R + 1];
+    // ---- sliced ELL position of own rows, held for the cycle ------------------
+    // the 64 rows of this wavefront in chunk r form one slice: entry k of this
+    // lane's row is at spos[r] + 64 k, for k < sK[r]
+    int64_t spos[R];
+    int sK[R];
+    {
+        const int64_t nsl = (n + kWave - 1) / kWave;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-        rbeg[r] = 0;
-        rlen[r] = 0;
-        if (row < n) {
-            rbeg[r] = p.rp[row];
-            rlen[r] = p.rp[row + 1] - rbeg[r];
+        for (int r = 0; r < R; ++r) {
+            const int64_t sl = (static_cast<int64_t>(blk) * RB + static_cast<int64_t>(r) * BLOCK) / kWave + wid;
+            spos[r] = 0;
+            sK[r] = 0;
+            if (sl < nsl) {
+                const int64_t a = p.sp[sl];
+                spos[r] = a + lane;
+                sK[r] = static_cast<int>((p.sp[sl + 1] - a) / kWave);
+            }
         }
     }
-    if (tid <= R) {
-        int64_t row = static_cast<int64_t>(blk) * RB + static_cast<int64_t>(tid) * BLOCK;
-        if (row > n) row = n;
-        cq[tid] = p.rp[row];
-    }
-    __syncthreads();
 
     // ---- sketch lists of the block's rows, sorted by sketch row --------------
     sketch_lists_build<R, BLOCK>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
@@ -229,62 +229,72 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         const int kw = min(j + 1, p.k);
 
         // ---- phase 1: m = A b_j and partial dots ---------------------------
+        // SpMV, nonzero slot outermost: slot q of the R rows is fetched with R
+        // independent loads, then R independent gathers (each row still sums
+        // its nonzeros in CSR order)
         TC m[R];
-        if (p.spmv_mode == 1) {
-            // CSR-stream: the chunk's products val[q] * b_j[col[q]] go to LDS with
-            // coalesced loads, then each thread sums its row in nonzero order.
-            double* prod = vals;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int q0 = cq[r], q1 = cq[r + 1];
-                TC am = TC(0);
-                if (q1 - q0 <= 2 * RB) {
-#pragma unroll 4
-                    for (int q = q0 + tid; q < q1; q += BLOCK)
-                        prod[q - q0] = static_cast<double>(Av[q] * from_basis<TC>(bj[p.ci[q]]));
-                    __syncthreads();
-                    for (int q = 0; q < rlen[r]; ++q) am += static_cast<TC>(prod[rbeg[r] - q0 + q]);
-                    __syncthreads();
-                } else {
-                    for (int q = 0; q < rlen[r]; ++q)
-                        am += Av[rbeg[r] + q] * from_basis<TC>(bj[p.ci[rbeg[r] + q]]);
-                }
-                m[r] = am;
-            }
-        } else if constexpr (HALO) {
+        for (int r = 0; r < R; ++r) m[r] = TC(0);
+        int kmax = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) kmax = max(kmax, sK[r]);
+        if constexpr (HALO) {
             // own rows from LDS; other blocks' rows of b_j recomputed from w and
             // the window of step j-1 (b_1 is in HBM, published at init)
             const int kwp = min(j, p.k);
             const TC nup = static_cast<TC>(coef[2 * p.k + 2]);
             const double* h2p = coef + p.k + 2;
             const TS* Bp = Bs + static_cast<int64_t>(j > 0 ? j - 1 : 0) * p.ldb;
+            for (int q = 0; q < kmax; ++q) {
+                int c[R];
+                TC v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                TC am = TC(0);
-                for (int q = 0; q < rlen[r]; ++q) {
-                    const int c = p.ci[rbeg[r] + q];
-                    TC bv;
-                    if (c >= row_lo && c < row_hi) {
-                        bv = bst[c - row_lo];
-                    } else if (j == 0) {
-                        bv = from_basis<TC>(bj[c]);
-                    } else {
-                        TC t = wbuf[c];
-                        for (int a = 0; a < kwp; ++a)
-                            t = gs_sub(t, static_cast<TC>(h2p[a]), from_basis<TC>(Bp[c - static_cast<int64_t>(a) * p.ldb]));
-                        bv = from_basis<TC>(to_basis<TS>(t / nup));
+                for (int r = 0; r < R; ++r) {
+                    c[r] = -1;
+                    v[r] = TC(0);
+                    if (q < sK[r]) {
+                        const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
+                        c[r] = p.ci[e];
+                        v[r] = Av[e];
                     }
-                    am += Av[rbeg[r] + q] * bv;
                 }
-                m[r] = am;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (q < sK[r]) {
+                        const int cc = c[r];
+                        TC bv;
+                        if (cc >= row_lo && cc < row_hi) {
+                            bv = bst[cc - row_lo];
+                        } else if (j == 0) {
+                            bv = from_basis<TC>(bj[cc]);
+                        } else {
+                            TC t = wbuf[cc];
+                            for (int a = 0; a < kwp; ++a)
+                                t = gs_sub(t, static_cast<TC>(h2p[a]),
+                                           from_basis<TC>(Bp[cc - static_cast<int64_t>(a) * p.ldb]));
+                            bv = from_basis<TC>(to_basis<TS>(t / nup));
+                        }
+                        m[r] += v[r] * bv;
+                    }
+                }
             }
         } else {
-            // one row per thread, nonzeros in order
+            for (int q = 0; q < kmax; ++q) {
+                int c[R];
+                TC v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                TC am = TC(0);
-                for (int q = 0; q < rlen[r]; ++q) am += Av[rbeg[r] + q] * from_basis<TC>(bj[p.ci[rbeg[r] + q]]);
-                m[r] = am;
+                for (int r = 0; r < R; ++r) {
+                    c[r] = 0;
+                    v[r] = TC(0);
+                    if (q < sK[r]) {
+                        const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
+                        c[r] = p.ci[e];
+                        v[r] = Av[e];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (q < sK[r]) m[r] += v[r] * from_basis<TC>(bj[c[r]]);
             }
         }
         dots_to_partials(m, j, kw, p.part_a);

@@ -84,6 +84,15 @@ struct Workspace {
     size_t valf_cap = 0;
     double* wbuf = nullptr;  // two-barrier Arnoldi: w of the current step (n)
     size_t wbuf_cap = 0;
+    // sliced ELL copy of A for the resident basis kernels
+    int* sell_K = nullptr;
+    size_t sell_K_cap = 0;
+    int64_t* sell_sp = nullptr;
+    size_t sell_sp_cap = 0;
+    int32_t* sell_col = nullptr;
+    size_t sell_col_cap = 0;
+    double* sell_val = nullptr;  // doubles or floats
+    size_t sell_val_cap = 0;
     // batched solve: descriptors, states, order, and one arena for every
     // system's basis, scratch vectors, sketch lists and small matrices
     BatchSys* bt_sys = nullptr;
@@ -248,20 +257,43 @@ int copy_scalars(Workspace& ws, hipStream_t stream) {
     return SGMRES_OK;
 }
 
+// Sliced ELL copy of A (sell.hip) with values in the basis arithmetic type.
+int build_sell(Workspace& ws, const sgmres_csr_t& A, int precision, hipStream_t st) {
+    const int64_t n = A.n;
+    const int64_t nsl = (n + 63) / 64;
+    SG_TRY(ensure(ws.sell_K, ws.sell_K_cap, static_cast<size_t>(nsl)));
+    SG_TRY(ensure(ws.sell_sp, ws.sell_sp_cap, static_cast<size_t>(nsl + 1)));
+    SG_TRY(launch_sell_width(n, A.row_ptr, ws.sell_K, st));
+    std::vector<int> K(static_cast<size_t>(nsl));
+    SG_TRY(hipMemcpyAsync(K.data(), ws.sell_K, sizeof(int) * nsl, hipMemcpyDeviceToHost, st));
+    SG_TRY(hipStreamSynchronize(st));
+    std::vector<int64_t> sp(static_cast<size_t>(nsl + 1), 0);
+    for (int64_t i = 0; i < nsl; ++i) sp[i + 1] = sp[i] + 64 * static_cast<int64_t>(K[i]);
+    const int64_t total = sp[nsl] > 0 ? sp[nsl] : 1;
+    SG_TRY(ensure(ws.sell_col, ws.sell_col_cap, static_cast<size_t>(total)));
+    const size_t es = precision == SGMRES_PREC_FP64 ? 8 : 4;
+    SG_TRY(ensure(ws.sell_val, ws.sell_val_cap, (static_cast<size_t>(total) * es + 7) / 8));
+    SG_TRY(hipMemcpyAsync(ws.sell_sp, sp.data(), sizeof(int64_t) * (nsl + 1), hipMemcpyHostToDevice, st));
+    SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, ws.sell_sp, ws.sell_col, ws.sell_val, precision, st));
+    SG_TRY(hipStreamSynchronize(st));  // sp (host vector) is read by the copy above
+    return SGMRES_OK;
+}
+
 // One basis cycle on the residual in ws.r (norm already in ws.sc->beta).
-// B is stored in the launch's basis type; val (null = A.val) in its arithmetic type.
+// B is stored in the launch's basis type; A is read through the sliced ELL
+// copy in ws (build_sell, same arithmetic type).
 int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zeta, uint64_t seed,
               uint32_t cycle, const ArnoldiLaunch& L, void* B, int64_t ldb, double* SB, double* SAB,
               double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
-              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0,
-              const void* val = nullptr) {
+              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ArnoldiParams p{};
     p.n = A.n;
     p.rp = A.row_ptr;
-    p.ci = A.col_idx;
-    p.val = val ? val : A.val;
+    p.sp = ws.sell_sp;
+    p.ci = ws.sell_col;
+    p.val = ws.sell_val;
     p.r = ws.r;
     p.beta = &ws.sc->beta;
     p.B = B;
@@ -295,15 +327,15 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
 int run_cheb_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int s, int zeta, uint64_t seed, uint32_t cycle,
                    const ArnoldiLaunch& L, const ChebCoef& cf, void* B, int64_t ldb, double* SB, double* SAB,
                    double* colnorm, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
-                   int per_block_release = 0, bool phase_timing = false, int sketch_basis = 1,
-                   const void* val = nullptr) {
+                   int per_block_release = 0, bool phase_timing = false, int sketch_basis = 1) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ChebParams p{};
     p.n = A.n;
     p.rp = A.row_ptr;
-    p.ci = A.col_idx;
-    p.val = val ? val : A.val;
+    p.sp = ws.sell_sp;
+    p.ci = ws.sell_col;
+    p.val = ws.sell_val;
     p.r = ws.r;
     p.beta = &ws.sc->beta;
     p.B = B;
@@ -460,13 +492,10 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(a.d)));
     SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
     if (cheb) SG_TRY(ensure(ws.colnorm, ws.colnorm_cap, static_cast<size_t>(a.d)));
-    // the basis cycles of the mixed-precision modes read an FP32 copy of A's values
-    const void* cyc_val = a.A.val;
-    if (a.precision != SGMRES_PREC_FP64) {
-        SG_TRY(ensure(ws.valf, ws.valf_cap, static_cast<size_t>(a.A.nnz)));
-        SG_TRY(launch_to_f32(a.A.nnz, a.A.val, ws.valf, st));
-        cyc_val = ws.valf;
-    }
+    // the basis cycles read A through its sliced ELL copy, values in the
+    // cycles' arithmetic type (FP32 in the mixed-precision modes)
+    rc = build_sell(ws, a.A, a.precision, st);
+    if (rc) return rc;
 
     // |b|, and clear the per-solve counters
     SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
@@ -531,11 +560,11 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         if (cheb)
             rc = run_cheb_cycle(ws, a.A, a.d, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, cf, ws.B, n,
                                 ws.SB, ws.SAB, ws.colnorm, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release,
-                                ev.on, 0, cyc_val);
+                                ev.on, 0);
         else
             rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
                            ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
-                           a.spmv_mode, cyc_val);
+                           a.spmv_mode);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
         rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
@@ -576,6 +605,7 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     a.profile = opts ? opts->profile : 0;
     a.per_block_release = opts ? opts->barrier_mode : 0;
     a.spmv_mode = opts ? opts->spmv_mode : 0;
+    if (a.spmv_mode != 0) return SGMRES_EINVAL;
     a.basis = opts ? opts->basis : SGMRES_BASIS_ARNOLDI;
     a.precision = opts ? opts->precision : SGMRES_PREC_FP64;
     a.halo_off = opts ? opts->halo_off : 0;
@@ -990,6 +1020,8 @@ int sgmres_arnoldi_cycle(const sgmres_csr_t* A, const double* r, int d, int k, i
     if (rc) return rc;
     rc = check_csr(*ws, *A, st);
     if (rc) return rc;
+    rc = build_sell(*ws, *A, SGMRES_PREC_FP64, st);
+    if (rc) return rc;
     // |r| into the scalar block, r copied into the workspace residual
     SG_TRY(hipMemsetAsync(&ws->sc->dc, 0, 5 * sizeof(int), st));
     SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, r, nullptr, ws->r, ws->part_vec, st));
@@ -1024,6 +1056,8 @@ int sgmres_chebyshev_cycle(const sgmres_csr_t* A, const double* r, int d, int s,
     rc = prepare_cheb(*ws, n, d, s, zeta, 0, 0, &L);
     if (rc) return rc;
     rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    rc = build_sell(*ws, *A, SGMRES_PREC_FP64, st);
     if (rc) return rc;
     SG_TRY(hipMemsetAsync(&ws->sc->dc, 0, 5 * sizeof(int), st));
     SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, r, nullptr, ws->r, ws->part_vec, st));
@@ -1118,7 +1152,8 @@ void sgmres_release_workspace(void) {
         if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
         void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_task, w.bt_slots, w.bt_slot_off, w.bt_gcnt, w.bt_arena,
                         w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
-                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
+                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sell_K, w.sell_sp, w.sell_col,
+                        w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);

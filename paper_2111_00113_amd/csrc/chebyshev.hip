@@ -1,7 +1,8 @@
 // Chebyshev basis cycle: the shifted-and-scaled Chebyshev recurrence of
 // arXiv:2111.00113 Section 4.4 (equation for b_j, j >= 3, with the starting
-// vectors b_1 = r/|r|, b_2 = (A - cI) b_1 / (2 rho)), fused with CSR SpMV and
-// sparse-sign sketching in one persistent cooperative launch.
+// vectors b_1 = r/|r|, b_2 = (A - cI) b_1 / (2 rho)), fused with SpMV (on the
+// sliced ELL copy of A, sell.hip) and sparse-sign sketching in one persistent
+// cooperative launch.
 //
 // The recurrence has no inner products, so a step needs one grid barrier (the
 // new column must be complete before any block gathers it for the next SpMV)
@@ -63,15 +64,22 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
                  p.per_block_release != 0};
     bar.setup(sync_lds);
 
-    int rbeg[R], rlen[R];
+    // sliced ELL position of own rows (see sell.hip): entry k of this lane's
+    // row in chunk r is at spos[r] + 64 k, for k < sK[r]
+    int64_t spos[R];
+    int sK[R];
+    {
+        const int64_t nsl = (n + kWave - 1) / kWave;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-        rbeg[r] = 0;
-        rlen[r] = 0;
-        if (row < n) {
-            rbeg[r] = p.rp[row];
-            rlen[r] = p.rp[row + 1] - rbeg[r];
+        for (int r = 0; r < R; ++r) {
+            const int64_t sl = (static_cast<int64_t>(blk) * RB + static_cast<int64_t>(r) * BLOCK) / kWave + wid;
+            spos[r] = 0;
+            sK[r] = 0;
+            if (sl < nsl) {
+                const int64_t a = p.sp[sl];
+                spos[r] = a + lane;
+                sK[r] = static_cast<int>((p.sp[sl + 1] - a) / kWave);
+            }
         }
     }
     sketch_lists_build<R, BLOCK>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
@@ -114,12 +122,31 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
 
     for (int j = 0; j < p.d; ++j) {
         const TS* bj = Bs + static_cast<int64_t>(j) * p.ldb;
+        // SpMV, nonzero slot outermost (R independent loads, then R gathers per
+        // slot; each row sums its nonzeros in CSR order)
         TC m[R];
+        int kmax = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            TC am = TC(0);
-            for (int q = 0; q < rlen[r]; ++q) am += Av[rbeg[r] + q] * from_basis<TC>(bj[p.ci[rbeg[r] + q]]);
-            m[r] = am;
+            m[r] = TC(0);
+            kmax = max(kmax, sK[r]);
+        }
+        for (int q = 0; q < kmax; ++q) {
+            int c[R];
+            TC v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                c[r] = 0;
+                v[r] = TC(0);
+                if (q < sK[r]) {
+                    const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
+                    c[r] = p.ci[e];
+                    v[r] = Av[e];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (q < sK[r]) m[r] += v[r] * from_basis<TC>(bj[c[r]]);
         }
         const bool more = j + 1 < p.d;
         TC bnext[R];

@@ -13,8 +13,9 @@ constexpr int kMaxZeta = 32;  // largest sketch column sparsity supported
 struct ArnoldiParams {
     int64_t n;
     const int32_t* rp;
-    const int32_t* ci;
-    const void* val;     // A's values in the kernel's arithmetic type
+    const int64_t* sp;   // sliced ELL copy of A (sell.hip): slice starts,
+    const int32_t* ci;   // columns
+    const void* val;     // and values in the kernel's arithmetic type
     const double* r;     // cycle residual, n
     const double* beta;  // device scalar |r|
     void* B;             // n x d in the basis storage type, leading dim ldb
@@ -83,8 +84,9 @@ inline size_t basis_elem_bytes(int precision) { return precision == 1 ? 4 : (pre
 struct ChebParams {
     int64_t n;
     const int32_t* rp;
-    const int32_t* ci;
-    const void* val;     // A's values in the kernel's arithmetic type
+    const int64_t* sp;   // sliced ELL copy of A (sell.hip): slice starts,
+    const int32_t* ci;   // columns
+    const void* val;     // and values in the kernel's arithmetic type
     const double* r;     // cycle residual, n
     const double* beta;  // device scalar |r|
     void* B;             // n x d raw recurrence vectors (storage type), leading dim ldb
@@ -204,6 +206,14 @@ hipError_t launch_batch_advance(int* ctr, BatchState* st, unsigned* gcnt, int ns
 hipError_t launch_batch_reset(BatchState* st, unsigned* gcnt, int nsys, int* ctr, hipStream_t stream);
 hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
                               hipStream_t stream);
+
+// ---- sliced ELL copy of A for the basis kernels (sell.hip) ----------------
+// K[i] = longest row of slice i (rows 64 i .. 64 i + 63); sp = exclusive prefix
+// of 64 K; scol / sval (sval in the basis arithmetic type: double for
+// SGMRES_PREC_FP64, float otherwise) hold sp[nslices] entries.
+hipError_t launch_sell_width(int64_t n, const int32_t* rp, int* K, hipStream_t stream);
+hipError_t launch_sell_fill(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const int64_t* sp,
+                            int32_t* scol, void* sval, int precision, hipStream_t stream);
 
 // ---- vector kernels (vec.hip) ----------------------------------------------
 constexpr int kVecBlock = 256;
