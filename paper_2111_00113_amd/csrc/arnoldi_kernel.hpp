@@ -448,8 +448,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             const int ee = static_cast<int>(e - jj * nsl) + (jj < dc ? off : 0);
             const double* col = (jj < dc) ? p.part_sk + jj * slab + static_cast<int64_t>(ee) * G
                                           : p.part_sk + static_cast<int64_t>(p.d) * slab + static_cast<int64_t>(ee) * G;
-            double t = 0.0;
-            for (int g = lane; g < G; g += kWave) t += col[g];
+            double t = lane_strided_sum(col, G, lane);
             t = wave_sum(t) * scale;
             if (lane == 0) {
                 if (jj == dc) p.g[ee] = t;

@@ -85,8 +85,8 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
         const TC* Av = static_cast<const TC*>(S.valc);
         TC* Ms = static_cast<TC*>(S.m);
         TC* Ws = static_cast<TC*>(S.w);
-        double* red_slot = p.slots + p.slot_off[sid];    // [2][P][kBatchRed]
-        double* sk_slot = red_slot + 2 * P * kBatchRed;  // [P][s]
+        double* red_slot = p.slots + p.slot_off[sid];    // [2][kBatchRed][P]
+        double* sk_slot = red_slot + 2 * P * kBatchRed;  // [s][P]
         unsigned* cnt = p.gcnt + sid;
         unsigned epoch = 0;
         int nred = 0;
@@ -125,9 +125,36 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
             __syncthreads();
             failed = failed || (fail_sh != 0);
         };
+        // Sums over the P parts of src[e * P + q], q = 0 .. P-1, for e in
+        // [e0, e1): a group of L lanes (L = P rounded up to a power of two, at
+        // most 64) per entry, up to four loads per lane issued together, then a
+        // fixed xor butterfly over the group.  Deterministic for a given P.
+        static_assert(kBatchMaxParts <= 4 * kWave, "group sums load at most four values per lane");
+        auto parts_sum = [&](const double* src, int e0, int e1, auto&& out) {
+            const int lane = tid & (kWave - 1);
+            int L = 1;
+            while (L < P && L < kWave) L <<= 1;
+            const int per_wave = kWave / L, ql = lane & (L - 1);
+            for (int eb = e0 + (tid / kWave) * per_wave; eb < e1; eb += NW * per_wave) {
+                const int e = eb + lane / L;
+                double t[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = ql + u * L;
+                    t[u] = (e < e1 && q < P) ? src[static_cast<int64_t>(e) * P + q] : 0.0;
+                }
+                double a = 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (ql + u * L < P) a += t[u];
+                for (int o = L >> 1; o >= 1; o >>= 1) a += __shfl_xor(a, o, kWave);
+                if (ql == 0 && e < e1) out(e, a);
+            }
+        };
         // red_out[0..nv) (this part's workgroup sums) -> sums over all parts.
-        // With sketch != null also the parts' sketch accumulators are exchanged
-        // (one barrier for both) and the lead part writes dst = scale * sum.
+        // With dst != null also the parts' sketch accumulators are exchanged
+        // (one barrier for both); part q sums the sketch rows of its share of
+        // [0, s) and writes dst = scale * sum for them.
         auto group_sum = [&](int nv, double* dst) {
             if (P == 1) {
                 if (dst)
@@ -136,21 +163,15 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
             }
             double* sl = red_slot + (nred & 1) * P * kBatchRed;
             ++nred;
-            if (tid < nv) sl[part * kBatchRed + tid] = red_out[tid];
+            if (tid < nv) sl[tid * P + part] = red_out[tid];
             if (dst)
-                for (int e = tid; e < s; e += BLOCK) sk_slot[static_cast<int64_t>(part) * s + e] = acc[e];
+                for (int e = tid; e < s; e += BLOCK) sk_slot[static_cast<int64_t>(e) * P + part] = acc[e];
             gsync();
-            if (tid < nv) {
-                double a = 0.0;
-                for (int q = 0; q < P; ++q) a += sl[q * kBatchRed + tid];
-                red_out[tid] = a;
-            }
-            if (dst && lead)
-                for (int e = tid; e < s; e += BLOCK) {
-                    double a = 0.0;
-                    for (int q = 0; q < P; ++q) a += sk_slot[static_cast<int64_t>(q) * s + e];
-                    dst[e] = a * scale;
-                }
+            parts_sum(sl, 0, nv, [&](int e, double a) { red_out[e] = a; });
+            if (dst)
+                parts_sum(sk_slot, static_cast<int>(static_cast<int64_t>(part) * s / P),
+                          static_cast<int>(static_cast<int64_t>(part + 1) * s / P),
+                          [&](int e, double a) { dst[e] = a * scale; });
             __syncthreads();
         };
         auto decide = [&](int code) {
@@ -208,16 +229,43 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
         for (int c = 0; c < nch; ++c) {
             const int ch = ch0 + c;
             const int64_t base = static_cast<int64_t>(ch) * CH + tid;
+            // A x with nonzero slot outermost over the R rows (independent
+            // loads in flight; each row summed in CSR order)
+            int rb[R], rl[R];
+            int kmax = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = base + r * BLOCK;
+                rb[r] = row < r1 ? S.rp[row] : 0;
+                rl[r] = row < r1 ? S.rp[row + 1] - rb[r] : 0;
+                kmax = max(kmax, rl[r]);
+            }
+            double ax[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) ax[r] = 0.0;
+            for (int q = 0; q < kmax; ++q) {
+                int c[R];
+                double v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    c[r] = 0;
+                    v[r] = 0.0;
+                    if (q < rl[r]) {
+                        c[r] = S.ci[rb[r] + q];
+                        v[r] = S.val[rb[r] + q];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (q < rl[r]) ax[r] += v[r] * S.x[c[r]];
+            }
             double rv[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + r * BLOCK;
                 rv[r] = 0.0;
                 if (row < r1) {
-                    double ax = 0.0;
-                    const int q1 = S.rp[row + 1];
-                    for (int q = S.rp[row]; q < q1; ++q) ax += S.val[q] * S.x[S.ci[q]];
-                    rv[r] = S.b[row] - ax;
+                    rv[r] = S.b[row] - ax[r];
                     S.r[row] = rv[r];
                     rr += rv[r] * rv[r];
                 }
@@ -290,21 +338,46 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
             for (int c = 0; c < nch; ++c) {
                 const int ch = ch0 + c;
                 const int64_t base = static_cast<int64_t>(ch) * CH + tid;
-                TC mv[R];
+                // m = A b_j, nonzero slot outermost over the R rows
+                int rb[R], rl[R];
+                int kmax = 0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int64_t row = base + r * BLOCK;
-                    TC am = TC(0);
+                    rb[r] = row < r1 ? S.rp[row] : 0;
+                    rl[r] = row < r1 ? S.rp[row + 1] - rb[r] : 0;
+                    kmax = max(kmax, rl[r]);
+                }
+                TC mv[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) mv[r] = TC(0);
+                for (int q = 0; q < kmax; ++q) {
+                    int c[R];
+                    TC v[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        c[r] = 0;
+                        v[r] = TC(0);
+                        if (q < rl[r]) {
+                            c[r] = S.ci[rb[r] + q];
+                            v[r] = Av[rb[r] + q];
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (q < rl[r]) mv[r] += v[r] * from_basis<TC>(bj[c[r]]);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t row = base + r * BLOCK;
                     if (row < r1) {
-                        const int q1 = S.rp[row + 1];
-                        for (int q = S.rp[row]; q < q1; ++q) am += Av[q] * from_basis<TC>(bj[S.ci[q]]);
+                        const TC am = mv[r];
                         Ms[row] = am;
                         dm[0] += static_cast<double>(am * am);
 #pragma unroll
                         for (int a = 0; a < kBatchMaxK; ++a)
                             if (a < kw) dm[1 + a] += static_cast<double>(Wv(a, row) * am);
                     }
-                    mv[r] = am;
                 }
                 __syncthreads();  // the previous chunk's lists and vals are consumed
                 const int64_t lo = static_cast<int64_t>(ch) * (s + 1);

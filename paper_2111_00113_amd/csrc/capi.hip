@@ -660,7 +660,6 @@ constexpr int kBatchMaxChunk = 4096;  // largest
 constexpr size_t kArenaAlign = 256;
 constexpr int64_t kBatchTuneRows = int64_t(1) << 20;  // smaller batches use 512 x 4
 constexpr int64_t kBatchPartRows = 16384;              // rows per part of a large system
-constexpr int kBatchMaxParts = 256;
 
 using BatchKey = std::tuple<int, int, int, int, int, int, int>;
 std::map<BatchKey, BatchCand> g_batch_tuned;

@@ -200,8 +200,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
         if (u < p.d) {
             if (wid == 0) {
                 const double* col = p.part_nrm + static_cast<int64_t>(u) * G;
-                double t = 0.0;
-                for (int g = lane; g < G; g += kWave) t += col[g];
+                double t = lane_strided_sum(col, G, lane);
                 t = wave_sum(t);
                 if (lane == 0) {
                     const double nrm = sqrt(t);
@@ -218,8 +217,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
         for (int e = wid; e < ne; e += NW) {
             const int ee = (u < p.d) ? e + off : e;
             const double* col = p.part_sk + static_cast<int64_t>(u) * slab + static_cast<int64_t>(ee) * G;
-            double t = 0.0;
-            for (int g = lane; g < G; g += kWave) t += col[g];
+            double t = lane_strided_sum(col, G, lane);
             t = wave_sum(t) * us;
             if (lane == 0) {
                 if (u == p.d) p.g[ee] = t;

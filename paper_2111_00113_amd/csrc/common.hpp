@@ -178,6 +178,23 @@ __device__ __forceinline__ void block_sum(const double (&vals)[NV], int nv, doub
     __syncthreads();
 }
 
+// This lane's share of sum_g col[g]: g = lane, lane + 64, ... < G, added in g
+// order.  The loads are issued four at a time before the adds, so a sum over
+// data just written by other workgroups waits for one memory round trip per
+// 256 entries rather than one per 64.
+__device__ __forceinline__ double lane_strided_sum(const double* col, int G, int lane) {
+    double acc = 0.0;
+    for (int g0 = lane; g0 < G; g0 += 4 * kWave) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = (g0 + u * kWave < G) ? col[g0 + u * kWave] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (g0 + u * kWave < G) acc += t[u];
+    }
+    return acc;
+}
+
 // Every block sums partial[v * G + g] over g (fixed order) for v < nv; result
 // in lds_out[0..nv).  One wavefront per value, lanes stride over g.
 __device__ __forceinline__ void grid_sum(const double* partial, int G, int nv, double* lds_out) {
@@ -185,8 +202,7 @@ __device__ __forceinline__ void grid_sum(const double* partial, int G, int nv, d
     const int wid = threadIdx.x / kWave;
     const int nw = blockDim.x / kWave;
     for (int v = wid; v < nv; v += nw) {
-        double acc = 0.0;
-        for (int g = lane; g < G; g += kWave) acc += partial[static_cast<int64_t>(v) * G + g];
+        double acc = lane_strided_sum(partial + static_cast<int64_t>(v) * G, G, lane);
         acc = wave_sum(acc);
         if (lane == 0) lds_out[v] = acc;
     }

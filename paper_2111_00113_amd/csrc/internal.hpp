@@ -173,7 +173,7 @@ struct BatchParams {
     const BatchTask* task;
     const BatchSys* sys;
     BatchState* st;
-    double* slots;       // per system: 2 x nparts x kBatchRed reduction slots, then nparts x s sketch slots
+    double* slots;       // per system: 2 x kBatchRed x nparts reduction slots, then s x nparts sketch slots
     const int64_t* slot_off;  // per system: offset of its slots (doubles)
     unsigned* gcnt;      // per system: arrivals at the group barrier this cycle
     int* queue;          // next task (zero at launch)
@@ -194,6 +194,7 @@ struct BatchLaunch {
 };
 constexpr int kBatchMaxK = 4;
 constexpr int kBatchRed = kBatchMaxK + 1;  // values per group reduction (window dots + a norm)
+constexpr int kBatchMaxParts = 256;         // parts per system; the group sums load at most 4 per lane
 // chunk rows a kernel instance handles at a time
 inline int batch_chunk(const BatchLaunch& L) { return L.block * L.R; }
 hipError_t batch_configure(int block, int R, int d, int s, int zeta, int precision, BatchLaunch* out);

@@ -147,17 +147,19 @@ def test_precision_rejects_unknown_mode(sg):
     assert e.value.rc == -1
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_large_system_beyond_resident_capacity(sg, orc, prec):
-    """n = 1,210,000 (cd1100) exceeds the resident basis kernel's 2^20 rows; the
-    solve runs on the part-split kernel of the batched path and must still
-    reach 1e-10 (true residual recomputed by the oracle)."""
-    A = synth.convection_diffusion(1100, (50.0, 20.0))
+@pytest.mark.parametrize("prec,grid", [("fp64", 1100), ("fp32", 1100), ("fp64", 2100)])
+def test_large_system_beyond_resident_capacity(sg, orc, prec, grid):
+    """n = 1,210,000 (cd1100, 74 parts) and n = 4,410,000 (cd2100, 256 parts:
+    the most a system is split into, so the group sums load four values per
+    lane) exceed the resident basis kernel's 2^20 rows; the solve runs on the
+    part-split kernel of the batched path and must still reach 1e-10 (true
+    residual recomputed by the oracle)."""
+    A = synth.convection_diffusion(grid, (50.0, 20.0))
     f = synth.rhs(A.n, 0)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
     rc, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(f), x, 200, 4, 400, 0, 1e-10, 1000, precision=prec)
     _, nrm = orc.residual(A, f, _np(x))
-    print(f"cd1100 {prec}: cycles {info['cycles']}, relres {nrm / np.linalg.norm(f):.3e}", flush=True)
+    print(f"cd{grid} {prec}: cycles {info['cycles']}, relres {nrm / np.linalg.norm(f):.3e}", flush=True)
     assert rc == sg.OK
     assert nrm / np.linalg.norm(f) <= 1e-10
     assert abs(info["relres"] - nrm / np.linalg.norm(f)) <= 1e-12
