@@ -187,67 +187,94 @@ __device__ __forceinline__ double row_of(const double (&col)[S], int p) {
     return readlane_d(v, p & (kWave - 1));
 }
 
-// col <- (I - tau v v^T) col with v = [1 at row p; vt below p] (vt zero at and above p)
+// Reflector p as a register column: zero above row p, 1 on it, the stored tail
+// (rows p+1 .. s-1 of vp) below.  live = false gives the zero vector.
 template <int S>
-__device__ __forceinline__ void apply_reflector(double (&col)[S], const double (&vt)[S], double tau, int p, int lane) {
-    const double head = row_of<S>(col, p);
-    double sd = 0.0;
-#pragma unroll
-    for (int q = 0; q < S; ++q) sd += vt[q] * col[q];
-    sd = (head + wave_sum(sd)) * tau;
+__device__ __forceinline__ void load_reflector(double (&v)[S], const double* vp, int p, int s, int lane, bool live) {
 #pragma unroll
     for (int q = 0; q < S; ++q) {
-        const int i = lane + q * kWave;
-        if (i == p) col[q] = head - sd;
-        else col[q] -= sd * vt[q];
+        const int r = lane + q * kWave;
+        const double x = vp[min(r, s - 1)];  // unconditional load (no branch around it), row clamped into the column
+        v[q] = !live ? 0.0 : (r > p && r < s) ? x : (r == p ? 1.0 : 0.0);
     }
 }
 
-// The same reflector applied to the first `ncol` of CB register-resident
-// columns; the CB dot products and their DPP reductions are interleaved so
-// their latencies overlap.  Per column the arithmetic equals apply_reflector.
-template <int S, int CB>
-__device__ __forceinline__ void apply_reflector_cols(double (&col)[CB][S], const double (&vt)[S], double tau, int p,
-                                                     int lane, int i0, int ncol) {
-    double head[CB], sd[CB];
+// col[i] <- (I - tau v v^T) col[i] for the register-resident columns i >= I0.
+// v carries its unit entry, so neither the dot product nor the update needs a
+// special row; the reductions of the columns are interleaved so that their
+// latencies overlap.
+template <int I0, int S, int CB>
+__device__ __forceinline__ void apply_reflector_cols(double (&col)[CB][S], const double (&v)[S], double tau) {
+    double sd[CB];
 #pragma unroll
-    for (int i = 0; i < CB; ++i) {
-        head[i] = 0.0;
-        sd[i] = 0.0;
-        if (i >= i0 && i < ncol) {
-            double hl = 0.0;
+    for (int i = I0; i < CB; ++i) {
+        double a = 0.0;
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
-                if (q == (p >> 6)) hl = col[i][q];
-                sd[i] += vt[q] * col[i][q];
-            }
-            head[i] = readlane_d(hl, p & (kWave - 1));
-        }
+        for (int q = 0; q < S; ++q) a += v[q] * col[i][q];
+        sd[i] = a;
     }
-    // interleaved wave sums (same step order as wave_sum)
+    // interleaved wave sums (the step order of wave_sum)
 #pragma unroll
-    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0xb1, 0xf>(sd[i]);
+    for (int i = I0; i < CB; ++i) sd[i] = dpp_add<0xb1, 0xf>(sd[i]);
 #pragma unroll
-    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x4e, 0xf>(sd[i]);
+    for (int i = I0; i < CB; ++i) sd[i] = dpp_add<0x4e, 0xf>(sd[i]);
 #pragma unroll
-    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x141, 0xf>(sd[i]);
+    for (int i = I0; i < CB; ++i) sd[i] = dpp_add<0x141, 0xf>(sd[i]);
 #pragma unroll
-    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x140, 0xf>(sd[i]);
+    for (int i = I0; i < CB; ++i) sd[i] = dpp_add<0x140, 0xf>(sd[i]);
 #pragma unroll
-    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x142, 0xa>(sd[i]);
+    for (int i = I0; i < CB; ++i) sd[i] = dpp_add<0x142, 0xa>(sd[i]);
 #pragma unroll
-    for (int i = 0; i < CB; ++i) sd[i] = dpp_add<0x143, 0xc>(sd[i]);
+    for (int i = I0; i < CB; ++i) sd[i] = dpp_add<0x143, 0xc>(sd[i]);
 #pragma unroll
-    for (int i = 0; i < CB; ++i) {
-        if (i >= i0 && i < ncol) {
-            const double t = (head[i] + readlane_d(sd[i], kWave - 1)) * tau;
+    for (int i = I0; i < CB; ++i) {
+        const double t = readlane_d(sd[i], kWave - 1) * tau;
+#pragma unroll
+        for (int q = 0; q < S; ++q) col[i][q] -= t * v[q];
+    }
+}
+
+// Factor the held column I (global column c0 + I, if below dc): its reflector
+// is written to C and tau, and applied at once to the held columns after it;
+// then the next held column.  Unrolled at compile time over I.
+template <int I, int S, int CB>
+__device__ __forceinline__ void factor_held(double (&col)[CB][S], int c0, int dc, int s, int lane,
+                                            double* __restrict__ C, double* __restrict__ tau) {
+    if constexpr (I < CB) {
+        const int c = c0 + I;
+        if (c < dc) {
+            double xl = 0.0;
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const int r = lane + q * kWave;
-                if (r == p) col[i][q] = head[i] - t;
-                else col[i][q] -= t * vt[q];
+                if (r > c) xl += col[I][q] * col[I][q];
             }
+            const double xn2 = wave_sum(xl);
+            const double alpha = row_of<S>(col[I], c);
+            double beta, tc, sc;
+            if (xn2 == 0.0) {  // identity reflector
+                beta = alpha;
+                tc = 0.0;
+                sc = 1.0;
+            } else {
+                const double nrm = sqrt(alpha * alpha + xn2);
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                tc = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
+            }
+            double v[S];
+            double* dst = C + static_cast<int64_t>(c) * s;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                const double tail = col[I][q] * sc;
+                if (r < s) dst[r] = (r < c) ? col[I][q] : (r == c ? beta : tail);
+                v[q] = (r > c) ? tail : (r == c ? 1.0 : 0.0);
+            }
+            if (lane == 0) tau[c] = tc;
+            if (tc != 0.0) apply_reflector_cols<I + 1, S, CB>(col, v, tc);
         }
+        factor_held<I + 1, S, CB>(col, c0, dc, s, lane, C, tau);
     }
 }
 
@@ -263,16 +290,17 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
     const int lane = threadIdx.x & (kWave - 1);
     const int c0 = (blockIdx.x * kPipeWaves + threadIdx.x / kWave) * CB;
     if (c0 > dc) return;
-    const int ncol = min(CB, dc + 1 - c0);  // columns held (column dc is g)
+    const int ncol = min(CB, dc + 1 - c0);  // columns held (column dc is g); the rest stay zero
     double col[CB][S];
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
-        const int c = c0 + i;
+        const int c = min(c0 + i, dc);  // columns past dc read g and are then zeroed
         const double* src = (c < dc) ? C + static_cast<int64_t>(c) * s : g;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const int r = lane + q * kWave;
-            col[i][q] = (i < ncol && r < s) ? src[r] : 0.0;
+            const double x = src[min(r, s - 1)];
+            col[i][q] = (i < ncol && r < s) ? x : 0.0;
         }
     }
 
@@ -296,70 +324,21 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        double vt[kBatch][S];
+        double v[kBatch][S];
         double tb[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const int p = p0 + b;
             tb[b] = (p < pend) ? tau[p] : 0.0;
-            const double* vp = C + static_cast<int64_t>(p) * s;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int r = lane + q * kWave;
-                vt[b][q] = (p < pend && r > p && r < s) ? vp[r] : 0.0;
-            }
+            load_reflector<S>(v[b], C + static_cast<int64_t>(p) * s, p, s, lane, p < pend);
         }
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const int p = p0 + b;
-            if (p < pend && tb[b] != 0.0) apply_reflector_cols<S, CB>(col, vt[b], tb[b], p, lane, 0, ncol);
-        }
+        for (int b = 0; b < kBatch; ++b)
+            if (tb[b] != 0.0) apply_reflector_cols<0, S, CB>(col, v[b], tb[b]);
     }
 
     // local factorisation of the held columns below dc
-#pragma unroll
-    for (int i = 0; i < CB; ++i) {
-        const int c = c0 + i;
-        if (i < ncol && c < dc) {
-            double xl = 0.0;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int r = lane + q * kWave;
-                if (r > c && r < s) xl += col[i][q] * col[i][q];
-            }
-            const double xn2 = wave_sum(xl);
-            const double alpha = row_of<S>(col[i], c);
-            double beta, tc, sc;
-            if (xn2 == 0.0) {
-                beta = alpha;
-                tc = 0.0;
-                sc = 1.0;
-            } else {
-                const double nrm = sqrt(alpha * alpha + xn2);
-                beta = (alpha >= 0.0) ? -nrm : nrm;
-                tc = (beta - alpha) / beta;
-                sc = 1.0 / (alpha - beta);
-            }
-            double vt[S];
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int r = lane + q * kWave;
-                double v = col[i][q];
-                if (r == c) v = beta;
-                else if (r > c && tc != 0.0) v = col[i][q] * sc;
-                col[i][q] = v;
-                vt[q] = (r > c && r < s) ? v : 0.0;
-            }
-            double* dst = C + static_cast<int64_t>(c) * s;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int r = lane + q * kWave;
-                if (r < s) dst[r] = col[i][q];
-            }
-            if (lane == 0) tau[c] = tc;
-            if (tc != 0.0) apply_reflector_cols<S, CB>(col, vt, tc, c, lane, i + 1, ncol);
-        }
-    }
+    factor_held<0, S, CB>(col, c0, dc, s, lane, C, tau);
     if (c0 < dc && lane == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(&sync->npub, static_cast<unsigned>(min(c0 + CB, dc)), __ATOMIC_RELAXED,
