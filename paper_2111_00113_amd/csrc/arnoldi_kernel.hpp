@@ -266,12 +266,12 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                         if (cc >= row_lo && cc < row_hi) {
                             bv = bst[cc - row_lo];
                         } else if (j == 0) {
-                            bv = from_basis<TC>(bj[cc]);
+                            bv = from_basis<TC>(load_coherent(bj + cc));
                         } else {
-                            TC t = wbuf[cc];
+                            TC t = load_coherent(wbuf + cc);
                             for (int a = 0; a < kwp; ++a)
                                 t = gs_sub(t, static_cast<TC>(h2p[a]),
-                                           from_basis<TC>(Bp[cc - static_cast<int64_t>(a) * p.ldb]));
+                                           from_basis<TC>(load_coherent(Bp + cc - static_cast<int64_t>(a) * p.ldb)));
                             bv = from_basis<TC>(to_basis<TS>(t / nup));
                         }
                         m[r] += v[r] * bv;
@@ -292,9 +292,15 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                         v[r] = Av[e];
                     }
                 }
+                // own rows of b_j were stored by this block; other blocks' rows
+                // are read device-coherently (the barriers take no acquire)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (q < sK[r]) m[r] += v[r] * from_basis<TC>(bj[c[r]]);
+                    if (q < sK[r]) {
+                        const int cc = c[r];
+                        const TS bv = (cc >= row_lo && cc < row_hi) ? bj[cc] : load_coherent(bj + cc);
+                        m[r] += v[r] * from_basis<TC>(bv);
+                    }
             }
         }
         dots_to_partials(m, j, kw, p.part_a);
@@ -315,7 +321,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         __syncthreads();
         block_sketch(0, sk_cut1, sk_dst);
         tick(1);
-        bar.wait();
+        bar.wait_relaxed();
         tick(2);
 
         // ---- phase 2: h, w = m - W h, partial dots ------------------------
@@ -347,14 +353,14 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-                if (row < n) wbuf[row] = w[r];
+                if (row < n) store_stream(wbuf + row, w[r]);
             }
         }
         dots_to_partials(w, j, kw, p.part_b);
         tick(3);
         bar.arrive();
         block_sketch(sk_cut1, sk_cut2, sk_dst);  // second third
-        bar.wait();
+        bar.wait_relaxed();
         tick(4);
 
         // ---- phase 3: h2, nu, b_{j+1} -------------------------------------
@@ -404,7 +410,12 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         for (int r = 0; r < R; ++r) {
             const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
             const TS st = to_basis<TS>(bnew[r] / nu_t);
-            if (row < n) bn[row] = st;
+            if (row < n) {
+                // the halo mode gathers own rows from LDS: nothing rereads the
+                // column from L2 in the next step
+                if constexpr (HALO) store_stream(bn + row, st);
+                else bn[row] = st;
+            }
             bnew[r] = from_basis<TC>(st);
         }
         if constexpr (KW > 0) {
@@ -426,7 +437,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         } else {
             bar.arrive();
             block_sketch(sk_cut2, s, sk_dst);  // last third
-            bar.wait();
+            bar.wait_relaxed();
         }
         tick(6);
     }

@@ -178,16 +178,48 @@ __device__ __forceinline__ void block_sum(const double (&vals)[NV], int nv, doub
     __syncthreads();
 }
 
+// Loads of values that other workgroups stored before the last grid barrier.
+// They are device-coherent (relaxed agent-scope atomic loads, which bypass the
+// CU's L1 and a stale copy in this XCD's L2), so a barrier whose readers use
+// them needs no acquire fence: the cache invalidation that fence performs costs
+// about 1.7 us per barrier on this chip.  A workgroup's own earlier stores are
+// visible to it through the ordinary path.
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+__device__ __forceinline__ float load_coherent(const float* p) {
+    return __uint_as_float(
+        __hip_atomic_load(reinterpret_cast<unsigned*>(const_cast<float*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ bf16_t load_coherent(const bf16_t* p) {
+    // the aligned 32-bit word holding the value
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    const unsigned w = __hip_atomic_load(reinterpret_cast<unsigned*>(a & ~static_cast<uintptr_t>(3)), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return bf16_t{static_cast<uint16_t>((a & 2) ? (w >> 16) : (w & 0xffffu))};
+}
+
+// Stores of streamed outputs (basis columns, the halo buffer): non-temporal,
+// so they do not linger as dirty L2 lines that the next grid barrier's
+// release has to write back.
+__device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(bf16_t* p, bf16_t v) {
+    __builtin_nontemporal_store(v.bits, reinterpret_cast<uint16_t*>(p));
+}
+
 // This lane's share of sum_g col[g]: g = lane, lane + 64, ... < G, added in g
-// order.  The loads are issued four at a time before the adds, so a sum over
-// data just written by other workgroups waits for one memory round trip per
-// 256 entries rather than one per 64.
+// order.  The partials were stored by other workgroups before a grid barrier
+// and are read device-coherently.  The loads are issued four at a time before
+// the adds, so the sum waits for one memory round trip per 256 entries rather
+// than one per 64.
 __device__ __forceinline__ double lane_strided_sum(const double* col, int G, int lane) {
     double acc = 0.0;
     for (int g0 = lane; g0 < G; g0 += 4 * kWave) {
         double t[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = (g0 + u * kWave < G) ? col[g0 + u * kWave] : 0.0;
+        for (int u = 0; u < 4; ++u) t[u] = (g0 + u * kWave < G) ? load_coherent(col + g0 + u * kWave) : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (g0 + u * kWave < G) acc += t[u];
@@ -311,6 +343,15 @@ struct GridSync {
             spin_ge(&w->gen, seq);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        __syncthreads();
+    }
+
+    // wait() without the acquire fence: afterwards the block may read other
+    // blocks' stores from before their arrival only through load_coherent.
+    // (The releases are unchanged; loads issued after the generation word is
+    // seen reach the device-coherent level, where those stores already are.)
+    __device__ __forceinline__ void wait_relaxed() {
+        if (threadIdx.x == 0) spin_ge(&w->gen, seq);
         __syncthreads();
     }
 

@@ -330,7 +330,8 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
         for (int b = 0; b < kBatch; ++b) {
             const int p = p0 + b;
             tb[b] = (p < pend) ? tau[p] : 0.0;
-            load_reflector<S>(v[b], C + static_cast<int64_t>(p) * s, p, s, lane, p < pend);
+            // past the batch: a zero reflector (the address stays inside column pend - 1)
+            load_reflector<S>(v[b], C + static_cast<int64_t>(min(p, pend - 1)) * s, p, s, lane, p < pend);
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b)
