@@ -156,26 +156,62 @@ __global__ __launch_bounds__(kLsqBlock) void lsq_batched_kernel(int s, const Bat
 }
 
 // ---------------------------------------------------------------------------
-// Blocked column-owner pipeline (s <= 64*S): wavefront w keeps columns
-// [w*CB, w*CB + CB) of C -- column dc stands for g -- in registers for the
-// whole factorisation.  It applies the reflectors of earlier wavefronts in
-// order as they are published, factors its own columns locally (each new
-// reflector applied at once to its later columns), writes them back (T entries
-// above the diagonal, beta on it, the reflector tail below) and publishes them
-// by raising a counter.  Every column therefore sees the reflectors in the
-// same order as in the one-workgroup kernel above.  The wavefront holding g
-// finishes with the kappa guard, the back substitution and the residual
-// estimate.  Launched cooperatively (all wavefronts resident); every wait is
-// bounded by a real-time limit.
+// Column-owner pipeline (s <= 64 S).  Wavefront w keeps columns
+// [CB w, CB w + CB) of C -- column dc stands for g -- in registers for the
+// whole factorisation; a workgroup holds kPipeWaves consecutive wavefronts, so
+// BC = kPipeWaves CB consecutive columns.  A wavefront applies, in order, the
+// reflectors of the earlier workgroups (announced by a device-wide counter and
+// loaded from C) and then those of the earlier wavefronts of its own workgroup
+// (announced one by one by a counter in LDS and read from an LDS copy), and
+// factors its own columns: each new reflector is copied to LDS and announced at
+// once, written to C, and applied to the wavefront's later columns.  Every
+// column thus sees the reflectors in the order of the one-workgroup kernel
+// above, and a hand-over between wavefronts of one workgroup costs an LDS
+// round trip instead of a device-wide release and acquire.  When its columns
+// are done a wavefront publishes them device-wide, in wavefront order (it
+// first waits for its predecessor's publication, so its release covers every
+// earlier reflector).  The wavefront holding g finishes with the kappa guard,
+// the back substitution and the residual estimate.  Launched cooperatively
+// (all wavefronts resident); every wait is bounded by a real-time limit.
 // ---------------------------------------------------------------------------
-constexpr int kPipeWaves = 4;
+constexpr int kPipeWaves = 8;
 constexpr int kPipeBlock = kPipeWaves * kWave;
-constexpr int kPipeCols = 8;  // columns per wavefront
+constexpr int kPipeCols = 4;                     // columns per wavefront
+constexpr int kPipeBC = kPipeWaves * kPipeCols;  // columns per workgroup
 
 struct LsqSync {
-    unsigned npub;  // reflectors published (monotone, in order)
+    unsigned npub;  // reflectors published device-wide (monotone, in order)
     unsigned pad[63];
 };
+
+// Bounded waits for *p >= target; false (abort raised or seen) on time-out.
+__device__ __forceinline__ bool lsq_spin_global(unsigned* p, unsigned target, int* abort, uint64_t limit) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+__device__ __forceinline__ unsigned lsq_spin_lds(unsigned* p, unsigned target, int* abort, uint64_t limit) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    unsigned v;
+    unsigned it = 0;
+    while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < target) {
+        if ((++it & 255u) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    return v;
+}
 
 // row p of a register-resident column (row p lives in lane p % 64, slot p / 64)
 template <int S>
@@ -194,8 +230,11 @@ __device__ __forceinline__ void load_reflector(double (&v)[S], const double* vp,
 #pragma unroll
     for (int q = 0; q < S; ++q) {
         const int r = lane + q * kWave;
-        const double x = vp[min(r, s - 1)];  // unconditional load (no branch around it), row clamped into the column
-        v[q] = !live ? 0.0 : (r > p && r < s) ? x : (r == p ? 1.0 : 0.0);
+        // the load is used unconditionally (a 0/1 factor rather than a select),
+        // so the compiler cannot sink it into a branch with its own wait; the
+        // row is clamped into the column
+        const double x = vp[min(r, s - 1)];
+        v[q] = x * ((live && r > p && r < s) ? 1.0 : 0.0) + ((live && r == p) ? 1.0 : 0.0);
     }
 }
 
@@ -234,12 +273,24 @@ __device__ __forceinline__ void apply_reflector_cols(double (&col)[CB][S], const
     }
 }
 
-// Factor the held column I (global column c0 + I, if below dc): its reflector
-// is written to C and tau, and applied at once to the held columns after it;
-// then the next held column.  Unrolled at compile time over I.
+// LDS of the pipeline workgroup: the reflectors of its BC columns in register
+// layout (slot q of lane l at (p * S + q) * 64 + l), their tau, and the count
+// of reflectors announced.
+template <int S>
+struct PipeLds {
+    double* refl;
+    double* tau;
+    unsigned* pub;
+    int bstart;  // first column of the workgroup
+};
+
+// Factor the held column I (global column c0 + I, if below dc): the new
+// reflector goes to LDS and is announced, then to C and tau, and is applied at
+// once to the held columns after it; then the next held column.  Unrolled at
+// compile time over I.
 template <int I, int S, int CB>
 __device__ __forceinline__ void factor_held(double (&col)[CB][S], int c0, int dc, int s, int lane,
-                                            double* __restrict__ C, double* __restrict__ tau) {
+                                            double* __restrict__ C, double* __restrict__ tau, const PipeLds<S>& L) {
     if constexpr (I < CB) {
         const int c = c0 + I;
         if (c < dc) {
@@ -263,18 +314,29 @@ __device__ __forceinline__ void factor_held(double (&col)[CB][S], int c0, int dc
                 sc = 1.0 / (alpha - beta);
             }
             double v[S];
+            double* lv = L.refl + static_cast<int64_t>(c - L.bstart) * S * kWave;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int r = lane + q * kWave;
+                v[q] = (r > c) ? col[I][q] * sc : (r == c ? 1.0 : 0.0);
+                lv[q * kWave + lane] = v[q];
+            }
+            if (lane == 0) L.tau[c - L.bstart] = tc;
+            // announce to the later wavefronts of this workgroup (LDS order only;
+            // the global stores below need not have landed)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            if (lane == 0) __hip_atomic_store(L.pub, static_cast<unsigned>(c + 1), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
             double* dst = C + static_cast<int64_t>(c) * s;
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const int r = lane + q * kWave;
-                const double tail = col[I][q] * sc;
-                if (r < s) dst[r] = (r < c) ? col[I][q] : (r == c ? beta : tail);
-                v[q] = (r > c) ? tail : (r == c ? 1.0 : 0.0);
+                if (r < s) dst[r] = (r < c) ? col[I][q] : (r == c ? beta : v[q]);
             }
             if (lane == 0) tau[c] = tc;
             if (tc != 0.0) apply_reflector_cols<I + 1, S, CB>(col, v, tc);
         }
-        factor_held<I + 1, S, CB>(col, c0, dc, s, lane, C, tau);
+        factor_held<I + 1, S, CB>(col, c0, dc, s, lane, C, tau, L);
     }
 }
 
@@ -286,12 +348,20 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
                                                                   int* __restrict__ iout, LsqSync* sync, int* abort,
                                                                   uint64_t limit) {
     constexpr int CB = kPipeCols;
+    extern __shared__ double lds[];
+    __shared__ unsigned lpub;
     const int dc = dc_dev ? *dc_dev : dc_host;
     const int lane = threadIdx.x & (kWave - 1);
-    const int c0 = (blockIdx.x * kPipeWaves + threadIdx.x / kWave) * CB;
+    const int bstart = blockIdx.x * kPipeBC;
+    const int c0 = bstart + (threadIdx.x / kWave) * CB;
+    if (threadIdx.x == 0) lpub = static_cast<unsigned>(bstart);
+    __syncthreads();
     if (c0 > dc) return;
+    const PipeLds<S> L{lds, lds + kPipeBC * S * kWave, &lpub, bstart};
     const int ncol = min(CB, dc + 1 - c0);  // columns held (column dc is g); the rest stay zero
     double col[CB][S];
+    // all loads issued together: addresses clamped into valid columns and the
+    // values kept by a 0/1 factor, so no load sits behind a branch
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
         const int c = min(c0 + i, dc);  // columns past dc read g and are then zeroed
@@ -299,18 +369,17 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const int r = lane + q * kWave;
-            const double x = src[min(r, s - 1)];
-            col[i][q] = (i < ncol && r < s) ? x : 0.0;
+            col[i][q] = src[min(r, s - 1)] * ((i < ncol && r < s) ? 1.0 : 0.0);
         }
     }
 
-    // reflectors of earlier wavefronts, applied in order as they are published;
-    // kBatch of them are loaded together so their loads overlap
+    // reflectors of earlier workgroups, applied in order as they are published
+    // device-wide; kBatch of them are loaded together so their loads overlap
     constexpr int kBatch = 4;
-    const int pmax = min(c0, dc);
+    const int pext = min(bstart, dc);
     unsigned avail = 0;
-    for (int p0 = 0; p0 < pmax; p0 += kBatch) {
-        const int pend = min(p0 + kBatch, pmax);
+    for (int p0 = 0; p0 < pext; p0 += kBatch) {
+        const int pend = min(p0 + kBatch, pext);
         if (static_cast<unsigned>(pend) > avail) {
             const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
             while ((avail = __hip_atomic_load(&sync->npub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
@@ -329,7 +398,7 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const int p = p0 + b;
-            tb[b] = (p < pend) ? tau[p] : 0.0;
+            tb[b] = (p < pend) ? tau[min(p, pend - 1)] : 0.0;
             // past the batch: a zero reflector (the address stays inside column pend - 1)
             load_reflector<S>(v[b], C + static_cast<int64_t>(min(p, pend - 1)) * s, p, s, lane, p < pend);
         }
@@ -338,9 +407,30 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
             if (tb[b] != 0.0) apply_reflector_cols<0, S, CB>(col, v[b], tb[b]);
     }
 
+    // reflectors of the earlier wavefronts of this workgroup, from LDS as they
+    // are announced
+    const int pown = min(c0, dc);
+    unsigned seen = static_cast<unsigned>(bstart);
+    for (int p = bstart; p < pown; ++p) {
+        if (seen <= static_cast<unsigned>(p)) {
+            seen = lsq_spin_lds(&lpub, static_cast<unsigned>(p + 1), abort, limit);
+            if (seen == 0) return;
+        }
+        const double* lv = L.refl + static_cast<int64_t>(p - bstart) * S * kWave;
+        double v[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) v[q] = lv[q * kWave + lane];
+        const double tp = L.tau[p - bstart];
+        if (tp != 0.0) apply_reflector_cols<0, S, CB>(col, v, tp);
+    }
+
     // local factorisation of the held columns below dc
-    factor_held<0, S, CB>(col, c0, dc, s, lane, C, tau);
+    factor_held<0, S, CB>(col, c0, dc, s, lane, C, tau, L);
+    // device-wide publication in wavefront order: after the predecessor's, one
+    // release covers this wavefront's stores and (already written back) all
+    // earlier ones
     if (c0 < dc && lane == 0) {
+        if (!lsq_spin_global(&sync->npub, static_cast<unsigned>(c0), abort, limit)) return;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(&sync->npub, static_cast<unsigned>(min(c0 + CB, dc)), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -348,6 +438,12 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
     if (dc >= c0 + CB) return;
 
     // ---- holder of g: Q^T g out, kappa guard, back substitution, r_est --------
+    // every earlier reflector published device-wide, then visible here
+    {
+        const bool ok = lsq_spin_global(&sync->npub, static_cast<unsigned>(c0), abort, limit);
+        if (!ok) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     double z[S];
 #pragma unroll
     for (int i = 0; i < CB; ++i)
@@ -359,24 +455,66 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
         const int r = lane + q * kWave;
         if (r < s) g[r] = z[q];
     }
-    // diagonal of T, one entry per lane-slot (all loads in flight together)
-    double dg[S];
+    // diagonal of T, one entry per lane-slot (all loads in flight together;
+    // entries past dc repeat T_{dc-1,dc-1} and are never consulted)
+    double dg[S], rinv[S];
+    const int jlast = max(dc - 1, 0);
 #pragma unroll
     for (int q = 0; q < S; ++q) {
-        const int j = lane + q * kWave;
-        dg[q] = (j < dc) ? fabs(C[static_cast<int64_t>(j) * s + j]) : 0.0;
+        const int jj = min(lane + q * kWave, jlast);
+        const double t = C[static_cast<int64_t>(jj) * s + jj];
+        dg[q] = fabs(t);
+        rinv[q] = 1.0 / t;  // for the back substitution (inf where T_jj = 0: past d_eff)
     }
-    int d_eff = 0;
-    double tmax = 0.0, tmin = INFINITY, kap = 0.0;
-    for (int j = 0; j < dc; ++j) {
-        const double a = row_of<S>(dg, j);
-        const double nmax = a > tmax ? a : tmax;
-        const double nmin = a < tmin ? a : tmin;
-        if (!(nmin > 0.0) || nmax / nmin > kappa_max) break;
-        tmax = nmax;
-        tmin = nmin;
-        kap = tmax / tmin;
-        d_eff = j + 1;
+    // kappa guard: d_eff is the first j whose prefix 0..j has a zero diagonal
+    // entry or max/min > kappa_max (dc if none).  Prefix max and min by a wave
+    // scan per slot, carried across slots; the first violation by ballot.
+    int d_eff = dc;
+    double kap = 0.0;
+    {
+        double cmax = 0.0, cmin = INFINITY;
+        double pmx[S], pmn[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            double mx = dg[q], mn = dg[q];
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const double omx = __shfl_up(mx, off, kWave);
+                const double omn = __shfl_up(mn, off, kWave);
+                if (lane >= off) {
+                    mx = omx > mx ? omx : mx;
+                    mn = omn < mn ? omn : mn;
+                }
+            }
+            mx = cmax > mx ? cmax : mx;
+            mn = cmin < mn ? cmin : mn;
+            pmx[q] = mx;
+            pmn[q] = mn;
+            cmax = readlane_d(mx, kWave - 1);
+            cmin = readlane_d(mn, kWave - 1);
+        }
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int j = lane + q * kWave;
+            const bool bad = j < dc && (!(pmn[q] > 0.0) || pmx[q] / pmn[q] > kappa_max);
+            const unsigned long long m = __ballot(bad);
+            if (!found && m != 0ull) {
+                found = true;
+                d_eff = q * kWave + __ffsll(static_cast<long long>(m)) - 1;
+            }
+        }
+        if (d_eff > 0) {
+            const int jk = d_eff - 1;
+            double a = pmx[0], b = pmn[0];
+#pragma unroll
+            for (int q = 1; q < S; ++q)
+                if ((jk >> 6) == q) {
+                    a = pmx[q];
+                    b = pmn[q];
+                }
+            kap = readlane_d(a, jk & (kWave - 1)) / readlane_d(b, jk & (kWave - 1));
+        }
     }
     double rl = 0.0;
 #pragma unroll
@@ -385,41 +523,37 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
         if (r >= d_eff && r < s) rl += z[q] * z[q];
     }
     const double rest = sqrt(wave_sum(rl));
-    // back substitution, column-oriented; the next columns of T are fetched
-    // kPrefetch steps ahead so the loads overlap the updates
-    constexpr int kPrefetch = 4;
-    double tc[kPrefetch][S];
-    double td[kPrefetch];
+    // back substitution T y = z, column-oriented: y_i = z_i (1 / T_ii), the
+    // reciprocals formed in parallel beforehand so no division sits on the
+    // serial chain; then z -= T[:, i] y_i over the slots holding rows below
+    // row i's slot (rows i and below are no longer read, so whole slots are
+    // updated without row masks).  The loops run over slots at compile time,
+    // so z_i is read straight from its register.  Columns of T sit in a ring of
+    // 8 (column i in entry i mod 8), each refilled with column i - 8 right after
+    // use; loads are unconditional (clamped to column 0 past the end).
+    constexpr int kRing = 8;
+    double tc[kRing][S];
+    auto load_tcol = [&](int i, double (&dst)[S]) {
+        const double* cp = C + static_cast<int64_t>(max(i, 0)) * s;
 #pragma unroll
-    for (int f = 0; f < kPrefetch; ++f) {
-        const int i = d_eff - 1 - f;
+        for (int q = 0; q < S; ++q) dst[q] = cp[min(lane + q * kWave, s - 1)];
+    };
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int r = lane + q * kWave;
-            tc[f][q] = (i >= 0 && r < i) ? C[static_cast<int64_t>(i) * s + r] : 0.0;
-        }
-        td[f] = (i >= 0) ? C[static_cast<int64_t>(i) * s + i] : 1.0;
-    }
-    for (int i0 = d_eff - 1; i0 >= 0; i0 -= kPrefetch) {
+    for (int u = 0; u < kRing; ++u) load_tcol(((d_eff - 1 - u) >> 3) * kRing + u, tc[u]);
 #pragma unroll
-        for (int f = 0; f < kPrefetch; ++f) {
-            const int i = i0 - f;
-            if (i >= 0) {
-                const double zi = row_of<S>(z, i);
-                const double yi = zi / td[f];
-                if (lane == 0) y[i] = yi;
+    for (int q = S - 1; q >= 0; --q) {
+        for (int gq = min((d_eff - 1) >> 3, 8 * q + 7); gq >= 8 * q; --gq) {
 #pragma unroll
-                for (int q = 0; q < S; ++q)
-                    if (lane + q * kWave < i) z[q] -= tc[f][q] * yi;
+            for (int u = kRing - 1; u >= 0; --u) {
+                const int i = kRing * gq + u;
+                if (i < d_eff) {
+                    const double yi = readlane_d(z[q], i & (kWave - 1)) * readlane_d(rinv[q], i & (kWave - 1));
+                    if (lane == 0) y[i] = yi;
+#pragma unroll
+                    for (int qq = 0; qq <= q; ++qq) z[qq] -= tc[u][qq] * yi;
+                }
+                load_tcol(i - kRing, tc[u]);
             }
-            // refill slot f with column i - kPrefetch
-            const int inext = i - kPrefetch;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int r = lane + q * kWave;
-                tc[f][q] = (inext >= 0 && r < inext) ? C[static_cast<int64_t>(inext) * s + r] : 0.0;
-            }
-            td[f] = (inext >= 0) ? C[static_cast<int64_t>(inext) * s + inext] : 1.0;
         }
     }
     if (lane == 0) {
@@ -452,18 +586,21 @@ hipError_t launch_lsq_pipeline(int s, int d_max, const int* dc_dev, int dc_host,
                                uint64_t limit, hipStream_t stream) {
     const int slots = (s + kWave - 1) / kWave;
     const void* fn = nullptr;
-    if (slots <= 1) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<1>);
-    else if (slots <= 2) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<2>);
-    else if (slots <= 4) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<4>);
-    else if (slots <= 8) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<8>);
+    int S = 0;
+    if (slots <= 1) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<1>), S = 1;
+    else if (slots <= 2) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<2>), S = 2;
+    else if (slots <= 4) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<4>), S = 4;
+    else if (slots <= 8) fn = reinterpret_cast<const void*>(lsq_pipeline_kernel<8>), S = 8;
     else return hipErrorInvalidValue;
-    hipError_t err = hipMemsetAsync(sync, 0, sizeof(LsqSync), stream);
+    const size_t lds = sizeof(double) * static_cast<size_t>(kPipeBC) * (S * kWave + 1);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (err != hipSuccess) return err;
-    const int waves = (d_max + 1 + kPipeCols - 1) / kPipeCols;
-    const int blocks = (waves + kPipeWaves - 1) / kPipeWaves;
+    err = hipMemsetAsync(sync, 0, sizeof(LsqSync), stream);
+    if (err != hipSuccess) return err;
+    const int blocks = (d_max + 1 + kPipeBC - 1) / kPipeBC;
     LsqSync* sp = static_cast<LsqSync*>(sync);
     void* args[] = {&s, &dc_dev, &dc_host, &C, &g, &tau, &kappa_max, &y, &dout, &iout, &sp, &abort, &limit};
-    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kPipeBlock), args, 0, stream);
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kPipeBlock), args, static_cast<unsigned>(lds), stream);
 }
 
 }  // namespace sg
