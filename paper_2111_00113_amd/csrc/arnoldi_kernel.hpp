@@ -76,7 +76,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
     int* lcount = lstart + (s + 1);
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
-    __shared__ unsigned sync_lds[2];
+    __shared__ unsigned sync_lds[3];
 
     const int G = gridDim.x;
     const int blk = xcd_logical_block(blockIdx.x, G);
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     const int64_t row_lo = static_cast<int64_t>(blk) * RB;
     const int64_t row_hi = min(n, row_lo + RB);
 
-    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
+    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
     bar.setup(sync_lds);
 

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
     int* lcount = lstart + (s + 1);
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
-    __shared__ unsigned sync_lds[2];
+    __shared__ unsigned sync_lds[3];
     __shared__ double unit_scale;
 
     const int G = gridDim.x;
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     TS* Bs = static_cast<TS*>(p.B);
     const TC cc = static_cast<TC>(p.c);
 
-    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u,
+    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
     bar.setup(sync_lds);
 

@@ -248,10 +248,13 @@ __device__ __forceinline__ void grid_sum(const double* partial, int G, int nv, d
 // hardware register): each block adds 1 to its XCD's counter, and the last
 // arriver on an XCD -- by then every block of that XCD has finished its stores
 // into the shared L2 -- issues one agent-scope release (L2 write-back) for the
-// whole XCD and adds 1 to a global counter.  The last XCD publishes the
-// generation number with a release store; waiters poll it and take an
-// agent-scope acquire.  This replaces G serialised L2 write-backs and G
-// contended atomics with 8 of each.  In `per_block_release` mode every block
+// whole XCD and publishes the generation number in its XCD's flag.  Waiters
+// poll the flags of the XCDs holding blocks (one lane per XCD) and take an
+// agent-scope acquire, or none (wait_relaxed) when they read other blocks'
+// data device-coherently.  This replaces G serialised L2 write-backs and G
+// contended atomics with 8 of each, and needs no global counter (measured:
+// 2.66 us per barrier plus a grid sum, against 2.91 us through a global
+// counter and generation word).  In `per_block_release` mode every block
 // also releases before arriving (the textbook protocol), which must give
 // bit-identical results.
 //
@@ -265,8 +268,9 @@ struct SyncWords {
     unsigned reg[16 * 64];   // per-XCD registered blocks, 256 B apart
     unsigned gcount;         // XCD-leader arrivals (+ registrations)
     unsigned pad0[63];
-    unsigned gen;            // published generation
+    unsigned gen;            // unused (kept for the layout of the setup counters)
     unsigned pad1[63];
+    unsigned xflag[16 * 64]; // per-XCD published generation, 256 B apart
 };
 
 __device__ __forceinline__ unsigned xcc_id() {
@@ -282,6 +286,7 @@ struct GridSync {
     unsigned xcc;
     unsigned my_size;  // blocks on this XCD
     unsigned nx;       // XCDs holding at least one block
+    unsigned xmask;    // bit x: XCD x holds at least one block
     unsigned seq;
     bool per_block_release;
 
@@ -298,7 +303,8 @@ struct GridSync {
         return true;
     }
 
-    // Once per launch, by every block: count blocks per XCD (one flat barrier).
+    // Once per launch, by every block: count blocks per XCD (one flat barrier);
+    // lds2: 3 unsigned of LDS.
     __device__ void setup(unsigned* lds2) {
         seq = 0;
         xcc = xcc_id();
@@ -307,15 +313,20 @@ struct GridSync {
             __hip_atomic_fetch_add(&w->gcount, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             spin_ge(&w->gcount, G);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            unsigned k = 0;
+            unsigned k = 0, m = 0;
             for (int i = 0; i < 16; ++i)
-                k += __hip_atomic_load(&w->reg[i * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+                if (__hip_atomic_load(&w->reg[i * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ++k;
+                    m |= 1u << i;
+                }
             lds2[0] = __hip_atomic_load(&w->reg[xcc * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             lds2[1] = k;
+            lds2[2] = m;
         }
         __syncthreads();
         my_size = lds2[0];
         nx = lds2[1];
+        xmask = lds2[2];
         __syncthreads();
     }
 
@@ -329,29 +340,45 @@ struct GridSync {
             const unsigned old =
                 __hip_atomic_fetch_add(&w->xcnt[xcc * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (old + 1 == seq * my_size) {
+                // the XCD's last arriver: one write-back covers its XCD
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                const unsigned o2 =
-                    __hip_atomic_fetch_add(&w->gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // this leader's release above already covers its XCD
-                if (o2 + 1 == G + seq * nx) __hip_atomic_store(&w->gen, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&w->xflag[xcc * 64], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+
+    // wavefront 0 polls the flags of the XCDs holding blocks, lane x for XCD x
+    __device__ __forceinline__ void spin_flags() {
+        if (threadIdx.x < kWave) {
+            const unsigned lane = threadIdx.x;
+            const bool mine = lane < 16 && ((xmask >> lane) & 1u);
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            for (;;) {
+                const unsigned f =
+                    mine ? __hip_atomic_load(&w->xflag[lane * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : seq;
+                if (__all(f >= seq)) break;
+                if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                    if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
         }
     }
 
     __device__ __forceinline__ void wait() {
-        if (threadIdx.x == 0) {
-            spin_ge(&w->gen, seq);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
+        spin_flags();
+        if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
     }
 
     // wait() without the acquire fence: afterwards the block may read other
     // blocks' stores from before their arrival only through load_coherent.
-    // (The releases are unchanged; loads issued after the generation word is
-    // seen reach the device-coherent level, where those stores already are.)
+    // (The releases are unchanged; loads issued after the flags are seen
+    // reach the device-coherent level, where those stores already are.)
     __device__ __forceinline__ void wait_relaxed() {
-        if (threadIdx.x == 0) spin_ge(&w->gen, seq);
+        spin_flags();
         __syncthreads();
     }
 
