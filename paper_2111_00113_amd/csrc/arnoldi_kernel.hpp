@@ -268,10 +268,23 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                         } else if (j == 0) {
                             bv = from_basis<TC>(load_coherent(bj + cc));
                         } else {
+                            // w is rewritten every step: read device-coherently.  A
+                            // basis column is written once per cycle, before any
+                            // read of it (and the cycle starts with an acquire), so
+                            // no stale copy can exist: plain loads, which hit this
+                            // XCD's L2 when the owner block shares it.  The first
+                            // four window loads are issued together (addresses
+                            // clamped into valid columns), then consumed in order.
                             TC t = load_coherent(wbuf + cc);
-                            for (int a = 0; a < kwp; ++a)
+                            TS wa[4];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a) wa[a] = Bp[cc - static_cast<int64_t>(min(a, kwp - 1)) * p.ldb];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+                                if (a < kwp) t = gs_sub(t, static_cast<TC>(h2p[a]), from_basis<TC>(wa[a]));
+                            for (int a = 4; a < kwp; ++a)
                                 t = gs_sub(t, static_cast<TC>(h2p[a]),
-                                           from_basis<TC>(load_coherent(Bp + cc - static_cast<int64_t>(a) * p.ldb)));
+                                           from_basis<TC>(Bp[cc - static_cast<int64_t>(a) * p.ldb]));
                             bv = from_basis<TC>(to_basis<TS>(t / nup));
                         }
                         m[r] += v[r] * bv;
