@@ -94,6 +94,16 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     TC* wbuf = static_cast<TC*>(p.wbuf);
     const int64_t row_lo = static_cast<int64_t>(blk) * RB;
     const int64_t row_hi = min(n, row_lo + RB);
+    // A basis column is written once per cycle, before anything reads it, and
+    // the launch begins with an acquire.  When columns start on 256-byte
+    // boundaries (and blocks own whole cache lines of them, RB being a multiple
+    // of 64 rows), no cache line can hold a stale copy of a column's entries:
+    // other blocks' rows of B are then read with plain loads, which hit the
+    // XCD's L2.  Otherwise a line may straddle two columns and be cached before
+    // the later column is written: such reads are device-coherent.
+    const bool fresh =
+        ((reinterpret_cast<uintptr_t>(p.B) | static_cast<uintptr_t>(p.ldb * sizeof(TS))) & 255u) == 0;
+    auto ldB = [&](const TS* q) -> TS { return fresh ? *q : load_coherent(q); };
 
     GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
@@ -268,23 +278,20 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                         } else if (j == 0) {
                             bv = from_basis<TC>(load_coherent(bj + cc));
                         } else {
-                            // w is rewritten every step: read device-coherently.  A
-                            // basis column is written once per cycle, before any
-                            // read of it (and the cycle starts with an acquire), so
-                            // no stale copy can exist: plain loads, which hit this
-                            // XCD's L2 when the owner block shares it.  The first
-                            // four window loads are issued together (addresses
-                            // clamped into valid columns), then consumed in order.
+                            // w is rewritten every step: read device-coherently; the
+                            // window columns as described at ldB.  The first four
+                            // window loads are issued together (addresses clamped
+                            // into valid columns), then consumed in order.
                             TC t = load_coherent(wbuf + cc);
                             TS wa[4];
 #pragma unroll
-                            for (int a = 0; a < 4; ++a) wa[a] = Bp[cc - static_cast<int64_t>(min(a, kwp - 1)) * p.ldb];
+                            for (int a = 0; a < 4; ++a) wa[a] = ldB(Bp + cc - static_cast<int64_t>(min(a, kwp - 1)) * p.ldb);
 #pragma unroll
                             for (int a = 0; a < 4; ++a)
                                 if (a < kwp) t = gs_sub(t, static_cast<TC>(h2p[a]), from_basis<TC>(wa[a]));
                             for (int a = 4; a < kwp; ++a)
                                 t = gs_sub(t, static_cast<TC>(h2p[a]),
-                                           from_basis<TC>(Bp[cc - static_cast<int64_t>(a) * p.ldb]));
+                                           from_basis<TC>(ldB(Bp + cc - static_cast<int64_t>(a) * p.ldb)));
                             bv = from_basis<TC>(to_basis<TS>(t / nup));
                         }
                         m[r] += v[r] * bv;
@@ -306,12 +313,12 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                     }
                 }
                 // own rows of b_j were stored by this block; other blocks' rows
-                // are read device-coherently (the barriers take no acquire)
+                // as described at ldB (the per-step barriers take no acquire)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (q < sK[r]) {
                         const int cc = c[r];
-                        const TS bv = (cc >= row_lo && cc < row_hi) ? bj[cc] : load_coherent(bj + cc);
+                        const TS bv = (cc >= row_lo && cc < row_hi) ? bj[cc] : ldB(bj + cc);
                         m[r] += v[r] * from_basis<TC>(bv);
                     }
             }

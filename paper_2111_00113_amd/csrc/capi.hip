@@ -484,7 +484,10 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     }
     SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
     // B in the basis storage type (allocated in doubles)
-    SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(n) * a.d * basis_elem_bytes(a.precision) + 7) / 8));
+    // columns padded to 128 entries: every column starts on a 256-byte boundary
+    // (the basis kernels then read other blocks' rows through L2)
+    const int64_t ldb = (n + 127) / 128 * 128;
+    SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(ldb) * a.d * basis_elem_bytes(a.precision) + 7) / 8));
     SG_TRY(ensure(ws.SB, ws.SB_cap, static_cast<size_t>(a.s) * a.d));
     SG_TRY(ensure(ws.SAB, ws.SAB_cap, static_cast<size_t>(a.s) * a.d));
     SG_TRY(ensure(ws.H, ws.H_cap, static_cast<size_t>(kk + 1) * a.d));
@@ -558,11 +561,11 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         }
         // the solve needs S A B and g only; S B is not formed
         if (cheb)
-            rc = run_cheb_cycle(ws, a.A, a.d, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, cf, ws.B, n,
+            rc = run_cheb_cycle(ws, a.A, a.d, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, cf, ws.B, ldb,
                                 ws.SB, ws.SAB, ws.colnorm, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release,
                                 ev.on, 0);
         else
-            rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, n,
+            rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, ldb,
                            ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
                            a.spmv_mode);
         if (rc) return rc;
@@ -570,7 +573,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.l1, st));
-        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, n, ws.y, a.x, st, cheb ? ws.colnorm : nullptr,
+        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, ldb, ws.y, a.x, st, cheb ? ws.colnorm : nullptr,
                               a.precision));
         if (ev.on) SG_TRY(hipEventRecord(ev.c1, st));
         ++cycles;

@@ -59,6 +59,8 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     const TC* Av = static_cast<const TC*>(p.val);
     TS* Bs = static_cast<TS*>(p.B);
     const TC cc = static_cast<TC>(p.c);
+    const bool fresh =
+        ((reinterpret_cast<uintptr_t>(p.B) | static_cast<uintptr_t>(p.ldb * sizeof(TS))) & 255u) == 0;
 
     GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
@@ -182,7 +184,12 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
                                   p.part_sk + static_cast<int64_t>(j) * slab, G, blk);
         tick(1);
         if (more) {
-            bar.wait();
+            // no acquire when the columns start on 256-byte boundaries: the
+            // next SpMV gathers column j + 1, written once per cycle before
+            // anything reads it (the launch began with an acquire), and no cache
+            // line then spans two columns, so none can hold a stale copy
+            if (fresh) bar.wait_relaxed();
+            else bar.wait();
             tick(2);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
