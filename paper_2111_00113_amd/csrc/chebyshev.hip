@@ -133,22 +133,33 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
             m[r] = TC(0);
             kmax = max(kmax, sK[r]);
         }
-        for (int q = 0; q < kmax; ++q) {
-            int c[R];
-            TC v[R];
+        // slot q + 1's column and value loads are issued before slot q is
+        // consumed: two slots of loads in flight
+        int c[R], cn[R];
+        TC v[R], vn[R];
+        auto load_slot = [&](int q, int (&cd)[R], TC (&vd)[R]) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                c[r] = 0;
-                v[r] = TC(0);
+                cd[r] = 0;
+                vd[r] = TC(0);
                 if (q < sK[r]) {
                     const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
-                    c[r] = p.ci[e];
-                    v[r] = Av[e];
+                    cd[r] = p.ci[e];
+                    vd[r] = Av[e];
                 }
             }
+        };
+        load_slot(0, c, v);
+        for (int q = 0; q < kmax; ++q) {
+            load_slot(q + 1, cn, vn);
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (q < sK[r]) m[r] += v[r] * from_basis<TC>(bj[c[r]]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                c[r] = cn[r];
+                v[r] = vn[r];
+            }
         }
         const bool more = j + 1 < p.d;
         TC bnext[R];
