@@ -147,7 +147,16 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 
     // ---- init: g partial (S r), b_1 = r/|r| ----------------------------------
     const double beta = *p.beta;
+    // window entries a = 0 .. KW-1 (0 = newest) of the own rows; in the halo
+    // mode the newest one is not held in registers: it is the column staged
+    // in LDS for the SpMV's gathers (bst), read from there
     TC win[KW > 0 ? KW : 1][R];
+    auto Wr = [&](int a, int r) -> TC {
+        if constexpr (HALO) {
+            if (a == 0) return bst[r * BLOCK + tid];
+        }
+        return win[a][r];
+    };
 #pragma unroll
     for (int a = 0; a < (KW > 0 ? KW : 1); ++a)
 #pragma unroll
@@ -193,7 +202,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             for (int a = 0; a < KW; ++a) {
                 TC u = TC(0);
 #pragma unroll
-                for (int r = 0; r < R; ++r) u += win[a][r] * x[r];
+                for (int r = 0; r < R; ++r) u += Wr(a, r) * x[r];
                 v[a + 1] = static_cast<double>(u);
             }
             block_sum<KW + 1>(v, kw + 1, red_tmp, red_out);
@@ -378,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 if (a < kw) {
                     const TC h = static_cast<TC>(coef[1 + a]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) w[r] -= h * win[a][r];
+                    for (int r = 0; r < R; ++r) w[r] -= h * Wr(a, r);
                 }
             }
         } else {
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 if (a < kw) {
                     const TC h = static_cast<TC>(c2[1 + a]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) bnew[r] = gs_sub(bnew[r], h, win[a][r]);
+                    for (int r = 0; r < R; ++r) bnew[r] = gs_sub(bnew[r], h, Wr(a, r));
                 }
             }
         } else {
@@ -461,9 +470,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
             for (int a = KW - 1; a > 0; --a)
 #pragma unroll
-                for (int r = 0; r < R; ++r) win[a][r] = win[a - 1][r];
+                for (int r = 0; r < R; ++r) win[a][r] = Wr(a - 1, r);
 #pragma unroll
-            for (int r = 0; r < R; ++r) win[0][r] = bnew[r];
+            for (int r = 0; r < R; ++r)
+                if constexpr (!HALO) win[0][r] = bnew[r];  // the halo mode stages it in LDS below
         }
         tick(5);
         if constexpr (HALO) {
