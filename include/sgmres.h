@@ -264,9 +264,12 @@ typedef struct {
  * system independently, with the method of sgmres_solve_ex for truncated
  * Arnoldi: the same sketch (keyed by seed, cycle and the row within the system)
  * and the same stopping rule per system, so system i gets what sgmres_solve_ex
- * gives for it alone, up to rounding.  All systems run in one persistent
- * launch per cycle, one workgroup per system; each cycle's kernels are replayed
- * from a captured hipGraph.  opts: zeta, kappa_max, precision (mixed precision
+ * gives for it alone, up to rounding.  Systems of at least 2^19 rows fill the
+ * chip alone: they are solved one after another by the resident kernels of
+ * sgmres_solve_ex.  The others run together, one persistent launch per cycle,
+ * each split into parts of at most 16384 rows taken by workgroups from a queue;
+ * each cycle's kernels are replayed from a captured hipGraph.  opts: zeta,
+ * kappa_max, precision (mixed precision
  * with FP64 refinement as in sgmres_solve_ex), block_size / rows_per_thread
  * (0 = 512 x 4 for batches under 2^20 rows, else chosen by timing the first
  * cycle of each candidate; the choice is kept

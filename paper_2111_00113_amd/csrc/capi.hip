@@ -662,6 +662,7 @@ constexpr int kBatchMinChunk = 1024;  // smallest block * R among the candidates
 constexpr int kBatchMaxChunk = 4096;  // largest
 constexpr size_t kArenaAlign = 256;
 constexpr int64_t kBatchTuneRows = int64_t(1) << 20;  // smaller batches use 512 x 4
+constexpr int64_t kBatchResidentRows = int64_t(1) << 19;  // such systems go to the resident kernels
 constexpr int64_t kBatchPartRows = 16384;              // rows per part of a large system
 
 using BatchKey = std::tuple<int, int, int, int, int, int, int>;
@@ -1167,9 +1168,69 @@ void sgmres_release_workspace(void) {
 
 int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
                          int restarts, const sgmres_options_t* opts, sgmres_batch_result_t* results, void* stream) {
-    std::lock_guard<std::mutex> lock(g_mutex);
-    return batch_solve_locked(nsys, systems, d, k, s, seed, tol, restarts, opts, results,
-                              static_cast<hipStream_t>(stream));
+    // Systems of at least kBatchResidentRows rows fill the chip on their own:
+    // they are solved one after another by the resident basis kernels (as
+    // sgmres_solve_ex would), the rest together by the part-split kernel.
+    const int zeta = (opts && opts->zeta) ? opts->zeta : 8;
+    const int prec = opts ? opts->precision : SGMRES_PREC_FP64;
+    if (prec != SGMRES_PREC_FP64 && prec != SGMRES_PREC_FP32 && prec != SGMRES_PREC_BF16_BASIS) return SGMRES_EINVAL;
+    if (nsys < 0 || (nsys > 0 && !systems) || !(tol >= 0.0) || restarts < 0 || k < 1 || k > kBatchMaxK)
+        return SGMRES_EINVAL;
+    std::vector<int> big, small;
+    for (int i = 0; i < nsys; ++i) {
+        const sgmres_system_t& y = systems[i];
+        if (!csr_ok(&y.A) || !y.b || !y.x || bad_sizes(y.A.n, d, k, s, zeta)) return SGMRES_EINVAL;
+        (y.A.n >= kBatchResidentRows ? big : small).push_back(i);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int all = SGMRES_OK;
+    if (!big.empty()) {
+        // every CSR is checked before anything is solved
+        std::lock_guard<std::mutex> lock(g_mutex);
+        Workspace* wsp = nullptr;
+        int rc = workspace(&wsp);
+        if (rc) return rc;
+        SG_TRY(hipMemsetAsync(&wsp->sc->csr_bad, 0, sizeof(int), st));
+        for (int i = 0; i < nsys; ++i)
+            SG_TRY(launch_csr_check(systems[i].A.n, systems[i].A.nnz, systems[i].A.row_ptr, systems[i].A.col_idx,
+                                    &wsp->sc->csr_bad, st));
+        rc = copy_scalars(*wsp, st);
+        if (rc) return rc;
+        if (wsp->host_sc->csr_bad) return SGMRES_ECSR;
+    }
+    for (int i : big) {
+        sgmres_options_t o{};
+        o.zeta = zeta;
+        o.kappa_max = opts ? opts->kappa_max : 0.0;
+        o.precision = prec;
+        sgmres_info_t info{};
+        const int rc = solve_entry(&systems[i].A, systems[i].b, systems[i].x, d, k, s, seed, tol, restarts, &o,
+                                   &info, stream);
+        if (rc < 0 && rc != SGMRES_ENONFINITE) return rc;
+        if (rc != SGMRES_OK) all = SGMRES_NOT_CONVERGED;
+        if (results) {
+            results[i].status = rc;
+            results[i].cycles = info.cycles;
+            results[i].steps = info.steps;
+            results[i].flags = info.flags;
+            results[i].relres = info.relres;
+        }
+    }
+    if (small.empty()) return all;
+    std::vector<sgmres_system_t> sub(small.size());
+    std::vector<sgmres_batch_result_t> sres(small.size());
+    for (size_t q = 0; q < small.size(); ++q) sub[q] = systems[small[q]];
+    int rc;
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        rc = batch_solve_locked(static_cast<int>(sub.size()), sub.data(), d, k, s, seed, tol, restarts, opts,
+                                sres.data(), st);
+    }
+    if (rc < 0) return rc;
+    if (rc != SGMRES_OK) all = SGMRES_NOT_CONVERGED;
+    if (results)
+        for (size_t q = 0; q < small.size(); ++q) results[small[q]] = sres[q];
+    return all;
 }
 
 const char* sgmres_version(void) { return "sgmres-gfx950 0.1.0"; }

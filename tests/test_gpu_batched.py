@@ -197,3 +197,26 @@ def test_batched_workload_subset(sg, orc):
     for (A, b), r, x in zip(batch, res, xs):
         _, nrm = orc.residual(A, b, x)
         assert nrm / np.linalg.norm(b) <= 1e-10
+
+
+def test_batched_routes_large_systems_to_resident_kernels(sg, orc):
+    """A system of at least 2^19 rows is solved alone by the resident kernels
+    (exactly what sgmres_solve gives), the others together by the part-split
+    kernel; results come back in the caller's order."""
+    big = synth.convection_diffusion(740, (30.0, 10.0))  # n = 547,600
+    small = synth.random_dominant(20000, offdiag=6, seed=2)
+    fb, fs = synth.rhs(big.n, 5), synth.rhs(small.n, 6)
+    dB, dS = sg.DeviceCSR.from_host(big), sg.DeviceCSR.from_host(small)
+    xs = [torch.zeros(small.n, dtype=torch.float64, device=DEV), torch.zeros(big.n, dtype=torch.float64, device=DEV)]
+    print("batch: small n=20000, big n=547600", flush=True)
+    rc, res = sg.sgmres_solve_batched([(dS, _t(fs), xs[0]), (dB, _t(fb), xs[1])], 60, 2, 130, 3, 1e-10, 300)
+    assert rc == sg.OK
+    x1 = torch.zeros(big.n, dtype=torch.float64, device=DEV)
+    rc1, info1 = sg.sgmres_solve(dB, _t(fb), x1, 60, 2, 130, 3, 1e-10, 300)
+    assert rc1 == sg.OK
+    assert torch.equal(xs[1], x1)
+    assert res[1]["cycles"] == info1["cycles"] and res[1]["relres"] == info1["relres"]
+    for (A, f), x, r in zip([(small, fs), (big, fb)], xs, res):
+        _, nrm = orc.residual(A, f, _np(x))
+        assert nrm / np.linalg.norm(f) <= 1e-10
+        assert abs(r["relres"] - nrm / np.linalg.norm(f)) <= 1e-12
