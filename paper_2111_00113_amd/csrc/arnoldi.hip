@@ -32,8 +32,7 @@ KernelFn pick_kernel(int block, int R, int KW, bool sketch_basis, int precision,
 size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta) {
     const int nw = block / kWave;
     const int RB = R * block;
-    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw * kRedSlots + kRedSlots + 2 * k + 3 +
-                                                2 * s * kSketchParts) +
+    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw * kRedSlots + kRedSlots + 2 * k + 3) +
            sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
 }
 

@@ -72,8 +72,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
     double* red_out = red_tmp + NW * kRedSlots;
     double* coef = red_out + kRedSlots;  // [0] <m,m>, [1..k] h ; [k+1] <w,w>, [k+2..2k+1] h2 ; [2k+2] nu
-    double* sk_tmp = coef + 2 * p.k + 3;  // 2s x kSketchParts partial sums
-    int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
+    int* lstart = reinterpret_cast<int*>(coef + 2 * p.k + 3);
     int* lcount = lstart + (s + 1);
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
     __shared__ unsigned sync_lds[3];
@@ -137,9 +136,16 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     // (vector 1) over sketch rows [r0, r1), staged in vals.
     constexpr int sk_v0 = SKB ? 0 : 1;
     constexpr int sk_nv = SKB ? 2 : 1;
+    // (no block synchronisation inside: the wavefronts of a block finish their
+    // pieces independently, the last one first doing the barrier arrival)
     auto block_sketch = [&](int r0, int r1, double* dst) {
-        sketch_lists_apply<BLOCK>(sk_v0, sk_nv, r0, r1, vals, RB, s, lstart, lists, sk_tmp, dst, G, blk);
+        sketch_lists_apply_lanes<BLOCK>(sk_v0, sk_nv, r0, r1, vals, RB, s, lstart, lists, dst, G, blk);
     };
+    // the thread that counts this block's barrier arrivals: one of the last
+    // wavefront, which gets no sketch pieces when a window has at most
+    // BLOCK - 64 of them, so the arrival's atomic round trip and the XCD
+    // write-back are not in front of any sketch work
+    constexpr unsigned kArriver = BLOCK - kWave;
     // the sketch of one step is spread over the barrier windows (three, or two
     // in the halo mode)
     const int sk_cut1 = HALO ? s / 2 : s / 3;
@@ -174,8 +180,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         vals[r * BLOCK + tid] = rv;
     }
     __syncthreads();
-    sketch_lists_apply<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, sk_tmp,
-                              p.part_sk + static_cast<int64_t>(p.d) * slab, G, blk);  // g partials after the d step slabs
+    // g partials after the d step slabs
+    sketch_lists_apply_lanes<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, p.part_sk + static_cast<int64_t>(p.d) * slab,
+                                    G, blk);
     bar.sync();  // B[:,0] and the g partials are complete
     if constexpr (HALO) {
 #pragma unroll
@@ -352,10 +359,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             }
         }
         dots_to_partials(m, j, kw, p.part_a);
-        tick(0);
-        bar.arrive();
-        // block sketch partials of b_j and m_j, first third, overlap the barrier
-        double* sk_dst = p.part_sk + static_cast<int64_t>(j) * slab;
+        // stage b_j and m_j for the sketch (published by the arrival's block
+        // synchronisation)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (SKB) {
@@ -366,7 +371,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             }
             vals[RB + r * BLOCK + tid] = static_cast<double>(m[r]);
         }
-        __syncthreads();
+        tick(0);
+        bar.arrive(kArriver);
+        // block sketch partials of b_j and m_j, first third, overlap the barrier
+        double* sk_dst = p.part_sk + static_cast<int64_t>(j) * slab;
         block_sketch(0, sk_cut1, sk_dst);
         tick(1);
         bar.wait_relaxed();
@@ -406,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         }
         dots_to_partials(w, j, kw, p.part_b);
         tick(3);
-        bar.arrive();
+        bar.arrive(kArriver);
         block_sketch(sk_cut1, sk_cut2, sk_dst);  // second third
         bar.wait_relaxed();
         tick(4);
@@ -484,7 +492,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             if (tid == 0) coef[2 * p.k + 2] = nu;
             __syncthreads();
         } else {
-            bar.arrive();
+            bar.arrive(kArriver);
             block_sketch(sk_cut2, s, sk_dst);  // last third
             bar.wait_relaxed();
         }

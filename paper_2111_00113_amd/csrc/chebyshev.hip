@@ -16,7 +16,8 @@
 // interval.
 //
 // Per step j (row state in registers: bt_{j-1}, bt_j):
-//   m = A bt_j;  bt_{j+1} = a (m - c bt_j) - q bt_{j-1} -> B[:, j+1]  -- arrive --
+//   m = A bt_j;  bt_{j+1} = a (m - c bt_j) - q bt_{j-1} -> B[:, j+1];
+//   stage m (and bt_j) in LDS, wavefront sums of |bt_j|^2           -- arrive --
 //   block partials: |bt_j|^2, S m (and S bt_j when SB is wanted)     -- wait --
 // End of cycle: block u reduces column u's norm, then its sketch entries
 // scaled by 1/(sqrt(zeta) |bt_u|); the last unit is g = S r.
@@ -36,13 +37,11 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     const int s = p.s;
     const int zeta = p.zeta;
     const int64_t n = p.n;
-    // LDS: vals (2 RB doubles; raw pattern at init) | reduction scratch (NW + 1)
-    //      | sketch piece sums | list starts (s+1) | counters (s) | lists (zeta RB)
+    // LDS: vals (2 RB doubles; raw pattern at init) | wavefront norm sums (NW)
+    //      | list starts (s+1) | counters (s) | lists (zeta RB)
     double* vals = smem;
     double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
-    double* red_out = red_tmp + NW;
-    double* sk_tmp = red_out + 1;
-    int* lstart = reinterpret_cast<int*>(sk_tmp + 2 * s * kSketchParts);
+    int* lstart = reinterpret_cast<int*>(red_tmp + NW);
     int* lcount = lstart + (s + 1);
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
     __shared__ unsigned sync_lds[3];
@@ -108,9 +107,13 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
         vals[r * BLOCK + tid] = rv;
     }
     __syncthreads();
-    sketch_lists_apply<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, sk_tmp,
-                              p.part_sk + static_cast<int64_t>(p.d) * slab, G, blk);
+    sketch_lists_apply_lanes<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, p.part_sk + static_cast<int64_t>(p.d) * slab,
+                                    G, blk);
     bar.sync();
+    // the thread that counts this block's barrier arrivals (the last
+    // wavefront's first lane); the other wavefronts start the step's sketch
+    // at once, without waiting for its atomic round trip
+    constexpr unsigned kArriver = BLOCK - kWave;
 
     const bool timing = p.phase_ticks != nullptr && blk == 0 && tid == 0;
     uint64_t t_last = timing ? __builtin_amdgcn_s_memrealtime() : 0;
@@ -174,12 +177,11 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
                 if (row < n) bn[row] = st;
                 bnext[r] = from_basis<TC>(st);
             }
-            tick(0);
-            bar.arrive();
-        } else {
-            tick(0);
         }
-        // partials of this step while the barrier completes
+        // partials of this step while the barrier completes: the block's
+        // |bt_j|^2 (wavefront sums, then their sum in wavefront order) and
+        // the sketch of m_j (and bt_j), staged in LDS before the arrival,
+        // whose block synchronisation publishes them
         double nn = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -188,11 +190,18 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
             if (p.sketch_basis) vals[r * BLOCK + tid] = bc;
             vals[RB + r * BLOCK + tid] = static_cast<double>(m[r]);
         }
-        const double nv[1] = {nn};
-        block_sum<1>(nv, 1, red_tmp, red_out);  // also publishes vals
-        if (tid == 0) p.part_nrm[static_cast<int64_t>(j) * G + blk] = red_out[0];
-        sketch_lists_apply<BLOCK>(sk_v0, sk_nv, 0, s, vals, RB, s, lstart, lists, sk_tmp,
-                                  p.part_sk + static_cast<int64_t>(j) * slab, G, blk);
+        nn = wave_sum(nn);
+        if (lane == 0) red_tmp[wid] = nn;
+        tick(0);
+        if (more) bar.arrive(kArriver);
+        else __syncthreads();
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int q = 0; q < NW; ++q) acc += red_tmp[q];
+            p.part_nrm[static_cast<int64_t>(j) * G + blk] = acc;
+        }
+        sketch_lists_apply_lanes<BLOCK>(sk_v0, sk_nv, 0, s, vals, RB, s, lstart, lists,
+                                        p.part_sk + static_cast<int64_t>(j) * slab, G, blk);
         tick(1);
         if (more) {
             // no acquire when the columns start on 256-byte boundaries: the
@@ -286,7 +295,7 @@ KernelFn pick_kernel(int block, int R, int precision) {
 size_t chebyshev_lds_bytes(int block, int R, int s, int zeta) {
     const int nw = block / kWave;
     const int RB = R * block;
-    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw + 1 + 2 * s * kSketchParts) +
+    return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw) +
            sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
 }
 

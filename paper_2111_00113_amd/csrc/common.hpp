@@ -331,11 +331,13 @@ struct GridSync {
     }
 
     // All prior global writes of this block become visible to every block that
-    // returns from the matching wait().
-    __device__ __forceinline__ void arrive() {
+    // returns from the matching wait().  Thread `who` does the counting (and
+    // the XCD's write-back when last); the other wavefronts go on at once,
+    // so work placed between arrive() and wait() can overlap that latency.
+    __device__ __forceinline__ void arrive(unsigned who = 0) {
         ++seq;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == who) {
             if (per_block_release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned old =
                 __hip_atomic_fetch_add(&w->xcnt[xcc * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -462,6 +464,27 @@ __device__ __forceinline__ double signed_val(const double* v, unsigned u) {
     return (u & 1u) ? -x : x;
 }
 
+// Piece `part` of list `row` of vector vv: entries [a0, a1) of the list summed
+// four at a time (independent loads), the four sums added pairwise.
+__device__ __forceinline__ double sketch_piece(const double* vv, const int* lstart, const uint16_t* lists, int row,
+                                               int part) {
+    const int q0 = lstart[row];
+    const int len = lstart[row + 1] - q0;
+    const int a0 = q0 + (len * part) / kSketchParts;
+    const int a1 = q0 + (len * (part + 1)) / kSketchParts;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int q = a0;
+    for (; q + 4 <= a1; q += 4) {
+        const unsigned u0 = lists[q], u1 = lists[q + 1], u2 = lists[q + 2], u3 = lists[q + 3];
+        acc0 += signed_val(vv, u0);
+        acc1 += signed_val(vv, u1);
+        acc2 += signed_val(vv, u2);
+        acc3 += signed_val(vv, u3);
+    }
+    for (; q < a1; ++q) acc0 += signed_val(vv, lists[q]);
+    return (acc0 + acc1) + (acc2 + acc3);
+}
+
 // Block share (unscaled) of S v over sketch rows [r0, r1) for vectors
 // v = v0 .. v0+nvec-1 staged in vals[v * RB + local].  Each list is cut into
 // kSketchParts pieces, each piece summed four entries at a time (independent
@@ -480,23 +503,7 @@ __device__ __forceinline__ void sketch_lists_reduce(int v0, int nvec, int r0, in
         const int part = t % kSketchParts;
         const int e = t / kSketchParts;
         const int v = e / nrow;
-        const int row = r0 + (e - v * nrow);
-        const int q0 = lstart[row];
-        const int len = lstart[row + 1] - q0;
-        const int a0 = q0 + (len * part) / kSketchParts;
-        const int a1 = q0 + (len * (part + 1)) / kSketchParts;
-        const double* vv = vals + (v0 + v) * RB;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        int q = a0;
-        for (; q + 4 <= a1; q += 4) {
-            const unsigned u0 = lists[q], u1 = lists[q + 1], u2 = lists[q + 2], u3 = lists[q + 3];
-            acc0 += signed_val(vv, u0);
-            acc1 += signed_val(vv, u1);
-            acc2 += signed_val(vv, u2);
-            acc3 += signed_val(vv, u3);
-        }
-        for (; q < a1; ++q) acc0 += signed_val(vv, lists[q]);
-        sk_tmp[t] = (acc0 + acc1) + (acc2 + acc3);
+        sk_tmp[t] = sketch_piece(vals + (v0 + v) * RB, lstart, lists, r0 + (e - v * nrow), part);
     }
     __syncthreads();
     for (int e = tid; e < nvec * nrow; e += BLOCK) {
@@ -508,15 +515,32 @@ __device__ __forceinline__ void sketch_lists_reduce(int v0, int nvec, int r0, in
     }
 }
 
-// Block partial of S v written to dst[(v * s + row) * G + blk] (see
-// sketch_lists_reduce).
+// Block partial of S v written to dst[(v * s + row) * G + blk], as
+// sketch_lists_reduce computes it but without a block-wide synchronisation or
+// LDS scratch: the kSketchParts pieces of a list are summed by consecutive
+// lanes of one wavefront and added, in the order of sketch_lists_reduce (the
+// same bits), by the first of them.  Starts after a __syncthreads() that published vals;
+// vals must stay unchanged until the caller's next block synchronisation.
 template <int BLOCK>
-__device__ __forceinline__ void sketch_lists_apply(int v0, int nvec, int r0, int r1, const double* vals, int RB,
-                                                   int s, const int* lstart, const uint16_t* lists, double* sk_tmp,
-                                                   double* dst, int G, int blk) {
-    sketch_lists_reduce<BLOCK>(v0, nvec, r0, r1, vals, RB, lstart, lists, sk_tmp, [&](int v, int row, double a) {
-        dst[static_cast<int64_t>(v * s + row) * G + blk] = a;
-    });
+__device__ __forceinline__ void sketch_lists_apply_lanes(int v0, int nvec, int r0, int r1, const double* vals,
+                                                         int RB, int s, const int* lstart, const uint16_t* lists,
+                                                         double* dst, int G, int blk) {
+    static_assert(BLOCK % kWave == 0 && kWave % kSketchParts == 0, "pieces of a list share a wavefront");
+    const int tid = threadIdx.x;
+    const int first = (tid & (kWave - 1)) & ~(kSketchParts - 1);
+    const int nrow = r1 - r0;
+    const int tasks = nvec * nrow * kSketchParts;  // a multiple of kSketchParts: the lanes of
+    for (int t = tid; t < tasks; t += BLOCK) {     // a list are active together
+        const int part = t % kSketchParts;
+        const int e = t / kSketchParts;
+        const int v = e / nrow;
+        const int row = r0 + (e - v * nrow);
+        const double piece = sketch_piece(vals + (v0 + v) * RB, lstart, lists, row, part);
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < kSketchParts; ++u) a += __shfl(piece, first + u, kWave);
+        if (part == 0) dst[static_cast<int64_t>((v0 + v) * s + row) * G + blk] = a;
+    }
 }
 
 // Blocks of a launch are dealt round-robin to the 8 XCDs; give each XCD a
