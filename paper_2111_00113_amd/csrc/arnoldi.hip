@@ -33,7 +33,8 @@ size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta) {
     const int nw = block / kWave;
     const int RB = R * block;
     return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw * kRedSlots + kRedSlots + 2 * k + 3) +
-           sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
+           sizeof(int) * static_cast<size_t>(2 * s + 2) +
+           sizeof(uint16_t) * static_cast<size_t>(sketch_lists_len(zeta * RB, s, true));
 }
 
 hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     double* coef = red_out + kRedSlots;  // [0] <m,m>, [1..k] h ; [k+1] <w,w>, [k+2..2k+1] h2 ; [2k+2] nu
     int* lstart = reinterpret_cast<int*>(coef + 2 * p.k + 3);
     int* lcount = lstart + (s + 1);
-    uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
+    uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s + 1);  // 8-byte aligned (2s + 2 ints)
     __shared__ unsigned sync_lds[3];
 
     const int G = gridDim.x;
@@ -110,26 +110,28 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 
     // ---- sliced ELL position of own rows, held for the cycle ------------------
     // the 64 rows of this wavefront in chunk r form one slice: entry k of this
-    // lane's row is at spos[r] + 64 k, for k < sK[r]
+    // lane's row is at spos[r] + 64 k + lane, for k < sK[r].  Both are the same
+    // for the whole wavefront and live in scalar registers.
     int64_t spos[R];
     int sK[R];
     {
         const int64_t nsl = (n + kWave - 1) / kWave;
+        const int wid_s = __builtin_amdgcn_readfirstlane(wid);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t sl = (static_cast<int64_t>(blk) * RB + static_cast<int64_t>(r) * BLOCK) / kWave + wid;
+            const int64_t sl = (static_cast<int64_t>(blk) * RB + static_cast<int64_t>(r) * BLOCK) / kWave + wid_s;
             spos[r] = 0;
             sK[r] = 0;
             if (sl < nsl) {
                 const int64_t a = p.sp[sl];
-                spos[r] = a + lane;
+                spos[r] = a;
                 sK[r] = static_cast<int>((p.sp[sl + 1] - a) / kWave);
             }
         }
     }
 
     // ---- sketch lists of the block's rows, sorted by sketch row --------------
-    sketch_lists_build<R, BLOCK>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
+    sketch_lists_build<R, BLOCK, true>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
                                  lcount, lists);
 
     // Block partials of S b_j (vector 0, only when SB is wanted) and S m_j
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     // (no block synchronisation inside: the wavefronts of a block finish their
     // pieces independently, the last one first doing the barrier arrival)
     auto block_sketch = [&](int r0, int r1, double* dst) {
-        sketch_lists_apply_lanes<BLOCK>(sk_v0, sk_nv, r0, r1, vals, RB, s, lstart, lists, dst, G, blk);
+        sketch_lists_apply_lanes<BLOCK>(sk_v0, sk_nv, r0, r1, vals, RB, s, lstart, lcount, lists, dst, G, blk);
     };
     // the thread that counts this block's barrier arrivals: one of the last
     // wavefront, which gets no sketch pieces when a window has at most
@@ -181,8 +183,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     }
     __syncthreads();
     // g partials after the d step slabs
-    sketch_lists_apply_lanes<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, p.part_sk + static_cast<int64_t>(p.d) * slab,
-                                    G, blk);
+    sketch_lists_apply_lanes<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lcount, lists,
+                                    p.part_sk + static_cast<int64_t>(p.d) * slab, G, blk);
     bar.sync();  // B[:,0] and the g partials are complete
     if constexpr (HALO) {
 #pragma unroll
@@ -283,19 +285,37 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                     cd[r] = -1;
                     vd[r] = TC(0);
                     if (q < sK[r]) {
-                        const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
+                        const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave + lane;
                         cd[r] = p.ci[e];
                         vd[r] = Av[e];
                     }
                 }
             };
             // (FP32 arithmetic only: the FP64 kernel is at its register limit
-            // and the extra registers spilled, measured slower overall)
+            // and the extra registers spilled, measured slower overall; it
+            // loads slot q + 1's columns only, so that slot q's gathers and
+            // value loads wait for one round trip instead of two)
             constexpr bool kLook = sizeof(TC) < 8;
+            auto load_cols = [&](int q, int (&cd)[R]) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cd[r] = -1;
+                    if (q < sK[r]) cd[r] = p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane];
+                }
+            };
             if constexpr (kLook) load_slot(0, c, v);
+            else load_cols(0, c);
             for (int q = 0; q < kmax; ++q) {
-                if constexpr (kLook) load_slot(q + 1, cn, vn);
-                else load_slot(q, c, v);
+                if constexpr (kLook) {
+                    load_slot(q + 1, cn, vn);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        v[r] = TC(0);
+                        if (q < sK[r]) v[r] = Av[spos[r] + static_cast<int64_t>(q) * kWave + lane];
+                    }
+                    load_cols(q + 1, cn);
+                }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (q < sK[r]) {
@@ -325,12 +345,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                         m[r] += v[r] * bv;
                     }
                 }
-                if constexpr (kLook) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        c[r] = cn[r];
-                        v[r] = vn[r];
-                    }
+                for (int r = 0; r < R; ++r) {
+                    c[r] = cn[r];
+                    if constexpr (kLook) v[r] = vn[r];
                 }
             }
         } else {
@@ -342,7 +360,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                     c[r] = 0;
                     v[r] = TC(0);
                     if (q < sK[r]) {
-                        const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
+                        const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave + lane;
                         c[r] = p.ci[e];
                         v[r] = Av[e];
                     }

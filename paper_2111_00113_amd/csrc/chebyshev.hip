@@ -43,7 +43,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
     int* lstart = reinterpret_cast<int*>(red_tmp + NW);
     int* lcount = lstart + (s + 1);
-    uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s);
+    uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s + 1);  // 8-byte aligned (2s + 2 ints)
     __shared__ unsigned sync_lds[3];
     __shared__ double unit_scale;
 
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
             }
         }
     }
-    sketch_lists_build<R, BLOCK>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
+    sketch_lists_build<R, BLOCK, true>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
                                  lcount, lists);
 
     const int sk_v0 = p.sketch_basis ? 0 : 1;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
         vals[r * BLOCK + tid] = rv;
     }
     __syncthreads();
-    sketch_lists_apply_lanes<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lists, p.part_sk + static_cast<int64_t>(p.d) * slab,
+    sketch_lists_apply_lanes<BLOCK>(0, 1, 0, s, vals, RB, s, lstart, lcount, lists, p.part_sk + static_cast<int64_t>(p.d) * slab,
                                     G, blk);
     bar.sync();
     // the thread that counts this block's barrier arrivals (the last
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
             for (int q = 0; q < NW; ++q) acc += red_tmp[q];
             p.part_nrm[static_cast<int64_t>(j) * G + blk] = acc;
         }
-        sketch_lists_apply_lanes<BLOCK>(sk_v0, sk_nv, 0, s, vals, RB, s, lstart, lists,
+        sketch_lists_apply_lanes<BLOCK>(sk_v0, sk_nv, 0, s, vals, RB, s, lstart, lcount, lists,
                                         p.part_sk + static_cast<int64_t>(j) * slab, G, blk);
         tick(1);
         if (more) {
@@ -296,7 +296,8 @@ size_t chebyshev_lds_bytes(int block, int R, int s, int zeta) {
     const int nw = block / kWave;
     const int RB = R * block;
     return sizeof(double) * static_cast<size_t>(arnoldi_vals_doubles(RB, zeta) + nw) +
-           sizeof(int) * static_cast<size_t>(2 * s + 1) + sizeof(uint16_t) * static_cast<size_t>(zeta) * RB;
+           sizeof(int) * static_cast<size_t>(2 * s + 2) +
+           sizeof(uint16_t) * static_cast<size_t>(sketch_lists_len(zeta * RB, s, true));
 }
 
 hipError_t chebyshev_configure(const ArnoldiShape& shape, ArnoldiLaunch* out) {

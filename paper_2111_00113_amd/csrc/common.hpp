@@ -400,9 +400,16 @@ struct GridSync {
 // --------------------------------------------------------------------------
 constexpr int kSketchParts = 4;  // each list is summed in this many pieces
 
-// raw: zeta * RB uint16 of scratch; lstart: s + 1 ints; lcount: s ints;
-// lists: zeta * RB uint16.  Ends with a __syncthreads().
-template <int R, int BLOCK>
+// raw: zeta * RB uint16 of scratch; lstart: s + 1 ints; lcount: s ints (the
+// list lengths on return); lists: sketch_lists_len(zeta * RB, s, PAD4) uint16.
+// PAD4: every list starts at a multiple of four entries (lists then 8-byte
+// aligned) and is followed by zero entries up to the next one, so a group of
+// four entries is one 8-byte load.  Ends with a __syncthreads().
+__host__ __device__ constexpr int sketch_lists_len(int entries, int s, bool pad4) {
+    return pad4 ? entries + 3 * s : entries;
+}
+
+template <int R, int BLOCK, bool PAD4 = false>
 __device__ __forceinline__ void sketch_lists_build(uint64_t seed, uint32_t cycle, int64_t base, int64_t n, int s, int zeta,
                                    uint16_t* raw, int* lstart, int* lcount, uint16_t* lists) {
     constexpr int RB = R * BLOCK;
@@ -425,7 +432,7 @@ __device__ __forceinline__ void sketch_lists_build(uint64_t seed, uint32_t cycle
         int run = 0;
         for (int e = 0; e < s; ++e) {
             lstart[e] = run;
-            run += lcount[e];
+            run += PAD4 ? ((lcount[e] + 3) & ~3) : lcount[e];
             lcount[e] = 0;
         }
         lstart[s] = run;
@@ -445,7 +452,9 @@ __device__ __forceinline__ void sketch_lists_build(uint64_t seed, uint32_t cycle
     }
     __syncthreads();
     for (int e = tid; e < s; e += BLOCK) {  // insertion sort: fixed order inside each list
-        const int q0 = lstart[e], q1 = lstart[e + 1];
+        const int q0 = lstart[e], q1 = q0 + lcount[e];
+        if constexpr (PAD4)
+            for (int q = q1; q < lstart[e + 1]; ++q) lists[q] = 0;
         for (int q = q0 + 1; q < q1; ++q) {
             const uint16_t key = lists[q];
             int z = q - 1;
@@ -515,16 +524,41 @@ __device__ __forceinline__ void sketch_lists_reduce(int v0, int nvec, int r0, in
     }
 }
 
-// Block partial of S v written to dst[(v * s + row) * G + blk], as
-// sketch_lists_reduce computes it but without a block-wide synchronisation or
-// LDS scratch: the kSketchParts pieces of a list are summed by consecutive
-// lanes of one wavefront and added, in the order of sketch_lists_reduce (the
-// same bits), by the first of them.  Starts after a __syncthreads() that published vals;
-// vals must stay unchanged until the caller's next block synchronisation.
+// Piece `part` of a list built with PAD4: the list's groups of four entries
+// are dealt to the pieces in order, each group read with one 8-byte load; the
+// entries of a group are added to four separate sums (zero entries past the
+// list's end skipped), the four sums then added pairwise.
+__device__ __forceinline__ double sketch_piece4(const double* vv, const int* lstart, const int* lcount,
+                                                const uint16_t* lists, int row, int part) {
+    const int len = lcount[row];
+    const int ng = (len + 3) >> 2;
+    const int g0 = (ng * part) / kSketchParts;
+    const int g1 = (ng * (part + 1)) / kSketchParts;
+    const uint2* L = reinterpret_cast<const uint2*>(lists + lstart[row]);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const uint2 w = L[g];
+        const int rem = len - 4 * g;  // entries of this group inside the list (>= 1)
+        const double x0 = signed_val(vv, w.x & 0xffffu), x1 = signed_val(vv, w.x >> 16);
+        const double x2 = signed_val(vv, w.y & 0xffffu), x3 = signed_val(vv, w.y >> 16);
+        acc0 += x0;
+        if (rem > 1) acc1 += x1;
+        if (rem > 2) acc2 += x2;
+        if (rem > 3) acc3 += x3;
+    }
+    return (acc0 + acc1) + (acc2 + acc3);
+}
+
+// Block partial of S v written to dst[(v * s + row) * G + blk] over lists
+// built with PAD4, without a block-wide synchronisation or LDS scratch: the
+// kSketchParts pieces of a list are summed by consecutive lanes of one
+// wavefront and added in piece order by the first of them.  Starts after a
+// __syncthreads() that published vals; vals must stay unchanged until the
+// caller's next block synchronisation.
 template <int BLOCK>
 __device__ __forceinline__ void sketch_lists_apply_lanes(int v0, int nvec, int r0, int r1, const double* vals,
-                                                         int RB, int s, const int* lstart, const uint16_t* lists,
-                                                         double* dst, int G, int blk) {
+                                                         int RB, int s, const int* lstart, const int* lcount,
+                                                         const uint16_t* lists, double* dst, int G, int blk) {
     static_assert(BLOCK % kWave == 0 && kWave % kSketchParts == 0, "pieces of a list share a wavefront");
     const int tid = threadIdx.x;
     const int first = (tid & (kWave - 1)) & ~(kSketchParts - 1);
@@ -535,7 +569,7 @@ __device__ __forceinline__ void sketch_lists_apply_lanes(int v0, int nvec, int r
         const int e = t / kSketchParts;
         const int v = e / nrow;
         const int row = r0 + (e - v * nrow);
-        const double piece = sketch_piece(vals + (v0 + v) * RB, lstart, lists, row, part);
+        const double piece = sketch_piece4(vals + (v0 + v) * RB, lstart, lcount, lists, row, part);
         double a = 0.0;
 #pragma unroll
         for (int u = 0; u < kSketchParts; ++u) a += __shfl(piece, first + u, kWave);
