@@ -93,6 +93,85 @@ __global__ __launch_bounds__(kCombineBlock) void combine_kernel(int64_t n, const
     }
 }
 
+// Four consecutive basis entries of one column as doubles, with one 16-byte
+// load (FP32), two (FP64) or one 8-byte load (bfloat16); p must be aligned to
+// the four entries.
+__device__ __forceinline__ void load_quad(const double* p, double (&o)[4]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ __forceinline__ void load_quad(const float* p, double (&o)[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+}
+__device__ __forceinline__ void load_quad(const bf16_t* p, double (&o)[4]) {
+    const uint2 a = *reinterpret_cast<const uint2*>(p);
+    o[0] = from_basis<double>(bf16_t{static_cast<uint16_t>(a.x & 0xffffu)});
+    o[1] = from_basis<double>(bf16_t{static_cast<uint16_t>(a.x >> 16)});
+    o[2] = from_basis<double>(bf16_t{static_cast<uint16_t>(a.y & 0xffffu)});
+    o[3] = from_basis<double>(bf16_t{static_cast<uint16_t>(a.y >> 16)});
+}
+
+// combine_kernel with four consecutive rows per thread: each column is read in
+// runs of 64 x 4 entries per wavefront, eight columns in flight, and every row
+// keeps two interleaved sums (even and odd columns).  Needs B and ldb aligned
+// to four entries; the n % 4 last rows are done by block 0 one per thread.
+constexpr int kCombineCols = 8;
+template <typename TS>
+__global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, const int* __restrict__ d_eff_p,
+                                                                 const TS* __restrict__ B, int64_t ldb,
+                                                                 const double* __restrict__ y,
+                                                                 double* __restrict__ x,
+                                                                 const double* __restrict__ cn) {
+    extern __shared__ double ys[];
+    const int d_eff = *d_eff_p;
+    for (int c = threadIdx.x; c < d_eff; c += kCombineBlock)
+        ys[c] = cn ? (cn[c] > 0.0 ? y[c] / cn[c] : 0.0) : y[c];
+    __syncthreads();
+    if (d_eff <= 0) return;
+    const int64_t nq = n / 4;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kCombineBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kCombineBlock + threadIdx.x; t < nq; t += stride) {
+        const int64_t i0 = 4 * t;
+        double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        int c = 0;
+        for (; c + kCombineCols <= d_eff; c += kCombineCols) {
+            double b[kCombineCols][4];
+#pragma unroll
+            for (int u = 0; u < kCombineCols; ++u) load_quad(B + static_cast<int64_t>(c + u) * ldb + i0, b[u]);
+#pragma unroll
+            for (int u = 0; u < kCombineCols; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][u & 1] = __builtin_fma(b[u][r], ys[c + u], acc[r][u & 1]);
+        }
+        for (; c < d_eff; ++c) {
+            double b[4];
+            load_quad(B + static_cast<int64_t>(c) * ldb + i0, b);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r][c & 1] = __builtin_fma(b[r], ys[c], acc[r][c & 1]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[i0 + r] += acc[r][0] + acc[r][1];
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const int64_t i = 4 * nq + threadIdx.x;
+        double a0 = 0.0, a1 = 0.0;
+        for (int c = 0; c < d_eff; ++c) {
+            const double v = from_basis<double>(B[static_cast<int64_t>(c) * ldb + i]) * ys[c];
+            if (c & 1) a1 += v;
+            else a0 += v;
+        }
+        x[i] += a0 + a1;
+    }
+}
+
 // bad[0] = 1 if row_ptr is not a valid prefix array for nnz entries or a
 // column index falls outside [0, n)
 __global__ void csr_check_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
@@ -174,6 +253,24 @@ hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B,
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
     const size_t lds = sizeof(double) * (d_max > 0 ? d_max : 1);
+    // four rows per thread where the columns allow aligned quad loads
+    const size_t esz = precision == SGMRES_PREC_FP32 ? 4 : precision == SGMRES_PREC_BF16_BASIS ? 2 : 8;
+    const size_t qa = esz == 8 ? 16 : 4 * esz;
+    if (((reinterpret_cast<uintptr_t>(B) | static_cast<uintptr_t>(ldb) * esz) % qa) == 0 && n >= 4) {
+        int64_t g4 = (n / 4 + kCombineBlock - 1) / kCombineBlock;
+        if (g4 > 2048) g4 = 2048;
+        if (g4 < 1) g4 = 1;
+        if (precision == SGMRES_PREC_FP32)
+            combine4_kernel<float><<<static_cast<int>(g4), kCombineBlock, lds, stream>>>(
+                n, d_eff, static_cast<const float*>(B), ldb, y, x, colnorm);
+        else if (precision == SGMRES_PREC_BF16_BASIS)
+            combine4_kernel<bf16_t><<<static_cast<int>(g4), kCombineBlock, lds, stream>>>(
+                n, d_eff, static_cast<const bf16_t*>(B), ldb, y, x, colnorm);
+        else
+            combine4_kernel<double><<<static_cast<int>(g4), kCombineBlock, lds, stream>>>(
+                n, d_eff, static_cast<const double*>(B), ldb, y, x, colnorm);
+        return hipGetLastError();
+    }
     if (precision == SGMRES_PREC_FP32)
         combine_kernel<float><<<static_cast<int>(g), kCombineBlock, lds, stream>>>(
             n, d_eff, static_cast<const float*>(B), ldb, y, x, colnorm);
