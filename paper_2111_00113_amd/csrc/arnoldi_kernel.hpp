@@ -20,11 +20,15 @@
 // so the result is bitwise reproducible).  The block partials of all steps are
 // kept and summed across blocks once, at the end of the cycle.
 //
-// Per step j (split-phase grid barriers, the first two carrying a reduction;
-// the block's sketch work fills the barrier waits):
-//   phase 1  m = A b_j; partial <m,m>, W^T m           -- arrive --
-//            stage m in LDS; sketch rows [0, s/3)        -- wait --
-//   phase 2  h = W^T m (grid sum); w = m - W h; partial <w,w>, W^T w
+// Per step j (three grid synchronisations, the first two carrying a
+// reduction; the block's sketch work fills the waits).  The first is not a
+// barrier: its partials are tagged with the step (tagged_store), and each
+// block waits for the tags as it loads them.  The others are split-phase grid
+// barriers:
+//   phase 1  m = A b_j; tagged partials <m,m>, W^T m
+//            stage m in LDS; sketch rows [0, s/3)
+//   phase 2  h = W^T m (sum of the tagged partials, waiting for them);
+//            w = m - W h; partial <w,w>, W^T w
 //                                                        -- arrive --
 //            sketch rows [s/3, 2s/3)                     -- wait --
 //   phase 3  h2 = W^T w; |w - W h2|^2 = <w,w> - |h2|^2 (window orthonormal to
@@ -198,9 +202,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         return row < n ? from_basis<TC>(Bs[static_cast<int64_t>(j - a) * p.ldb + row]) : TC(0);
     };
 
-    // partial sums of <x,x> and W^T x over own rows -> part[q*G + blk]
-    // slot q = 0: <x,x>; slot q = 1 + a: <W_a, x>
-    auto dots_to_partials = [&](const TC (&x)[R], int j, int kw, double* part) {
+    // partial sums of <x,x> and W^T x over own rows, handed to put(q, value)
+    // by thread q: slot q = 0: <x,x>; slot q = 1 + a: <W_a, x>
+    auto dots_to_partials = [&](const TC (&x)[R], int j, int kw, auto put) {
         if constexpr (KW > 0) {
             double v[KW + 1];
             TC t = TC(0);
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 v[a + 1] = static_cast<double>(u);
             }
             block_sum<KW + 1>(v, kw + 1, red_tmp, red_out);
-            if (tid <= kw) part[static_cast<int64_t>(tid) * G + blk] = red_out[tid];
+            if (tid <= kw) put(tid, red_out[tid]);
         } else {
             for (int q0 = 0; q0 < kw + 1; q0 += kChunk) {
                 double v[kChunk];
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 }
                 const int cnt = min(kChunk, kw + 1 - q0);
                 block_sum<kChunk>(v, cnt, red_tmp, red_out);
-                if (tid < cnt) part[static_cast<int64_t>(q0 + tid) * G + blk] = red_out[tid];
+                if (tid < cnt) put(q0 + tid, red_out[tid]);
             }
         }
     };
@@ -376,9 +380,14 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                     }
             }
         }
-        dots_to_partials(m, j, kw, p.part_a);
-        // stage b_j and m_j for the sketch (published by the arrival's block
-        // synchronisation)
+        // the first reduction of the step goes through tagged partials (tag
+        // j + 1) instead of a grid barrier: nothing else written before it is
+        // read by other blocks before the second barrier
+        const unsigned tag_a = static_cast<unsigned>(j + 1);
+        dots_to_partials(m, j, kw, [&](int q, double val) {
+            tagged_store(p.part_a + 2 * (static_cast<int64_t>(q) * G + blk), val, tag_a);
+        });
+        // stage b_j and m_j for the sketch
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (SKB) {
@@ -389,17 +398,17 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             }
             vals[RB + r * BLOCK + tid] = static_cast<double>(m[r]);
         }
+        __syncthreads();
         tick(0);
-        bar.arrive(kArriver);
-        // block sketch partials of b_j and m_j, first third, overlap the barrier
+        // block sketch partials of b_j and m_j, first third, while the other
+        // blocks' partials arrive
         double* sk_dst = p.part_sk + static_cast<int64_t>(j) * slab;
         block_sketch(0, sk_cut1, sk_dst);
         tick(1);
-        bar.wait_relaxed();
-        tick(2);
 
         // ---- phase 2: h, w = m - W h, partial dots ------------------------
-        grid_sum(p.part_a, G, kw + 1, coef);  // coef[0] = <m,m>, coef[1+a] = h_a
+        grid_sum_tagged(p.part_a, G, kw + 1, tag_a, coef, p.abort, p.spin_limit);  // coef[0] = <m,m>, coef[1+a] = h_a
+        tick(2);
         if (j == p.d - 1) {
             block_sketch(sk_cut1, s, sk_dst);
             break;
@@ -430,7 +439,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 if (row < n) store_stream(wbuf + row, w[r]);
             }
         }
-        dots_to_partials(w, j, kw, p.part_b);
+        dots_to_partials(w, j, kw, [&](int q, double val) { p.part_b[static_cast<int64_t>(q) * G + blk] = val; });
         tick(3);
         bar.arrive(kArriver);
         block_sketch(sk_cut1, sk_cut2, sk_dst);  // second third

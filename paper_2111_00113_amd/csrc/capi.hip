@@ -68,7 +68,7 @@ struct Workspace {
     double* tau = nullptr;
     size_t tau_cap = 0;
     unsigned* lsq_sync = nullptr;
-    double* part_a = nullptr;
+    unsigned long long* part_a = nullptr;  // tagged partials, two words each
     size_t part_a_cap = 0;
     double* part_b = nullptr;
     size_t part_b_cap = 0;
@@ -287,6 +287,9 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
               double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
               int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
+    // tags of the step partials start at 1: clear the slots of earlier launches
+    SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.part_a), static_cast<int64_t>(4 * (k + 1)) * L.grid, 0u,
+                           stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ArnoldiParams p{};
     p.n = A.n;
@@ -395,7 +398,7 @@ int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int
                     ArnoldiLaunch* L, int sketch_basis, int precision = SGMRES_PREC_FP64) {
     ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis, precision, 0};
     if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
-    SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(k + 1) * L->grid));
+    SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(2 * (k + 1)) * L->grid));
     SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
     SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
     return SGMRES_OK;

@@ -242,6 +242,82 @@ __device__ __forceinline__ void grid_sum(const double* partial, int G, int nv, d
 }
 
 // --------------------------------------------------------------------------
+// Tagged partial sums.  A double is published without a grid barrier as two
+// relaxed 64-bit stores, each holding one 32-bit half of the value in its low
+// word and a tag in its high word.  A reader that finds the expected tag in
+// both words has the value (each 64-bit access is single-copy atomic).  Where
+// nothing but the partials themselves must be ordered, this replaces a grid
+// barrier followed by grid_sum: the wait and the loads of the partials are
+// the same memory round trip.  Tags must change from one use of a slot to the
+// next and must not match the slots' contents at launch (the host clears
+// them, tags start at 1).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void tagged_store(unsigned long long* slot, double v, unsigned tag) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned long long t = static_cast<unsigned long long>(tag) << 32;
+    __hip_atomic_store(slot, t | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 1, t | (b & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// This lane's share of sum_g of the tagged partials col[2g], col[2g + 1]
+// (g = lane, lane + 64, ... < G, in the order of lane_strided_sum).  Each
+// group of four partials is reloaded until all carry `tag`; the wait is
+// bounded like the grid barrier's (abort[0] raised after `limit` ticks of the
+// 100 MHz counter, or already raised: the sum is then meaningless and the
+// host reports the time-out).
+__device__ __forceinline__ double tagged_lane_sum(const unsigned long long* col, int G, int lane, unsigned tag,
+                                                  int* abort, uint64_t limit) {
+    const unsigned long long want = static_cast<unsigned long long>(tag);
+    double acc = 0.0;
+    for (int g0 = lane; g0 < G; g0 += 4 * kWave) {
+        unsigned long long hi[4], lo[4];
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        for (;;) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hi[u] = want << 32;
+                lo[u] = want << 32;
+                if (g0 + u * kWave < G) {
+                    const unsigned long long* q = col + 2 * static_cast<int64_t>(g0 + u * kWave);
+                    hi[u] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    lo[u] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            bool ok = true;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ok = ok && (hi[u] >> 32) == want && (lo[u] >> 32) == want;
+            if (ok) break;
+            if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (g0 + u * kWave < G)
+                acc += __longlong_as_double(static_cast<long long>((hi[u] << 32) | (lo[u] & 0xffffffffull)));
+    }
+    return acc;
+}
+
+// grid_sum over tagged partials part[2 (v G + g) + {0, 1}], v < nv; result in
+// lds_out[0..nv).  Ends with a __syncthreads().
+__device__ __forceinline__ void grid_sum_tagged(const unsigned long long* part, int G, int nv, unsigned tag,
+                                                double* lds_out, int* abort, uint64_t limit) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    for (int v = wid; v < nv; v += nw) {
+        double acc = tagged_lane_sum(part + 2 * static_cast<int64_t>(v) * G, G, lane, tag, abort, limit);
+        acc = wave_sum(acc);
+        if (lane == 0) lds_out[v] = acc;
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------------------
 // Split-phase grid barrier for a cooperative launch (all blocks resident).
 //
 // Arrival is counted per XCD (the chip's 8 L2 domains, read from the XCC_ID
