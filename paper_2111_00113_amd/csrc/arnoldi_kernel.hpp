@@ -439,16 +439,21 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 if (row < n) store_stream(wbuf + row, w[r]);
             }
         }
-        dots_to_partials(w, j, kw, [&](int q, double val) { p.part_b[static_cast<int64_t>(q) * G + blk] = val; });
+        // tagged as well: the second barrier still orders w and the basis
+        // columns, but its partials are loaded while the barrier is polled
+        dots_to_partials(w, j, kw, [&](int q, double val) {
+            tagged_store(p.part_b + 2 * (static_cast<int64_t>(q) * G + blk), val, tag_a);
+        });
         tick(3);
         bar.arrive(kArriver);
         block_sketch(sk_cut1, sk_cut2, sk_dst);  // second third
-        bar.wait_relaxed();
+        // wavefront 0 polls the barrier while the others load the partials
+        double* c2 = coef + p.k + 1;
+        bar.spin_flags();
+        grid_sum_tagged(p.part_b, G, kw + 1, tag_a, c2, p.abort, p.spin_limit, 1);  // c2[0] = <w,w>, c2[1+a] = h2_a
         tick(4);
 
         // ---- phase 3: h2, nu, b_{j+1} -------------------------------------
-        double* c2 = coef + p.k + 1;
-        grid_sum(p.part_b, G, kw + 1, c2);  // c2[0] = <w,w>, c2[1+a] = h2_a
         double h2sq = 0.0;
         for (int a = 0; a < kw; ++a) h2sq += c2[1 + a] * c2[1 + a];
         const double nu2 = c2[0] - h2sq;

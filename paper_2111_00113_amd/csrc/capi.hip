@@ -68,10 +68,10 @@ struct Workspace {
     double* tau = nullptr;
     size_t tau_cap = 0;
     unsigned* lsq_sync = nullptr;
-    unsigned long long* part_a = nullptr;  // tagged partials, two words each
-    size_t part_a_cap = 0;
-    double* part_b = nullptr;
-    size_t part_b_cap = 0;
+    // tagged partials of the Arnoldi steps' two reductions, two words each:
+    // part_a then part_b, (k+1) x G each, cleared together before a launch
+    unsigned long long* part_ab = nullptr;
+    size_t part_ab_cap = 0;
     double* part_sk = nullptr;
     size_t part_sk_cap = 0;
     double* part_vec = nullptr;
@@ -288,7 +288,7 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
               int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
     // tags of the step partials start at 1: clear the slots of earlier launches
-    SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.part_a), static_cast<int64_t>(4 * (k + 1)) * L.grid, 0u,
+    SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.part_ab), static_cast<int64_t>(8 * (k + 1)) * L.grid, 0u,
                            stream));
     if (ev_start) SG_TRY(hipEventRecord(ev_start, stream));
     ArnoldiParams p{};
@@ -311,8 +311,8 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
     p.zeta = zeta;
     p.seed = seed;
     p.cycle = cycle;
-    p.part_a = ws.part_a;
-    p.part_b = ws.part_b;
+    p.part_a = ws.part_ab;
+    p.part_b = ws.part_ab + static_cast<int64_t>(2 * (k + 1)) * L.grid;
     p.part_sk = ws.part_sk;
     p.sync = ws.sync;
     p.per_block_release = per_block_release;
@@ -398,8 +398,7 @@ int prepare_arnoldi(Workspace& ws, int64_t n, int d, int k, int s, int zeta, int
                     ArnoldiLaunch* L, int sketch_basis, int precision = SGMRES_PREC_FP64) {
     ArnoldiShape shape{n, d, k, s, zeta, block, rpt, 0, 0, sketch_basis, precision, 0};
     if (arnoldi_configure(shape, L) != hipSuccess) return SGMRES_EINVAL;
-    SG_TRY(ensure(ws.part_a, ws.part_a_cap, static_cast<size_t>(2 * (k + 1)) * L->grid));
-    SG_TRY(ensure(ws.part_b, ws.part_b_cap, static_cast<size_t>(k + 1) * L->grid));
+    SG_TRY(ensure(ws.part_ab, ws.part_ab_cap, static_cast<size_t>(4 * (k + 1)) * L->grid));
     SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(2 * s * d + s) * L->grid));
     return SGMRES_OK;
 }
@@ -1157,7 +1156,7 @@ void sgmres_release_workspace(void) {
         Workspace& w = kv.second;
         if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
         void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_task, w.bt_slots, w.bt_slot_off, w.bt_gcnt, w.bt_arena,
-                        w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_a, w.part_b, w.part_sk,
+                        w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_ab, w.part_sk,
                         w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sell_K, w.sell_sp, w.sell_col,
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch};

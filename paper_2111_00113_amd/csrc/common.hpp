@@ -302,14 +302,16 @@ __device__ __forceinline__ double tagged_lane_sum(const unsigned long long* col,
     return acc;
 }
 
-// grid_sum over tagged partials part[2 (v G + g) + {0, 1}], v < nv; result in
-// lds_out[0..nv).  Ends with a __syncthreads().
+// grid_sum over tagged partials part[2 (v G + g) + {0, 1}], v < nv, by the
+// wavefronts from `first` on (the others, e.g. one polling a barrier, just
+// join the closing synchronisation); result in lds_out[0..nv).  Ends with a
+// __syncthreads().
 __device__ __forceinline__ void grid_sum_tagged(const unsigned long long* part, int G, int nv, unsigned tag,
-                                                double* lds_out, int* abort, uint64_t limit) {
+                                                double* lds_out, int* abort, uint64_t limit, int first = 0) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const int nw = blockDim.x / kWave;
-    for (int v = wid; v < nv; v += nw) {
+    const int nw = blockDim.x / kWave - first;
+    for (int v = wid - first; v >= 0 && v < nv; v += nw) {
         double acc = tagged_lane_sum(part + 2 * static_cast<int64_t>(v) * G, G, lane, tag, abort, limit);
         acc = wave_sum(acc);
         if (lane == 0) lds_out[v] = acc;

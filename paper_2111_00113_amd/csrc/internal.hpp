@@ -28,7 +28,7 @@ struct ArnoldiParams {
     uint64_t seed;
     uint32_t cycle;
     unsigned long long* part_a;  // (k+1) x G tagged partials (two words each), zero at launch
-    double* part_b;              // (k+1) x G
+    unsigned long long* part_b;  // (k+1) x G tagged partials, zero at launch
     double* part_sk;  // (2s x G) per step for d steps, then s x G for g
     void* sync;       // SyncWords, zero at launch
     int per_block_release;
