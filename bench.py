@@ -35,10 +35,10 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # in profiles/<kernel>_cd1024_hbm_counters.md).  Valid only for the kernel
 # source it was measured on; any change to it makes the figure stale (null).
 MEASURED_TRAFFIC = {
-    "arnoldi": {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "00b57b491482a3ce",
-                "bytes_per_launch": 2.0451e+10},
-    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "4ec8a719fb291afb",
-                  "bytes_per_launch": 1.7402e+10},
+    "arnoldi": {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "6715d25c6fee57f1",
+                "bytes_per_launch": 2.0515e+10},
+    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "7cf934c66f10d26c",
+                  "bytes_per_launch": 1.6908e+10},
 }
 
 
