@@ -66,19 +66,21 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     bar.setup(sync_lds);
 
     // sliced ELL position of own rows (see sell.hip): entry k of this lane's
-    // row in chunk r is at spos[r] + 64 k, for k < sK[r]
+    // row in chunk r is at spos[r] + 64 k + lane, for k < sK[r]; both are the
+    // same for the whole wavefront and live in scalar registers
     int64_t spos[R];
     int sK[R];
     {
         const int64_t nsl = (n + kWave - 1) / kWave;
+        const int wid_s = __builtin_amdgcn_readfirstlane(wid);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t sl = (static_cast<int64_t>(blk) * RB + static_cast<int64_t>(r) * BLOCK) / kWave + wid;
+            const int64_t sl = (static_cast<int64_t>(blk) * RB + static_cast<int64_t>(r) * BLOCK) / kWave + wid_s;
             spos[r] = 0;
             sK[r] = 0;
             if (sl < nsl) {
                 const int64_t a = p.sp[sl];
-                spos[r] = a + lane;
+                spos[r] = a;
                 sK[r] = static_cast<int>((p.sp[sl + 1] - a) / kWave);
             }
         }
@@ -114,6 +116,18 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     // wavefront's first lane); the other wavefronts start the step's sketch
     // at once, without waiting for its atomic round trip
     constexpr unsigned kArriver = BLOCK - kWave;
+    // When only S m is sketched, the first half of vals is free: it holds the
+    // block's own rows of the current column (as TC), and the SpMV gathers
+    // those from LDS; other blocks' rows come from B.
+    const bool lds_b = !p.sketch_basis;
+    TC* bst = reinterpret_cast<TC*>(vals);
+    const int64_t row_lo = static_cast<int64_t>(blk) * RB;
+    const int64_t row_hi = min(n, row_lo + RB);
+    if (lds_b) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) bst[r * BLOCK + tid] = bcur[r];
+    }
+    __syncthreads();
 
     const bool timing = p.phase_ticks != nullptr && blk == 0 && tid == 0;
     uint64_t t_last = timing ? __builtin_amdgcn_s_memrealtime() : 0;
@@ -146,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
                 cd[r] = 0;
                 vd[r] = TC(0);
                 if (q < sK[r]) {
-                    const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave;
+                    const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave + lane;
                     cd[r] = p.ci[e];
                     vd[r] = Av[e];
                 }
@@ -157,7 +171,11 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
             load_slot(q + 1, cn, vn);
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (q < sK[r]) m[r] += v[r] * from_basis<TC>(bj[c[r]]);
+                if (q < sK[r]) {
+                    const int cc = c[r];
+                    const TC bv = (lds_b && cc >= row_lo && cc < row_hi) ? bst[cc - row_lo] : from_basis<TC>(bj[cc]);
+                    m[r] += v[r] * bv;
+                }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 c[r] = cn[r];
@@ -195,6 +213,12 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
         tick(0);
         if (more) bar.arrive(kArriver);
         else __syncthreads();
+        // every SpMV of the block is done with column j: stage column j + 1
+        // (published by the wait's block synchronisation)
+        if (lds_b && more) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) bst[r * BLOCK + tid] = bnext[r];
+        }
         if (tid == 0) {
             double acc = 0.0;
             for (int q = 0; q < NW; ++q) acc += red_tmp[q];
