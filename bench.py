@@ -37,8 +37,8 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "arnoldi": {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "6715d25c6fee57f1",
                 "bytes_per_launch": 2.0515e+10},
-    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "7cf934c66f10d26c",
-                  "bytes_per_launch": 1.6908e+10},
+    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "8e4cf126c5bc4d95",
+                  "bytes_per_launch": 1.5467e+10},
 }
 
 
