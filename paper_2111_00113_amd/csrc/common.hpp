@@ -478,7 +478,8 @@ struct GridSync {
 // --------------------------------------------------------------------------
 constexpr int kSketchParts = 4;  // each list is summed in this many pieces
 
-// raw: zeta * RB uint16 of scratch; lstart: s + 1 ints; lcount: s ints (the
+// raw: scratch of at least zeta * RB uint16 and BLOCK * RB / 256 bytes (the
+// pattern, then the ordering bitmaps); lstart: s + 1 ints; lcount: s ints (the
 // list lengths on return); lists: sketch_lists_len(zeta * RB, s, PAD4) uint16.
 // PAD4: every list starts at a multiple of four entries (lists then 8-byte
 // aligned) and is followed by zero entries up to the next one, so a group of
@@ -529,18 +530,59 @@ __device__ __forceinline__ void sketch_lists_build(uint64_t seed, uint32_t cycle
         }
     }
     __syncthreads();
-    for (int e = tid; e < s; e += BLOCK) {  // insertion sort: fixed order inside each list
-        const int q0 = lstart[e], q1 = q0 + lcount[e];
-        if constexpr (PAD4)
-            for (int q = q1; q < lstart[e + 1]; ++q) lists[q] = 0;
-        for (int q = q0 + 1; q < q1; ++q) {
-            const uint16_t key = lists[q];
-            int z = q - 1;
-            while (z >= q0 && lists[z] > key) {
-                lists[z + 1] = lists[z];
-                --z;
+    // Fixed order inside each list (ascending local row): wavefront w takes
+    // lists w, w + NW, ...  It marks the list's rows in a bitmap of the
+    // block's rows (and their signs in a second one), both in the raw scratch,
+    // which is no longer needed; then each lane reads one 64-row word, and
+    // the words' popcounts, scanned across the lanes in word order, give where
+    // its rows go.  A row appears at most once in a list (the zeta rows of a
+    // column of S are distinct).
+    {
+        constexpr int NW = BLOCK / kWave;
+        constexpr int NWORDS = (RB + 63) / 64;
+        const int lane = tid & (kWave - 1);
+        const int wid = tid / kWave;
+        unsigned long long* bm = reinterpret_cast<unsigned long long*>(raw) + static_cast<int64_t>(wid) * 2 * NWORDS;
+        unsigned long long* sg = bm + NWORDS;
+        for (int w = lane; w < 2 * NWORDS; w += kWave) bm[w] = 0ull;
+        for (int e = wid; e < s; e += NW) {
+            const int q0 = lstart[e];
+            const int len = lcount[e];
+            for (int i = lane; i < len; i += kWave) {
+                const unsigned key = lists[q0 + i];
+                const unsigned u = key >> 1;
+                atomicOr(&bm[u >> 6], 1ull << (u & 63u));
+                if (key & 1u) atomicOr(&sg[u >> 6], 1ull << (u & 63u));
             }
-            lists[z + 1] = key;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            int done = 0;
+            for (int w0 = 0; w0 < NWORDS; w0 += kWave) {
+                const int w = w0 + lane;
+                unsigned long long word = 0ull, sgn = 0ull;
+                if (w < NWORDS) {
+                    word = bm[w];
+                    sgn = sg[w];
+                    bm[w] = 0ull;
+                    sg[w] = 0ull;
+                }
+                const int c = __popcll(word);
+                int incl = c;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int t = __shfl_up(incl, o, kWave);
+                    if (lane >= o) incl += t;
+                }
+                int pos = q0 + done + incl - c;
+                while (word) {
+                    const int b = __ffsll(static_cast<long long>(word)) - 1;
+                    lists[pos++] = static_cast<uint16_t>(((w * 64 + b) << 1) | static_cast<int>((sgn >> b) & 1ull));
+                    word &= word - 1ull;
+                }
+                done += __shfl(incl, kWave - 1, kWave);
+            }
+            if constexpr (PAD4)
+                for (int q = q0 + len + lane; q < lstart[e + 1]; q += kWave) lists[q] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
     }
     __syncthreads();
