@@ -70,8 +70,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     const int s = p.s;
     const int zeta = p.zeta;
     const int64_t n = p.n;
-    // LDS: vals (2 RB doubles; the raw pattern at init) | reduction scratch |
-    //      coefficients | list starts (s+1) | counters (s) | lists (zeta RB)
+    // LDS: vals (2 RB doubles; the raw pattern, then the list-ordering bitmaps,
+    //      at init) | reduction scratch | coefficients | list starts (s+1) |
+    //      list lengths (s, one spare) | lists (zeta RB + 3s, groups of four)
     double* vals = smem;
     double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
     double* red_out = red_tmp + NW * kRedSlots;

@@ -37,8 +37,9 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
     const int s = p.s;
     const int zeta = p.zeta;
     const int64_t n = p.n;
-    // LDS: vals (2 RB doubles; raw pattern at init) | wavefront norm sums (NW)
-    //      | list starts (s+1) | counters (s) | lists (zeta RB)
+    // LDS: vals (2 RB doubles; raw pattern and list-ordering bitmaps at init)
+    //      | wavefront norm sums (NW) | list starts (s+1) | list lengths (s, one
+    //      spare) | lists (zeta RB + 3s, groups of four)
     double* vals = smem;
     double* red_tmp = vals + arnoldi_vals_doubles(RB, zeta);
     int* lstart = reinterpret_cast<int*>(red_tmp + NW);
