@@ -120,10 +120,10 @@ __device__ __forceinline__ void load_quad(const bf16_t* p, double (&o)[4]) {
 }
 
 // combine_kernel with four consecutive rows per thread: each column is read in
-// runs of 64 x 4 entries per wavefront, eight columns in flight, and every row
+// runs of 64 x 4 entries per wavefront, sixteen columns in flight, and every row
 // keeps two interleaved sums (even and odd columns).  Needs B and ldb aligned
 // to four entries; the n % 4 last rows are done by block 0 one per thread.
-constexpr int kCombineCols = 8;
+constexpr int kCombineCols = 16;
 template <typename TS>
 __global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, const int* __restrict__ d_eff_p,
                                                                  const TS* __restrict__ B, int64_t ldb,
