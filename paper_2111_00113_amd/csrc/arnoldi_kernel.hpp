@@ -219,8 +219,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 for (int r = 0; r < R; ++r) u += Wr(a, r) * x[r];
                 v[a + 1] = static_cast<double>(u);
             }
-            block_sum<KW + 1>(v, kw + 1, red_tmp, red_out);
-            if (tid <= kw) put(tid, red_out[tid]);
+            // (no closing synchronisation: both callers synchronise the block
+            // before red_tmp is written again)
+            block_sum_put<KW + 1>(v, kw + 1, red_tmp, put);
         } else {
             for (int q0 = 0; q0 < kw + 1; q0 += kChunk) {
                 double v[kChunk];

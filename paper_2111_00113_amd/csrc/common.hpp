@@ -178,6 +178,29 @@ __device__ __forceinline__ void block_sum(const double (&vals)[NV], int nv, doub
     __syncthreads();
 }
 
+// block_sum whose thread v hands sum v to put(v, sum) itself (same order of
+// additions), without the closing synchronisation: lds_tmp must not be
+// rewritten before the caller's next __syncthreads().
+template <int NV, typename Put>
+__device__ __forceinline__ void block_sum_put(const double (&vals)[NV], int nv, double* lds_tmp, Put put) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nv) {
+            const double t = wave_sum(vals[v]);
+            if (lane == 0) lds_tmp[v * nw + wid] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double acc = 0.0;
+        for (int q = 0; q < nw; ++q) acc += lds_tmp[threadIdx.x * nw + q];
+        put(static_cast<int>(threadIdx.x), acc);
+    }
+}
+
 // Loads of values that other workgroups stored before the last grid barrier.
 // They are device-coherent (relaxed agent-scope atomic loads, which bypass the
 // CU's L1 and a stale copy in this XCD's L2), so a barrier whose readers use
