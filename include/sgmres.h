@@ -94,7 +94,19 @@ typedef struct {
      * [0] SpMV + recurrence, [1] norm and sketch partials, [2] barrier wait,
      * [7] end-of-cycle reduction. */
     double phase_us[8];
+    /* Basis kernel that ran (the last cycle's launch): SGMRES_PATH_*, its
+     * workgroup size, rows per thread and grid (0 when no basis cycle ran). */
+    int32_t path;
+    int32_t launch_block;
+    int32_t launch_rows;
+    int32_t launch_grid;
 } sgmres_info_t;
+
+#define SGMRES_PATH_ARNOLDI_3BAR 1 /* resident truncated Arnoldi, three grid barriers per step */
+#define SGMRES_PATH_ARNOLDI_HALO 2 /* resident truncated Arnoldi, two barriers (halo rebuild) */
+#define SGMRES_PATH_CHEBYSHEV 3    /* resident Chebyshev basis, one barrier per step */
+#define SGMRES_PATH_PART_SPLIT 4   /* part-split kernel of the batched solve (n above the
+                                      resident capacity) */
 
 /* Options of sgmres_solve_ex; zero-initialise for the defaults. */
 typedef struct {

@@ -12,8 +12,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     # -ffp-contract=off: no fused multiply-adds, so every operation rounds as written.
+    # -fopenmp: row loops and fixed-chunk sums may run on several threads (same bits).
     cmd = [
-        "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+        "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
         "-Wall", "-Wextra", SRC, "-o", LIB + ".tmp", "-lm",
     ]
     if verbose:

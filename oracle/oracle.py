@@ -17,7 +17,7 @@ __all__ = [
     "philox4x32_10", "sketch_pattern", "sketch_apply", "sketch_dense", "csr_spmv",
     "csr_transpose", "residual", "arnoldi_cycle", "sketched_lsq", "basis_combine",
     "sgmres_solve", "sgmres_solve_transposed", "dense_solve_gradient", "lib",
-    "chebyshev_cycle", "sgmres_solve_chebyshev",
+    "chebyshev_cycle", "sgmres_solve_chebyshev", "set_threads", "get_threads",
 ]
 
 OK = 0
@@ -89,8 +89,21 @@ def lib():
                 _c.c_int, _c.c_uint64, _c.c_double, _c.c_int, _c.c_double, _f64p,
             ]
             fn.restype = _c.c_int
+        L.oracle_set_threads.argtypes = [_c.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_get_threads.argtypes = []
+        L.oracle_get_threads.restype = _c.c_int
         _LIB = L
     return _LIB
+
+
+def set_threads(t: int) -> None:
+    """OpenMP threads of the row loops and fixed-chunk sums (bits do not depend on it)."""
+    lib().oracle_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
 
 
 def _csr(A):

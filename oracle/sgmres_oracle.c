@@ -41,6 +41,14 @@
  *   R-cheb    Chebyshev basis (Section 4.4): the recurrence runs on the
  *             unnormalised vectors; each is scaled to unit norm only for B,
  *             S B and S A B.  A vector of norm 0 gives a zero column.
+ *
+ * Summation order.  Every sum over the n rows (inner products, norms, the
+ * sketch S v) is taken in fixed chunks of OR_CHUNK consecutive rows: each
+ * chunk is summed in ascending row order, and the chunk sums are added in
+ * ascending chunk order.  Row-wise loops (SpMV, vector updates, the basis
+ * combination) have no cross-row sums.  The result therefore does not depend
+ * on the number of threads: oracle_set_threads(t) only spreads the chunks and
+ * rows over t OpenMP threads (default 1), and any t gives the same bits.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +63,17 @@
 
 #define OR_FLAG_KAPPA_TRUNC 1
 #define OR_FLAG_BREAKDOWN 2
+
+#define OR_CHUNK 4096 /* rows per fixed reduction chunk */
+
+static int g_threads = 1;
+
+/* Threads used by the row loops and chunk sums (results are identical for any
+ * count, see "Summation order" above). */
+void oracle_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
+int oracle_get_threads(void) { return g_threads; }
+
+static int64_t chunks_of(int64_t n) { return (n + OR_CHUNK - 1) / OR_CHUNK; }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al., SC'11): a 4x32-bit Feistel-like bijection    */
@@ -118,28 +137,53 @@ void oracle_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i, int s, int 
     }
 }
 
+/* Unscaled sum over rows [i0, i1) of S[:, i] v[i] into acc (s entries, added
+ * to), rows ascending and, inside a column, in acceptance order. */
+static void sketch_rows(int64_t i0, int64_t i1, const double *v, uint64_t seed, uint32_t cycle, int s,
+                        int zeta, int32_t *rows, int8_t *signs, double *acc) {
+    for (int64_t i = i0; i < i1; ++i) {
+        oracle_sketch_pattern(seed, cycle, i, s, zeta, rows, signs);
+        for (int t = 0; t < zeta; ++t) acc[rows[t]] += (double)signs[t] * v[i];
+    }
+}
+
 /* g = S v for v of length n, S = (1/sqrt(zeta)) [s_1 ... s_n]  (R-scale).
- * Accumulation runs over i ascending and, inside a column, in acceptance order;
- * the scale is applied once at the end. */
+ * Each chunk of OR_CHUNK rows is accumulated on its own (sketch_rows); the
+ * chunk sums are added in chunk order; the scale is applied once at the end. */
 int oracle_sketch_apply(int64_t n, const double *v, uint64_t seed, uint32_t cycle, int s, int zeta,
                         double *g) {
     if (n < 0 || s < 1 || zeta < 1 || zeta > s) return OR_EINVAL;
-    int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)zeta);
-    int8_t *signs = (int8_t *)malloc((size_t)zeta);
-    if (!rows || !signs) {
+    const int64_t nc = chunks_of(n);
+    double *part = (double *)calloc((size_t)(nc > 0 ? nc : 1) * (size_t)s, sizeof(double));
+    if (!part) return OR_ENOMEM;
+    int bad = 0;
+#pragma omp parallel num_threads(g_threads)
+    {
+        int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)zeta);
+        int8_t *signs = (int8_t *)malloc((size_t)zeta);
+        if (!rows || !signs) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nc; ++c) {
+                const int64_t i1 = (c + 1) * OR_CHUNK < n ? (c + 1) * OR_CHUNK : n;
+                sketch_rows(c * OR_CHUNK, i1, v, seed, cycle, s, zeta, rows, signs, part + (size_t)c * s);
+            }
+        }
         free(rows);
         free(signs);
+    }
+    if (bad) {
+        free(part);
         return OR_ENOMEM;
     }
     for (int r = 0; r < s; ++r) g[r] = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        oracle_sketch_pattern(seed, cycle, i, s, zeta, rows, signs);
-        for (int t = 0; t < zeta; ++t) g[rows[t]] += (double)signs[t] * v[i];
-    }
+    for (int64_t c = 0; c < nc; ++c)
+        for (int r = 0; r < s; ++r) g[r] += part[(size_t)c * s + r];
     const double scale = 1.0 / sqrt((double)zeta);
     for (int r = 0; r < s; ++r) g[r] *= scale;
-    free(rows);
-    free(signs);
+    free(part);
     return OR_OK;
 }
 
@@ -148,6 +192,7 @@ int oracle_sketch_apply(int64_t n, const double *v, uint64_t seed, uint32_t cycl
 /* ------------------------------------------------------------------------ */
 void oracle_csr_spmv(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                      const double *x, double *y) {
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) acc += val[p] * x[col_idx[p]];
@@ -178,10 +223,30 @@ int oracle_csr_transpose(int64_t n, const int32_t *row_ptr, const int32_t *col_i
     return OR_OK;
 }
 
-static double dot(int64_t n, const double *a, const double *b) {
+/* sum_i a[i] b[i] in the fixed chunk order (chunk sums kept, then added in
+ * chunk order; without memory for them the same sums are formed one chunk
+ * after another, which gives the same bits). */
+static double chunk_dot(int64_t i0, int64_t i1, const double *a, const double *b) {
     double acc = 0.0;
-    for (int64_t i = 0; i < n; ++i) acc += a[i] * b[i];
+    for (int64_t i = i0; i < i1; ++i) acc += a[i] * b[i];
     return acc;
+}
+
+static double dot(int64_t n, const double *a, const double *b) {
+    const int64_t nc = chunks_of(n);
+    double *part = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    double tot = 0.0;
+    if (!part) {
+        for (int64_t c = 0; c < nc; ++c)
+            tot += chunk_dot(c * OR_CHUNK, (c + 1) * OR_CHUNK < n ? (c + 1) * OR_CHUNK : n, a, b);
+        return tot;
+    }
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (int64_t c = 0; c < nc; ++c)
+        part[c] = chunk_dot(c * OR_CHUNK, (c + 1) * OR_CHUNK < n ? (c + 1) * OR_CHUNK : n, a, b);
+    for (int64_t c = 0; c < nc; ++c) tot += part[c];
+    free(part);
+    return tot;
 }
 
 static int all_finite(int64_t n, const double *a) {
@@ -194,6 +259,7 @@ static int all_finite(int64_t n, const double *a) {
 double oracle_residual(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                        const double *f, const double *x, double *r) {
     oracle_csr_spmv(n, row_ptr, col_idx, val, x, r);
+    #pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < n; ++i) r[i] = f[i] - r[i];
     return sqrt(dot(n, r, r));
 }
@@ -233,6 +299,7 @@ int oracle_arnoldi_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col_i
     /* g = S r; b_1 = r / |r| */
     oracle_sketch_apply(n, r, seed, cycle, s, zeta, g);
     const double beta = sqrt(dot(n, r, r));
+    #pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < n; ++i) B[i] = r[i] / beta;
 
     int dc = d;
@@ -251,6 +318,7 @@ int oracle_arnoldi_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col_i
             for (int a = 0; a < kw; ++a) h[a] = dot(n, B + (size_t)(j - a) * n, w);
             for (int a = 0; a < kw; ++a) {
                 const double *wa = B + (size_t)(j - a) * n;
+                #pragma omp parallel for num_threads(g_threads) schedule(static)
                 for (int64_t i = 0; i < n; ++i) w[i] -= h[a] * wa[i];
                 hsum[a] += h[a];
             }
@@ -265,6 +333,7 @@ int oracle_arnoldi_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col_i
             break;
         }
         double *bn = B + (size_t)(j + 1) * n;
+        #pragma omp parallel for num_threads(g_threads) schedule(static)
         for (int64_t i = 0; i < n; ++i) bn[i] = w[i] / nu;
     }
     free(m);
@@ -312,13 +381,17 @@ int oracle_chebyshev_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col
     const double qcoef = (dx * dx - dy * dy) / (4.0 * rho);
     for (int j = 0; j < d; ++j) { /* 0-based: this iteration forms b_{j+1} */
         if (j == 0) {
+            #pragma omp parallel for num_threads(g_threads) schedule(static)
             for (int64_t i = 0; i < n; ++i) nxt[i] = r[i] / beta;
         } else {
             oracle_csr_spmv(n, row_ptr, col_idx, val, cur, t); /* t = A b_{j} (1-based j) */
+            #pragma omp parallel for num_threads(g_threads) schedule(static)
             for (int64_t i = 0; i < n; ++i) t[i] -= c * cur[i];
             if (j == 1) {
+                #pragma omp parallel for num_threads(g_threads) schedule(static)
                 for (int64_t i = 0; i < n; ++i) nxt[i] = t[i] / (2.0 * rho);
             } else {
+                #pragma omp parallel for num_threads(g_threads) schedule(static)
                 for (int64_t i = 0; i < n; ++i) nxt[i] = (t[i] - qcoef * prev[i]) / rho;
             }
         }
@@ -326,6 +399,7 @@ int oracle_chebyshev_cycle(int64_t n, const int32_t *row_ptr, const int32_t *col
         const double nj = sqrt(dot(n, nxt, nxt));
         nrm[j] = nj;
         double *bj = B + (size_t)j * n;
+        #pragma omp parallel for num_threads(g_threads) schedule(static)
         for (int64_t i = 0; i < n; ++i) bj[i] = nj > 0.0 ? nxt[i] / nj : 0.0;
         oracle_csr_spmv(n, row_ptr, col_idx, val, bj, t);
         oracle_sketch_apply(n, bj, seed, cycle, s, zeta, SB + (size_t)j * s);
@@ -419,6 +493,7 @@ int oracle_sketched_lsq(int s, int dc, double *C, double *g, double kappa_max, d
 
 /* x <- x + B[:, :d_eff] y   (R-soln) */
 void oracle_basis_combine(int64_t n, int d_eff, const double *B, const double *y, double *x) {
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int c = 0; c < d_eff; ++c) acc += B[(size_t)c * n + i] * y[c];

@@ -437,6 +437,7 @@ int solve_large(const SolveArgs& a, sgmres_info_t* info) {
         rep.relres = r.relres;
         rep.rest_est = t.nf > 0 ? t.rest / t.nf : 0.0;
         rep.kappa_est = t.kappa;
+        if (r.cycles > 0) rep.path = SGMRES_PATH_PART_SPLIT;
         *info = rep;
     }
     return r.status;
@@ -466,6 +467,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     if (rc) return rc;
     rc = check_csr(ws, a.A, st);
     if (rc) return rc;
+    bool halo = false;
     // Two grid barriers per Arnoldi step when at most a quarter of the
     // nonzeros reach outside their row's block (their b_j entries are then
     // recomputed by the block that needs them).
@@ -481,6 +483,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
             if (arnoldi_configure(hs, &H) == hipSuccess && H.R == L.R && H.block == L.block && H.KW == L.KW) {
                 SG_TRY(ensure(ws.wbuf, ws.wbuf_cap, (static_cast<size_t>(n) * 8 + 7) / 8));
                 L = H;
+                halo = true;
             }
         }
     }
@@ -581,6 +584,12 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         ++cycles;
     }
     rep.cycles = cycles;
+    if (cycles > 0) {
+        rep.path = cheb ? SGMRES_PATH_CHEBYSHEV : (halo ? SGMRES_PATH_ARNOLDI_HALO : SGMRES_PATH_ARNOLDI_3BAR);
+        rep.launch_block = L.block;
+        rep.launch_rows = L.R;
+        rep.launch_grid = L.grid;
+    }
     if (ev.on)
         for (int q = 0; q < 8; ++q) rep.phase_us[q] = 1e-2 * static_cast<double>(ws.host_sc->phase_ticks[q]);
     if (info) *info = rep;

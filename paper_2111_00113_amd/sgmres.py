@@ -23,6 +23,10 @@ FLAG_KAPPA_TRUNC = 1
 FLAG_BREAKDOWN = 2
 BASIS_ARNOLDI = 0
 BASIS_CHEBYSHEV = 1
+PATH_ARNOLDI_3BAR = 1
+PATH_ARNOLDI_HALO = 2
+PATH_CHEBYSHEV = 3
+PATH_PART_SPLIT = 4
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16_BASIS = 2
@@ -67,6 +71,10 @@ class _Info(ctypes.Structure):
         ("t_lsq_ms", ctypes.c_double),
         ("t_combine_ms", ctypes.c_double),
         ("phase_us", ctypes.c_double * 8),
+        ("path", ctypes.c_int32),
+        ("launch_block", ctypes.c_int32),
+        ("launch_rows", ctypes.c_int32),
+        ("launch_grid", ctypes.c_int32),
     ]
 
 
@@ -205,7 +213,8 @@ def _info(i: _Info) -> dict:
     return dict(cycles=i.cycles, steps=i.steps, d_eff_last=i.d_eff_last, flags=i.flags, relres=i.relres,
                 rest_est=i.rest_est, kappa_est=i.kappa_est, t_residual_ms=i.t_residual_ms,
                 t_basis_ms=i.t_basis_ms, t_lsq_ms=i.t_lsq_ms, t_combine_ms=i.t_combine_ms,
-                phase_us=list(i.phase_us))
+                phase_us=list(i.phase_us), path=i.path, launch_block=i.launch_block,
+                launch_rows=i.launch_rows, launch_grid=i.launch_grid)
 
 
 def _raise(fn, rc):

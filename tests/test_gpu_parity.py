@@ -10,6 +10,9 @@ the arithmetic (summation order differs between the two sides):
     true relative residuals within 1e-10 of each other.
 """
 
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -19,6 +22,15 @@ import synth
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _host_threads():
+    # the oracle's sums have a fixed order: threads change its run time only
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 1
 
 
 @pytest.fixture(scope="module")
@@ -331,25 +343,162 @@ def test_solve_lucky_breakdown(sg, orc):
     assert np.allclose(x, x_o, rtol=1e-14, atol=1e-15)
 
 
+# ---------------------------------------------------------------- launch shapes
+# The solve picks one row per thread whenever the grid fits, so the small cases
+# above run R = 1.  The benchmarked launch (n = 2^20) runs four rows per thread
+# in the two-barrier mode.  Here the solve path is forced to every launch shape
+# at n = 65,536 (grids of 64 / R workgroups of 1024) and compared with the
+# oracle's cycle, in both barrier modes and, for Arnoldi, bitwise between them.
+@pytest.fixture(scope="module")
+def cd256(orc):
+    A = synth.convection_diffusion(256, (50.0, 20.0))  # n = 65536 spans all 8 XCDs at R = 1
+    f = synth.rhs(A.n, 0)
+    orc.set_threads(_host_threads())
+    try:
+        _, x_arn, info_arn = orc.sgmres_solve(A, f, d=60, k=4, s=120, seed=3, tol=0.0, restarts=0)
+        _, x_ch, info_ch = orc.sgmres_solve_chebyshev(A, f, (4.0, 4.0, 0.0), d=60, s=120, seed=3, tol=0.0,
+                                                      restarts=0)
+    finally:
+        orc.set_threads(1)
+    return A, f, (x_arn, info_arn), (x_ch, info_ch)
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8])
+def test_solve_launch_shapes_arnoldi(sg, orc, cd256, R):
+    A, f, (x_o, info_o), _ = cd256
+    dA = sg.DeviceCSR.from_host(A)
+    outs = {}
+    for halo_off in (False, True):
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 4, 120, 3, 0.0, 0, block_size=1024, rows_per_thread=R,
+                                   halo_off=halo_off)
+        assert rc == sg.NOT_CONVERGED and info["cycles"] == 1
+        assert (info["launch_block"], info["launch_rows"], info["launch_grid"]) == (1024, R, 64 // R)
+        assert info["path"] == (sg.PATH_ARNOLDI_3BAR if halo_off else sg.PATH_ARNOLDI_HALO)
+        xg = _np(x)
+        assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-8
+        assert abs(info["relres"] - info_o["relres"]) < 1e-10
+        assert np.isclose(info["rest_est"], info_o["rest_est"], rtol=1e-8)
+        outs[halo_off] = (xg, info["relres"])
+    # the halo rebuild reproduces the owner's bits
+    assert np.array_equal(outs[False][0], outs[True][0]) and outs[False][1] == outs[True][1]
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8])
+def test_solve_launch_shapes_chebyshev(sg, orc, cd256, R):
+    A, f, _, (x_o, info_o) = cd256
+    dA = sg.DeviceCSR.from_host(A)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 1, 120, 3, 0.0, 0, block_size=1024, rows_per_thread=R,
+                               cheb_box=(4.0, 4.0, 0.0))
+    assert rc == sg.NOT_CONVERGED and info["cycles"] == 1
+    assert info["path"] == sg.PATH_CHEBYSHEV and info["launch_rows"] == R and info["launch_grid"] == 64 // R
+    xg = _np(x)
+    assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-8
+    assert abs(info["relres"] - info_o["relres"]) < 1e-10
+
+
+# ---------------------------------------------------------------- near breakdown
+def _near_invariant(eps):
+    # graded diagonal; b has weight 1 on a 2-dimensional invariant subspace and
+    # eps elsewhere, so the third basis vector comes from a w of norm ~eps |m|
+    n = 3000
+    A = synth.diagonal(np.linspace(1.0, 3.0, n))
+    f = eps * synth.rhs(n, 5)
+    f[0] += 1.0
+    f[1] += 1.0
+    return A, f
+
+
+def _identity_plus_small():
+    # A = I + 1e-7 R: the first Gram-Schmidt pass cancels almost all of A b_j
+    base = synth.random_dominant(4000, offdiag=6, seed=23)
+    val = base.val / np.abs(base.val).max() * 1e-7
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    val = np.where(rows == base.col_idx, val + 1.0, val)
+    return synth.CSR(base.n, base.row_ptr, base.col_idx, val), synth.rhs(base.n, 6)
+
+
+@pytest.mark.parametrize("case", ["eps1e-6", "eps1e-10", "eps1e-13", "i_plus_1e-7r"])
+def test_second_pass_norm_near_breakdown(sg, orc, case):
+    """The kernel forms the new column's norm as nu^2 = |w|^2 - |h2|^2 from the
+    second reduction; the oracle takes |w - W h2| directly.  Near breakdown the
+    two may differ by the rounding of w itself (~u |m|), not more."""
+    A, f = _identity_plus_small() if case.startswith("i_") else _near_invariant(float(case[3:]))
+    d, k, s = 12, 2, 40
+    out = sg.sgmres_arnoldi_cycle(sg.DeviceCSR.from_host(A), _t(f), d, k, s, 8, 7, 0)
+    ref = orc.arnoldi_cycle(A, f, d, k, s, 8, 7, 0)
+    assert out["dc"] == ref["dc"] == d and out["flags"] == ref["flags"] == 0
+    H, Href = _np(out["H"]), ref["H"]
+    anorm = np.abs(A.val).max() * 2.0  # bound on |A b_j| for unit b_j (diagonal or I + small)
+    assert np.all(np.abs(H[k, : d - 1] - Href[k, : d - 1]) <= 64 * 2.0**-53 * anorm), (H[k], Href[k])
+    rc, x, info, rc_o, x_o, info_o = _solve_both(sg, orc, A, f, d, k, s, 0.0, 0, seed=7)
+    assert np.linalg.norm(x - x_o) / np.linalg.norm(x_o) < 1e-8
+    assert abs(info["relres"] - info_o["relres"]) < 1e-10
+
+
 # ---------------------------------------------------------------- full size
-def test_full_size_workload_converges(sg, orc):
-    """n = 1,048,576, d = 200, k = 4, s = 400 (the benchmarked launch): the GPU
-    solve reaches relative residual 1e-10, confirmed by the oracle's residual."""
+@pytest.fixture(scope="module")
+def cd1024():
     A, f, p = synth.workload("cd1024")
+    return A, f, p
+
+
+def test_full_size_one_cycle_parity(sg, orc, cd1024):
+    """One cycle of the benchmarked solve (n = 2^20, d = 200, k = 4, s = 400;
+    four rows per thread, two-barrier kernel) through sgmres_solve, against
+    the oracle's cycle."""
+    A, f, p = cd1024
+    dA = sg.DeviceCSR.from_host(A)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc, info = sg.sgmres_solve(dA, _t(f), x, p["d"], p["k"], p["s"], p["seed"], 0.0, 0)
+    print("gpu one cycle:", info, flush=True)
+    assert rc == sg.NOT_CONVERGED and info["cycles"] == 1 and info["steps"] == p["d"]
+    assert info["path"] == sg.PATH_ARNOLDI_HALO and info["launch_rows"] == 4 and info["launch_grid"] == 256
+    orc.set_threads(_host_threads())
+    try:
+        rc_o, x_o, info_o = orc.sgmres_solve(A, f, d=p["d"], k=p["k"], s=p["s"], zeta=p["zeta"], seed=p["seed"],
+                                             tol=0.0, restarts=0)
+    finally:
+        orc.set_threads(1)
+    print("oracle one cycle:", info_o, flush=True)
+    xg = _np(x)
+    assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-8
+    assert abs(info["relres"] - info_o["relres"]) < 1e-10
+    assert np.isclose(info["rest_est"], info_o["rest_est"], rtol=1e-8)
+    assert info["d_eff_last"] == info_o["d_eff_last"]
+
+
+def test_full_size_workload_converges(sg, orc, cd1024):
+    """n = 1,048,576, d = 200, k = 4, s = 400 (the benchmarked launch): the GPU
+    solve reaches relative residual 1e-10, confirmed by the oracle's residual,
+    in the oracle's number of cycles (stored by tests/golden/
+    make_cd1024_oracle_solve.py, which calls only the oracle)."""
+    A, f, p = cd1024
+    with open(os.path.join(GOLDEN, "cd1024_oracle_solve.json")) as fh:
+        gold = json.load(fh)
     dA = sg.DeviceCSR.from_host(A)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
     rc, info = sg.sgmres_solve(dA, _t(f), x, p["d"], p["k"], p["s"], p["seed"], p["tol"], p["restarts"])
-    print("full-size solve:", info, flush=True)
-    assert rc == sg.OK
+    print("full-size solve:", info, "oracle:", {k: gold[k] for k in ("cycles", "relres")}, flush=True)
+    assert rc == sg.OK and gold["rc"] == 0
     _, nrm = orc.residual(A, f, _np(x))
     assert nrm / np.linalg.norm(f) <= 1e-10
     assert abs(nrm / np.linalg.norm(f) - info["relres"]) <= 1e-12
+    assert abs(info["cycles"] - gold["cycles"]) <= 1
+    assert abs(info["relres"] - gold["relres"]) <= 1e-10
+    # a converged x is fixed only to about kappa(A) tol relative (kappa ~ 4e5
+    # here: |dx| <~ 4e-5 |x| ~ 0.8, i.e. ~1e-3 per entry on average)
+    xg = _np(x)
+    xs = xg[gold["x_sample_index"]]
+    assert np.allclose(xs, gold["x_sample"], rtol=0, atol=1e-2)
+    assert abs(np.linalg.norm(xg) - gold["x_norm"]) <= 1e-4 * gold["x_norm"]
 
 
-def test_full_size_first_steps_parity(sg, orc):
+def test_full_size_first_steps_parity(sg, orc, cd1024):
     """Same operator and launch shape as the benchmark (n = 2^20, k = 4, s = 400),
     first 12 basis columns against the oracle."""
-    A, f, p = synth.workload("cd1024")
+    A, f, p = cd1024
     d = 12
     out = sg.sgmres_arnoldi_cycle(sg.DeviceCSR.from_host(A), _t(f), d, p["k"], p["s"], 8, 0, 0)
     ref = orc.arnoldi_cycle(A, f, d, p["k"], p["s"], 8, 0, 0)

@@ -76,6 +76,74 @@ def test_pattern_keyed_by_seed_cycle_column(orc):
     assert not np.array_equal(a[:4], f)
 
 
+def _pattern_from_words(orc, seed, cycle, i, s, zeta):
+    """The written pattern specification applied to raw Philox4x32-10 blocks:
+    key (lo32 seed, hi32 seed), counter (lo32 i, hi32 i, cycle, t); the words
+    of blocks t = 0, 1, ... in order, word u proposing row floor(u s / 2^32)
+    with sign -1 iff u is odd; repeats of an accepted row skipped."""
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    rows, signs = [], []
+    t = 0
+    while len(rows) < zeta:
+        words = orc.philox4x32_10([i & 0xFFFFFFFF, i >> 32, cycle, t], key)
+        for u in (int(w) for w in words):
+            if len(rows) == zeta:
+                break
+            row = (u * s) >> 32
+            if row in rows:
+                continue
+            rows.append(row)
+            signs.append(-1 if u & 1 else 1)
+        t += 1
+    return rows, signs
+
+
+@pytest.mark.parametrize("seed,cycle,i0,s,zeta", [(0, 0, 0, 400, 8), (12345678901234, 7, 2**32 - 3, 400, 8),
+                                                  (5, 1, 17, 9, 8), (9, 2, 100, 200, 32), (3, 4, 7, 1, 1)])
+def test_pattern_follows_written_spec_word_by_word(orc, seed, cycle, i0, s, zeta):
+    # Pins the mapping from the Philox words (themselves pinned by the
+    # known-answer vectors) to rows and signs: the word order, the row formula
+    # and the sign bit.  A sign read from bit 31, or words taken in another
+    # order, would pass the statistical pins below but fail here.
+    rows, signs = orc.sketch_pattern(seed, cycle, i0, 6, s, zeta)
+    for q in range(6):
+        r_ref, s_ref = _pattern_from_words(orc, seed, cycle, i0 + q, s, zeta)
+        assert rows[q].tolist() == r_ref
+        assert signs[q].tolist() == s_ref
+
+
+def test_pattern_sign_independent_of_row(orc):
+    # the sign bit (bit 0 of the word) is independent of the row, which the top
+    # bits decide: in the upper and the lower half of the rows about half the
+    # signs are negative (a sign taken from bit 31 would make every upper-half
+    # row negative)
+    rows, signs = orc.sketch_pattern(seed=77, cycle=1, i0=0, count=5000, s=400, zeta=8)
+    for half in (rows < 200, rows >= 200):
+        neg = float((signs[half] < 0).mean())
+        assert abs(neg - 0.5) < 0.02
+
+
+def test_oracle_bits_independent_of_thread_count(orc):
+    # every sum over rows runs in fixed chunks of 4096 rows, so threads only
+    # spread the work: a cycle and a restarted solve give identical bits
+    A = synth.convection_diffusion(100, (50.0, 20.0))  # n = 10,000: three chunks, ragged tail
+    f = synth.rhs(A.n, 0)
+    outs = []
+    try:
+        for t in (1, 3, 8):
+            orc.set_threads(t)
+            c = orc.arnoldi_cycle(A, f, 20, 4, 40, 8, 5, 1)
+            rc, x, info = orc.sgmres_solve(A, f, d=20, k=4, s=40, seed=5, tol=1e-12, restarts=4)
+            outs.append((c, x, info))
+    finally:
+        orc.set_threads(1)
+    for c, x, info in outs[1:]:
+        for key in ("B", "SB", "SAB", "H", "g"):
+            assert np.array_equal(c[key], outs[0][0][key]), key
+        assert np.array_equal(x, outs[0][1])
+        assert info == outs[0][2]
+
+
 def test_sketch_apply_matches_dense_matrix(orc):
     rng = np.random.default_rng(0)
     n, s, zeta = 300, 50, 8
