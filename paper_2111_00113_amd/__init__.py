@@ -18,6 +18,10 @@ from .sgmres import (  # noqa: F401
     PREC_FP64,
     PREC_FP32,
     PREC_BF16_BASIS,
+    PATH_ARNOLDI_3BAR,
+    PATH_ARNOLDI_HALO,
+    PATH_CHEBYSHEV,
+    PATH_PART_SPLIT,
     LIB_PATH,
     lib,
     sgmres_solve,

@@ -347,7 +347,7 @@ def test_solve_lucky_breakdown(sg, orc):
 # The solve picks one row per thread whenever the grid fits, so the small cases
 # above run R = 1.  The benchmarked launch (n = 2^20) runs four rows per thread
 # in the two-barrier mode.  Here the solve path is forced to every launch shape
-# at n = 65,536 (grids of 64 / R workgroups of 1024) and compared with the
+# at n = 65,536 (grids of 65,536 / (block R) workgroups) and compared with the
 # oracle's cycle, in both barrier modes and, for Arnoldi, bitwise between them.
 @pytest.fixture(scope="module")
 def cd256(orc):
@@ -363,17 +363,21 @@ def cd256(orc):
     return A, f, (x_arn, info_arn), (x_ch, info_ch)
 
 
-@pytest.mark.parametrize("R", [1, 2, 4, 8])
-def test_solve_launch_shapes_arnoldi(sg, orc, cd256, R):
+# (workgroup size, rows per thread): at 1024 threads the LDS lists cap R at 4
+SHAPES = [(1024, 1), (1024, 2), (1024, 4), (512, 8)]
+
+
+@pytest.mark.parametrize("block,R", SHAPES)
+def test_solve_launch_shapes_arnoldi(sg, orc, cd256, block, R):
     A, f, (x_o, info_o), _ = cd256
     dA = sg.DeviceCSR.from_host(A)
     outs = {}
     for halo_off in (False, True):
         x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
-        rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 4, 120, 3, 0.0, 0, block_size=1024, rows_per_thread=R,
+        rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 4, 120, 3, 0.0, 0, block_size=block, rows_per_thread=R,
                                    halo_off=halo_off)
         assert rc == sg.NOT_CONVERGED and info["cycles"] == 1
-        assert (info["launch_block"], info["launch_rows"], info["launch_grid"]) == (1024, R, 64 // R)
+        assert (info["launch_block"], info["launch_rows"], info["launch_grid"]) == (block, R, A.n // (block * R))
         assert info["path"] == (sg.PATH_ARNOLDI_3BAR if halo_off else sg.PATH_ARNOLDI_HALO)
         xg = _np(x)
         assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-8
@@ -384,15 +388,16 @@ def test_solve_launch_shapes_arnoldi(sg, orc, cd256, R):
     assert np.array_equal(outs[False][0], outs[True][0]) and outs[False][1] == outs[True][1]
 
 
-@pytest.mark.parametrize("R", [1, 2, 4, 8])
-def test_solve_launch_shapes_chebyshev(sg, orc, cd256, R):
+@pytest.mark.parametrize("block,R", SHAPES)
+def test_solve_launch_shapes_chebyshev(sg, orc, cd256, block, R):
     A, f, _, (x_o, info_o) = cd256
     dA = sg.DeviceCSR.from_host(A)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
-    rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 1, 120, 3, 0.0, 0, block_size=1024, rows_per_thread=R,
+    rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 1, 120, 3, 0.0, 0, block_size=block, rows_per_thread=R,
                                cheb_box=(4.0, 4.0, 0.0))
     assert rc == sg.NOT_CONVERGED and info["cycles"] == 1
-    assert info["path"] == sg.PATH_CHEBYSHEV and info["launch_rows"] == R and info["launch_grid"] == 64 // R
+    assert info["path"] == sg.PATH_CHEBYSHEV
+    assert (info["launch_block"], info["launch_rows"], info["launch_grid"]) == (block, R, A.n // (block * R))
     xg = _np(x)
     assert np.linalg.norm(xg - x_o) / np.linalg.norm(x_o) < 1e-8
     assert abs(info["relres"] - info_o["relres"]) < 1e-10
