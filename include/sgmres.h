@@ -179,7 +179,14 @@ int sgmres_solve_ex(const sgmres_csr_t *A, const double *b, double *x, int d, in
 int sgmres_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s,
                           int zeta, int32_t *rows, int8_t *signs, void *stream);
 
-/* g = S v (Section 2.3.2, scale 1/sqrt(zeta)): v has n entries, g has s. */
+/* g = S v (Section 2.3.2, scale 1/sqrt(zeta)): v (device) has n >= 0 entries,
+ * g (device) has s; requires 1 <= s <= 4096 and 1 <= zeta <= min(s, 32).  The
+ * sums run in a fixed order (rows in chunks of 512, each sketch row's terms in
+ * ascending input index inside a chunk, chunk totals per workgroup, then the
+ * workgroups in order), so the result is the same bits on every call.  Uses
+ * the library's workspace (allocated on first use); returns after the work on
+ * `stream` has finished.  Errors: SGMRES_EINVAL for a bad size or null
+ * pointer, SGMRES_ENOMEM / SGMRES_EHIP from the runtime. */
 int sgmres_sketch_apply(int64_t n, const double *v, uint64_t seed, uint32_t cycle, int s,
                         int zeta, double *g, void *stream);
 

@@ -983,7 +983,7 @@ int sgmres_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t cou
 
 int sgmres_sketch_apply(int64_t n, const double* v, uint64_t seed, uint32_t cycle, int s, int zeta, double* g,
                         void* stream) {
-    if (n < 0 || (n > 0 && !v) || !g || s < 1 || s > 32767 || zeta < 1 || zeta > s || zeta > kMaxZeta)
+    if (n < 0 || (n > 0 && !v) || !g || s < 1 || s > kMaxS || zeta < 1 || zeta > s || zeta > kMaxZeta)
         return SGMRES_EINVAL;
     std::lock_guard<std::mutex> lock(g_mutex);
     Workspace* ws = nullptr;

@@ -252,8 +252,10 @@ hipError_t launch_to_f32(int64_t count, const double* in, float* out, hipStream_
 // ---- sketch kernels (sketch.hip) -------------------------------------------
 hipError_t launch_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s,
                                  int zeta, int32_t* rows, int8_t* signs, hipStream_t stream);
-// g = S v using part (s x G workspace, G = sketch_grid(n))
+// g = S v using part (s x G workspace, G = sketch_grid(n)); dynamic LDS of
+// sketch_apply_lds_bytes(s, zeta) (at most 159,752 bytes for s <= 4096, zeta <= 32)
 int sketch_grid(int64_t n);
+size_t sketch_apply_lds_bytes(int s, int zeta);
 hipError_t launch_sketch_apply(int64_t n, const double* v, uint64_t seed, uint32_t cycle, int s,
                                int zeta, double* part, double* g, hipStream_t stream);
 

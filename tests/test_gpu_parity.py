@@ -78,13 +78,31 @@ def test_sketch_pattern_full_size_sample(sg, orc):
         assert np.array_equal(_np(rows), r_ref) and np.array_equal(_np(signs), s_ref)
 
 
-@pytest.mark.parametrize("n,s,zeta", [(1, 4, 2), (1000, 80, 8), (123457, 400, 8), (70000, 7, 7)])
+@pytest.mark.parametrize("n,s,zeta", [(1, 4, 2), (1000, 80, 8), (123457, 400, 8), (70000, 7, 7), (0, 5, 3),
+                                      (300001, 4096, 32), (513, 4096, 1)])
 def test_sketch_apply(sg, orc, n, s, zeta):
-    v = synth.rhs(n, 3)
+    v = synth.rhs(n, 3) if n else np.zeros(0)
     g = _np(sg.sgmres_sketch_apply(_t(v), 11, 2, s, zeta))
-    ref = orc.sketch_apply(v, 11, 2, s, zeta)
-    row_mass = np.abs(v).sum() * zeta / s / np.sqrt(zeta)  # typical sum of |terms| per sketch row
+    ref = orc.sketch_apply(v, 11, 2, s, zeta) if n else np.zeros(s)
+    row_mass = max(np.abs(v).sum(), 1.0) * zeta / s / np.sqrt(zeta)  # typical sum of |terms| per sketch row
     assert np.allclose(g, ref, rtol=0, atol=1e-12 * row_mass)
+
+
+def test_sketch_apply_same_bits(sg, orc):
+    """The sums run in a fixed order: repeated calls give identical bits (n
+    spans all 512 workgroups, each taking several 512-row chunks)."""
+    n, s, zeta = (1 << 20) + 77, 400, 8
+    v = _t(synth.rhs(n, 8))
+    first = _np(sg.sgmres_sketch_apply(v, 5, 1, s, zeta))
+    for _ in range(3):
+        assert np.array_equal(_np(sg.sgmres_sketch_apply(v, 5, 1, s, zeta)), first)
+    ref = orc.sketch_apply(_np(v), 5, 1, s, zeta)
+    assert np.allclose(first, ref, rtol=0, atol=1e-12 * np.abs(_np(v)).sum() * np.sqrt(zeta) / s)
+
+
+def test_sketch_apply_rejects_large_s(sg):
+    with pytest.raises(sg.SGMRESError):
+        sg.sgmres_sketch_apply(_t(np.ones(10)), 0, 0, 4097, 8)
 
 
 # ---------------------------------------------------------------- residual
