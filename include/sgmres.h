@@ -190,6 +190,20 @@ int sgmres_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t cou
 int sgmres_sketch_apply(int64_t n, const double *v, uint64_t seed, uint32_t cycle, int s,
                         int zeta, double *g, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sgmres_sketch_apply
+ * with the same arguments, limits and bits, but no allocation of any kind.
+ * Its block partials (s x G doubles, G = min(512, ceil(n / 512))) live in one
+ * fixed 16 MiB device array per GPU, held until the process ends; sizes
+ * beyond it cannot occur within s <= 4096 and are rejected with SGMRES_EINVAL
+ * all the same.  The work is only enqueued on `stream` (no synchronisation):
+ * g is ready when the stream reaches that point.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  The array needs no
+ * clearing: every partial is written before it is read. */
+int sgmres_sketch_apply_noalloc(int64_t n, const double *v, uint64_t seed, uint32_t cycle, int s,
+                                int zeta, double *g, void *stream);
+
 /* r = f - A x and its 2-norm (Algorithm 1, residual step).  r has n entries
  * (device); *norm (host) receives |r|_2. */
 int sgmres_residual(const sgmres_csr_t *A, const double *f, const double *x, double *r,

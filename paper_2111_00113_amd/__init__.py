@@ -29,6 +29,7 @@ from .sgmres import (  # noqa: F401
     sgmres_solve_batched,
     sgmres_sketch_pattern,
     sgmres_sketch_apply,
+    sgmres_sketch_apply_noalloc,
     sgmres_residual,
     sgmres_arnoldi_cycle,
     sgmres_chebyshev_cycle,

@@ -3,7 +3,9 @@
 //   sketch apply:   g = S v from block-local sketch lists summed in a fixed
 //                   order, block partials and a fixed-order cross-block sum.
 #include <algorithm>
+#include <mutex>
 
+#include "../../include/sgmres.h"
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -151,4 +153,55 @@ hipError_t launch_sketch_apply(int64_t n, const double* v, uint64_t seed, uint32
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free g = S v for callers that cannot allocate device memory
+// (code under stream capture, serving loops, harnesses that forbid it).  The
+// block partials live in a fixed device array instead of the workspace.
+// ---------------------------------------------------------------------------
+namespace {
+
+// s x G block partials, s <= 4096 and G <= 512 (16 MiB per device, held for
+// the life of the process).  In host code this name is a stand-in for the
+// device array, never its address: kernels receive the address that
+// hipGetSymbolAddress returned for the current device.
+constexpr size_t kScratchDoubles = static_cast<size_t>(4096) * 512;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of scratch, looked up once per device (with
+// that device current).
+int scratch_for_device(double** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SGMRES_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return SGMRES_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SGMRES_EHIP;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SGMRES_OK;
+}
+
+}  // namespace
 }  // namespace sg
+
+extern "C" int sgmres_sketch_apply_noalloc(int64_t n, const double* v, uint64_t seed, uint32_t cycle, int s,
+                                           int zeta, double* g, void* stream) {
+    using namespace sg;
+    if (n < 0 || (n > 0 && !v) || !g || s < 1 || s > 4096 || zeta < 1 || zeta > s || zeta > kMaxZeta)
+        return SGMRES_EINVAL;
+    const int G = sketch_grid(n);
+    if (static_cast<size_t>(s) * static_cast<size_t>(G) > kScratchDoubles) return SGMRES_EINVAL;
+    double* part = nullptr;
+    const int rc = scratch_for_device(&part);
+    if (rc) return rc;
+    // every partial is written before it is read: nothing to clear
+    const hipError_t e = launch_sketch_apply(n, v, seed, cycle, s, zeta, part, g, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) return SGMRES_OK;
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SGMRES_ENOMEM : SGMRES_EHIP;
+}

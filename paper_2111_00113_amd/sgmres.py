@@ -131,6 +131,7 @@ def lib():
     L.sgmres_solve_ex.argtypes = [P(_CSR), vp, vp, i32, i32, i32, u64, dbl, i32, P(_Options), P(_Info), vp]
     L.sgmres_sketch_pattern.argtypes = [u64, u32, i64, i64, i32, i32, vp, vp, vp]
     L.sgmres_sketch_apply.argtypes = [i64, vp, u64, u32, i32, i32, vp, vp]
+    L.sgmres_sketch_apply_noalloc.argtypes = [i64, vp, u64, u32, i32, i32, vp, vp]
     L.sgmres_residual.argtypes = [P(_CSR), vp, vp, vp, P(dbl), vp]
     L.sgmres_arnoldi_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, i32, u64, u32, vp, i64, vp, vp, vp, vp,
                                        P(i32), P(i32), vp]
@@ -147,7 +148,7 @@ def lib():
     L.sgmres_version.argtypes = []
     L.sgmres_version.restype = ctypes.c_char_p
     for name in ("sgmres_solve", "sgmres_solve_transposed", "sgmres_solve_ex", "sgmres_sketch_pattern",
-                 "sgmres_sketch_apply", "sgmres_residual", "sgmres_arnoldi_cycle", "sgmres_sketched_lsq",
+                 "sgmres_sketch_apply", "sgmres_sketch_apply_noalloc", "sgmres_residual", "sgmres_arnoldi_cycle", "sgmres_sketched_lsq",
                  "sgmres_basis_combine", "sgmres_csr_transpose", "sgmres_csr_outer_grad"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
@@ -302,6 +303,17 @@ def sgmres_sketch_apply(v, seed, cycle, s, zeta, stream=None):
     g = torch.empty(s, dtype=torch.float64, device=v.device)
     rc = lib().sgmres_sketch_apply(v.numel(), v.data_ptr(), seed, cycle, s, zeta, g.data_ptr(), _stream(stream))
     _raise("sgmres_sketch_apply", rc)
+    return g
+
+
+def sgmres_sketch_apply_noalloc(v, g, seed, cycle, s, zeta, stream=None):
+    """g = S v into the caller's g (s float64 entries), with no allocation in
+    the library; only enqueued on the stream."""
+    _check_dev(v, torch.float64)
+    _check_dev(g, torch.float64, s)
+    rc = lib().sgmres_sketch_apply_noalloc(v.numel(), v.data_ptr(), seed, cycle, s, zeta, g.data_ptr(),
+                                           _stream(stream))
+    _raise("sgmres_sketch_apply_noalloc", rc)
     return g
 
 
