@@ -79,14 +79,64 @@ def compulsory_launch_bytes(n: int, nnz: int, dc: float, prec: str = "fp64") -> 
     return dc * ((4.0 + vb) * nnz + eb * n) + eb * n * (dc - 1) + (8.0 + eb) * n + 4.0 * (n + 1)
 
 
-def cpu_baseline(A, f, p, cycles_per_solve: float, sample_cols: int) -> dict:
-    """Time the oracle on one bounded sample of a cycle and scale to solves/s."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_cycles_per_solve(workload: str):
+    """Cycles the oracle's own restarted solve of this workload takes (stored
+    by tests/golden/make_cd1024_oracle_solve.py, which calls only the oracle)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle_solve.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return int(json.load(fh)["cycles"])
+
+
+def cpu_baseline(A, f, p, cycles_per_solve: float, cycles_source: str, sample_cols: int) -> dict:
+    """The CPU oracle timed on this host on a bounded sample of the workload,
+    scaled to solves/s with the oracle's own cycle count.
+
+    All cores (the threads this process may run on, at most 16): one complete
+    cycle at full size (residual, d basis columns with their sketches, the
+    sketched least squares, the combine).  One core: the residual, the first
+    sample_cols basis columns of that cycle (scaled by d / sample_cols), the
+    least squares and the combine.  The oracle's sums have a fixed order, so
+    the thread count changes only its run time."""
     import numpy as np
 
     import oracle
 
     n = A.n
     d, k, s, zeta = p["d"], p["k"], p["s"], p["zeta"]
+    try:
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        cores = 1
+    model = cpu_model()
+    out = {"kind": "oracle", "unit": "solves/s", "cpu_model": model}
+    # all cores: one full cycle (a one-cycle solve) at full size
+    oracle.set_threads(cores)
+    try:
+        t0 = time.perf_counter()
+        r0, _ = oracle.residual(A, f, np.zeros(n))
+        t_res_all = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.sgmres_solve(A, f, d=d, k=k, s=s, zeta=zeta, seed=p["seed"], tol=0.0, restarts=0)
+        t_one_all = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+    # a one-cycle solve evaluates |b|, two residuals and one cycle; a solve of
+    # C cycles evaluates C + 1 residuals and C cycles
+    per_solve_all = cycles_per_solve * (t_one_all - t_res_all) + t_res_all
+    # one core: a bounded part of the same cycle
     t0 = time.perf_counter()
     r, _ = oracle.residual(A, f, np.zeros(n))
     t_res = time.perf_counter() - t0
@@ -106,19 +156,20 @@ def cpu_baseline(A, f, p, cycles_per_solve: float, sample_cols: int) -> dict:
     t0 = time.perf_counter()
     L.oracle_basis_combine(n, d, Bd, y, x)
     t_comb = time.perf_counter() - t0
-    per_cycle = t_res + t_basis * (d / sample_cols) + t_lsq + t_comb
-    per_solve = per_cycle * cycles_per_solve + t_res
-    return {
-        "value": 1.0 / per_solve,
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"one residual, {sample_cols} of {d} basis columns of cycle 0, one {s}x{d} sketched "
-                   f"least-squares solve and one {n}x{d} combine at full size; basis time scaled by "
-                   f"{d}/{sample_cols}, cycle time by {cycles_per_solve:.1f} cycles per solve (measured "
-                   f"on the GPU run); {per_solve:.1f} s per solve, sample took "
-                   f"{t_res + t_basis + t_lsq + t_comb:.1f} s"),
-    }
+    per_solve_1 = cycles_per_solve * (t_res + t_basis * (d / sample_cols) + t_lsq + t_comb) + t_res
+    out.update({
+        "value": 1.0 / per_solve_all,
+        "cores": cores,
+        "s_per_solve": per_solve_all,
+        "single_core": {"value": 1.0 / per_solve_1, "cores": 1, "s_per_solve": per_solve_1},
+        "cycles_per_solve": cycles_per_solve,
+        "sample": (f"{cores} threads: one full cycle at full size timed as a one-cycle oracle solve "
+                   f"({t_one_all:.1f} s); 1 thread: one residual, {sample_cols} of {d} basis columns of cycle 0 "
+                   f"(scaled by {d}/{sample_cols}), one {s}x{d} sketched least-squares solve and one {n}x{d} "
+                   f"combine ({t_res + t_basis + t_lsq + t_comb:.1f} s); both scaled by {cycles_per_solve:g} "
+                   f"cycles per solve ({cycles_source}); host CPU {model}"),
+    })
+    return out
 
 
 def grad_bench(args, A, f, p, sg, torch, np) -> int:
@@ -266,7 +317,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--workload", default="cd1024")
-    ap.add_argument("--cpu-sample-cols", type=int, default=160)
+    ap.add_argument("--cpu-sample-cols", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
@@ -428,9 +479,23 @@ def main() -> int:
             "residual": t_res / args.steps,
         },
     }
+    rf = out["roofline"]
+    # the same launch time against two other byte counts, labelled: the bytes the
+    # counters measured (when current for this kernel source) and the bytes this
+    # kernel must move (window kept on chip, no row pointers)
+    rf["frac_basis"] = "algorithmic bytes per launch (12 nnz + 4n + 8n(k+1) per step) / avg launch time"
+    if rf["traffic"]:
+        rf["frac_measured_traffic"] = rf["traffic"] / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS
+    rf["frac_compulsory"] = rf["compulsory_bytes_per_launch"] / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS
+    rf["target_frac"] = 0.60
+    rf["gap_to_target"] = 0.60 - rf["frac"]
     if not args.no_cpu_baseline and not cheb and args.precision == "fp64":
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(A, f, p, cycles / args.steps, args.cpu_sample_cols)
+        oc = oracle_cycles_per_solve(args.workload)
+        src = ("the oracle's own solve of this workload, tests/golden" if oc is not None
+               else "no stored oracle solve for this workload: the GPU run's count")
+        out["cpu_baseline"] = cpu_baseline(A, f, p, float(oc) if oc is not None else cycles / args.steps, src,
+                                           args.cpu_sample_cols)
     print(json.dumps(out), flush=True)
     del dA, fb, x
     torch.cuda.synchronize()
