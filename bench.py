@@ -332,6 +332,10 @@ def main() -> int:
                          "batch: many systems per launch against one-at-a-time FP64 solves")
     ap.add_argument("--batch-count", type=int, default=256, help="systems in the many-systems workload")
     ap.add_argument("--block-rhs", type=int, default=32, help="right-hand sides of the n = 2^20 block")
+    ap.add_argument("--path", default="auto", choices=["auto", "stream", "part-split"],
+                    help="basis kernel for systems beyond the resident capacity (auto: streaming)")
+    ap.add_argument("--stream-state", type=int, default=0, choices=[0, 1, 2],
+                    help="streaming path: 0 auto, 1 m and w in registers, 2 in an HBM buffer")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -374,12 +378,14 @@ def main() -> int:
     cheb = args.basis == "chebyshev"
     box = tuple(float(t) for t in args.cheb_box.split(",")) if cheb else None
 
+    path = {"auto": 0, "stream": sg.PATH_STREAM, "part-split": sg.PATH_PART_SPLIT}[args.path]
+
     def solve(profile: bool) -> dict:
         x.zero_()
         rc, info = sg.sgmres_solve(dA, fb, x, d, k, s, p["seed"], p["tol"], p["restarts"], zeta=p["zeta"],
                                    profile=profile, block_size=args.block_size,
                                    rows_per_thread=args.rows_per_thread, spmv_mode=args.spmv_mode, cheb_box=box,
-                                   precision=args.precision)
+                                   precision=args.precision, path=path, stream_state=args.stream_state)
         if rc != sg.OK:
             raise RuntimeError(f"solve did not converge: {info}")
         return info
@@ -405,12 +411,17 @@ def main() -> int:
     t_lsq = sum(i["t_lsq_ms"] for i in infos)
     t_comb = sum(i["t_combine_ms"] for i in infos)
     t_res = sum(i["t_residual_ms"] for i in infos)
+    t_sketch = sum(i["t_sketch_ms"] for i in infos)
     dc_avg = steps / cycles
-    launch_ms = t_basis / cycles
+    run_path = infos[-1]["path"]
+    streaming = run_path == sg.PATH_STREAM
+    # streaming path: the basis kernel alone (the sketch of the finished basis,
+    # S A B = (S B) H and g = S r follow it as separate launches)
+    launch_ms = (t_basis - t_sketch) / cycles
     pr = args.precision
     launch_bytes = (cheb_launch_bytes(A.n, A.nnz, dc_avg, pr) if cheb
                     else basis_launch_bytes(A.n, A.nnz, k, dc_avg, pr))
-    resident = launch_ms > 0.0  # the resident basis kernel ran (not the part-split path of large systems)
+    resident = launch_ms > 0.0  # a basis kernel was timed (not the part-split path of large systems)
     if not resident:
         launch_ms = elapsed * 1e3 / cycles  # whole cycle: basis, least squares and combine
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
@@ -458,9 +469,10 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": (MEASURED_TRAFFIC[args.basis]["bytes_per_launch"]
                         if kernel_source_hash(args.basis) == MEASURED_TRAFFIC[args.basis]["source_hash"]
-                        and args.workload == "cd1024" and args.precision == "fp64" else None),
+                        and args.workload == "cd1024" and args.precision == "fp64" and not streaming else None),
             "traffic_unit": "bytes per launch",
-            "kernel": ("chebyshev_kernel" if cheb else "arnoldi_kernel (spmv_truncarnoldi)") if resident
+            "kernel": ("stream_kernel (streaming truncated Arnoldi)" if streaming else
+                       ("chebyshev_kernel" if cheb else "arnoldi_kernel (spmv_truncarnoldi)")) if resident
                       else "batched_cycle_kernel as a batch of one (n above the resident capacity); "
                            "time per whole cycle",
             "bytes_per_launch": launch_bytes,
@@ -474,12 +486,23 @@ def main() -> int:
                                     for q in range(8)],
         "gpu_ms_per_solve": {
             "basis": t_basis / args.steps,
+            "sketch_of_basis": t_sketch / args.steps,
             "lsq": t_lsq / args.steps,
             "combine": t_comb / args.steps,
             "residual": t_res / args.steps,
         },
     }
     rf = out["roofline"]
+    if streaming:
+        # the same algorithmic bytes over the basis kernel plus the sketch of the
+        # finished basis (the fused kernels' counterpart)
+        both_ms = t_basis / cycles
+        rf["sketch_ms_per_cycle"] = t_sketch / cycles
+        rf["frac_basis_and_sketch"] = launch_bytes / (both_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS
+    out["path"] = {1: "arnoldi 3-barrier", 2: "arnoldi halo", 3: "chebyshev", 4: "part-split",
+                   5: "stream"}.get(run_path, str(run_path))
+    out["launch"] = {"block": infos[-1]["launch_block"], "rows_per_thread": infos[-1]["launch_rows"],
+                     "grid": infos[-1]["launch_grid"]}
     # the same launch time against two other byte counts, labelled: the bytes the
     # counters measured (when current for this kernel source) and the bytes this
     # kernel must move (window kept on chip, no row pointers)

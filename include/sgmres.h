@@ -95,18 +95,24 @@ typedef struct {
      * [7] end-of-cycle reduction. */
     double phase_us[8];
     /* Basis kernel that ran (the last cycle's launch): SGMRES_PATH_*, its
-     * workgroup size, rows per thread and grid (0 when no basis cycle ran). */
+     * workgroup size, rows per thread and grid (0 when no basis cycle ran).
+     * SGMRES_PATH_STREAM reports rows per thread as -P when each workgroup
+     * parks its rows' m and w in an HBM buffer (P rows per thread and tile). */
     int32_t path;
     int32_t launch_block;
     int32_t launch_rows;
     int32_t launch_grid;
+    double t_sketch_ms; /* streaming path: sketch of the finished basis, S A B = (S B) H
+                           and g = S r (profile only; included in t_basis_ms) */
 } sgmres_info_t;
 
 #define SGMRES_PATH_ARNOLDI_3BAR 1 /* resident truncated Arnoldi, three grid barriers per step */
 #define SGMRES_PATH_ARNOLDI_HALO 2 /* resident truncated Arnoldi, two barriers (halo rebuild) */
 #define SGMRES_PATH_CHEBYSHEV 3    /* resident Chebyshev basis, one barrier per step */
-#define SGMRES_PATH_PART_SPLIT 4   /* part-split kernel of the batched solve (n above the
-                                      resident capacity) */
+#define SGMRES_PATH_PART_SPLIT 4   /* part-split kernel of the batched solve */
+#define SGMRES_PATH_STREAM 5       /* streaming truncated Arnoldi (n above the resident
+                                      capacity): window read back from B, S B formed
+                                      from the finished basis and S A B = (S B) H */
 
 /* Options of sgmres_solve_ex; zero-initialise for the defaults. */
 typedef struct {
@@ -132,6 +138,13 @@ typedef struct {
     int32_t halo_off;   /* truncated Arnoldi: nonzero keeps three grid barriers per step;
                            0 uses two when at most a quarter of the nonzeros reach outside
                            their row's block of the basis kernel (results are bit-identical) */
+    int32_t path;       /* 0 auto: the resident kernels when the system fits them, else
+                           SGMRES_PATH_STREAM (k <= 4, s <= 1024), else the part-split
+                           kernel (k <= 4); SGMRES_PATH_STREAM or SGMRES_PATH_PART_SPLIT
+                           force that path (truncated Arnoldi only) */
+    int32_t stream_state; /* streaming path: 0 auto, 1 keep m and w in registers (fails
+                             with SGMRES_EINVAL when the grid cannot hold every row),
+                             2 park them in an HBM buffer between phases */
 } sgmres_options_t;
 
 /*

@@ -22,6 +22,7 @@ from .sgmres import (  # noqa: F401
     PATH_ARNOLDI_HALO,
     PATH_CHEBYSHEV,
     PATH_PART_SPLIT,
+    PATH_STREAM,
     LIB_PATH,
     lib,
     sgmres_solve,

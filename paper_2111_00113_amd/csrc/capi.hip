@@ -121,6 +121,14 @@ struct Workspace {
     size_t t_val_cap = 0;
     int32_t* t_scratch = nullptr;
     size_t t_scratch_cap = 0;
+    // streaming path: per-chunk sketch lists, block partials of S B, the m / w
+    // state buffer (HBM-state instances)
+    uint32_t* st_lists = nullptr;
+    size_t st_lists_cap = 0;
+    double* st_part = nullptr;
+    size_t st_part_cap = 0;
+    double* st_state = nullptr;
+    size_t st_state_cap = 0;
 };
 
 std::mutex g_mutex;
@@ -202,6 +210,8 @@ struct SolveArgs {
     double cheb_c, cheb_dx, cheb_dy;
     int precision;  // SGMRES_PREC_*
     int halo_off;   // nonzero: three grid barriers per Arnoldi step always
+    int path;       // 0 auto, SGMRES_PATH_STREAM / SGMRES_PATH_PART_SPLIT forced
+    int stream_state;  // 0 auto, 1 registers, 2 HBM buffer
     hipStream_t stream;
 };
 
@@ -229,10 +239,10 @@ bool cheb_coefficients(double c, double dx, double dy, ChebCoef* out) {
 
 // HIP events bracketing the kernels of one cycle (profiling only).
 struct CycleEvents {
-    hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr, l1 = nullptr, c1 = nullptr;
+    hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr, l1 = nullptr, c1 = nullptr, k1 = nullptr;
     bool on = false;
     hipError_t create() {
-        hipEvent_t* all[] = {&r0, &r1, &b0, &b1, &l1, &c1};
+        hipEvent_t* all[] = {&r0, &r1, &b0, &b1, &l1, &c1, &k1};
         for (hipEvent_t* e : all) {
             hipError_t err = hipEventCreate(e);
             if (err != hipSuccess) return err;
@@ -241,7 +251,7 @@ struct CycleEvents {
         return hipSuccess;
     }
     ~CycleEvents() {
-        hipEvent_t all[] = {r0, r1, b0, b1, l1, c1};
+        hipEvent_t all[] = {r0, r1, b0, b1, l1, c1, k1};
         for (hipEvent_t e : all)
             if (e) (void)hipEventDestroy(e);
     }
@@ -443,6 +453,163 @@ int solve_large(const SolveArgs& a, sgmres_info_t* info) {
     return r.status;
 }
 
+// Truncated Arnoldi on the streaming basis kernel (systems beyond the resident
+// kernels' capacity, or forced).  Per cycle: residual -> basis kernel (window
+// read back from B, b_1 .. b_{d+1} and H) -> the cycle's sketch lists -> g = S r,
+// S B of the d + 1 columns, S A B = (S B) H -> sketched least squares ->
+// x += B y.  Caller holds g_mutex.
+int solve_stream(const SolveArgs& a, Workspace& ws, sgmres_info_t* info) {
+    const int64_t n = a.A.n;
+    const int kk = (a.k > a.d - 1) ? (a.d > 1 ? a.d - 1 : 1) : a.k;
+    hipStream_t st = a.stream;
+    if (kk > kStreamMaxK || !basis_sketch_fits(a.s, a.zeta)) return SGMRES_EINVAL;
+    StreamLaunch L{};
+    if (stream_configure(n, 1, kk, a.precision, &L) != hipSuccess) return SGMRES_EINVAL;
+    if (a.stream_state == 2 && !L.hst) {
+        // HBM state requested: same tile size, one tile per workgroup up to the chip
+        StreamLaunch H{};
+        if (stream_configure(int64_t(1) << 40, 1, kk, a.precision, &H) != hipSuccess) return SGMRES_EINVAL;
+        const int64_t tiles = (n + int64_t(H.P) * kStreamBlock - 1) / (int64_t(H.P) * kStreamBlock);
+        H.grid = static_cast<int>(tiles < H.grid ? tiles : H.grid);
+        L = H;
+    } else if (a.stream_state == 1 && L.hst) {
+        return SGMRES_EINVAL;
+    }
+    int rc = check_csr(ws, a.A, st);
+    if (rc) return rc;
+    const size_t eb = basis_elem_bytes(a.precision);
+    // columns padded to 128 entries (256-byte aligned), d + 1 of them
+    const int64_t ldb = (n + 127) / 128 * 128;
+    SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
+    SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(ldb) * (a.d + 1) * eb + 7) / 8));
+    SG_TRY(ensure(ws.SB, ws.SB_cap, static_cast<size_t>(a.s) * (a.d + 1)));
+    SG_TRY(ensure(ws.SAB, ws.SAB_cap, static_cast<size_t>(a.s) * a.d));
+    SG_TRY(ensure(ws.H, ws.H_cap, static_cast<size_t>(kk + 1) * a.d));
+    SG_TRY(ensure(ws.g, ws.g_cap, static_cast<size_t>(a.s)));
+    SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(a.d)));
+    SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    SG_TRY(ensure(ws.part_ab, ws.part_ab_cap, static_cast<size_t>(4 * (kStreamMaxK + 1)) * L.grid));
+    SG_TRY(ensure(ws.part_sk, ws.part_sk_cap, static_cast<size_t>(a.s) * sketch_grid(n)));
+    SG_TRY(ensure(ws.st_lists, ws.st_lists_cap, static_cast<size_t>(basis_lists_words(n, a.s, a.zeta))));
+    SG_TRY(ensure(ws.st_part, ws.st_part_cap,
+                  static_cast<size_t>(basis_sketch_grid(n)) * (a.d + 1) * static_cast<size_t>(a.s)));
+    if (L.hst) SG_TRY(ensure(ws.st_state, ws.st_state_cap, static_cast<size_t>(n)));
+    rc = build_sell(ws, a.A, a.precision, st);
+    if (rc) return rc;
+
+    SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
+    SG_TRY(hipMemsetAsync(ws.sc->phase_ticks, 0, sizeof(ws.sc->phase_ticks), st));
+    SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, a.b, nullptr, ws.r, ws.part_vec, st));
+    SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(n), &ws.sc->nf, nullptr, st));
+    rc = copy_scalars(ws, st);
+    if (rc) return rc;
+    const double nf = ws.host_sc->nf;
+    sgmres_info_t rep{};
+    if (!std::isfinite(nf)) return SGMRES_ENONFINITE;
+    if (nf == 0.0) {
+        SG_TRY(launch_fill(a.x, n, 0.0, st));
+        SG_TRY(hipStreamSynchronize(st));
+        if (info) *info = rep;
+        return SGMRES_OK;
+    }
+    int cycles = 0;
+    int status = SGMRES_OK;
+    CycleEvents ev;
+    if (a.profile) SG_TRY(ev.create());
+    for (;;) {
+        if (ev.on) SG_TRY(hipEventRecord(ev.r0, st));
+        SG_TRY(launch_residual(n, a.A.row_ptr, a.A.col_idx, a.A.val, a.b, a.x, ws.r, ws.part_vec, st));
+        SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(n), &ws.sc->beta, &ws.sc->nf, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.r1, st));
+        rc = copy_scalars(ws, st);
+        if (rc) return rc;
+        const DevScalars& h = *ws.host_sc;
+        if (ev.on) rep.t_residual_ms += CycleEvents::ms(ev.r0, ev.r1);
+        if (cycles > 0) {
+            rep.steps += h.dc;
+            rep.d_eff_last = h.d_eff;
+            rep.rest_est = h.rest / nf;
+            rep.kappa_est = h.kappa;
+            if (ev.on) {
+                rep.t_basis_ms += CycleEvents::ms(ev.b0, ev.b1);
+                rep.t_sketch_ms += CycleEvents::ms(ev.k1, ev.b1);
+                rep.t_lsq_ms += CycleEvents::ms(ev.b1, ev.l1);
+                rep.t_combine_ms += CycleEvents::ms(ev.l1, ev.c1);
+            }
+        }
+        rep.flags = h.flags | h.lsq_flags;
+        rep.relres = h.rho;
+        if (h.abort) {
+            status = SGMRES_ETIMEOUT;
+            break;
+        }
+        if (!std::isfinite(h.rho)) {
+            status = SGMRES_ENONFINITE;
+            break;
+        }
+        if (h.rho <= a.tol) {
+            status = SGMRES_OK;
+            break;
+        }
+        if (cycles > a.restarts) {
+            status = SGMRES_NOT_CONVERGED;
+            break;
+        }
+        const uint32_t cyc = static_cast<uint32_t>(cycles);
+        SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, st));
+        // tags of the step partials start at 1: clear the slots of earlier launches
+        SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.part_ab),
+                               static_cast<int64_t>(8 * (kStreamMaxK + 1)) * L.grid, 0u, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.b0, st));
+        StreamParams p{};
+        p.n = n;
+        p.sp = ws.sell_sp;
+        p.ci = ws.sell_col;
+        p.val = ws.sell_val;
+        p.r = ws.r;
+        p.beta = &ws.sc->beta;
+        p.B = ws.B;
+        p.ldb = ldb;
+        p.H = ws.H;
+        p.d = a.d;
+        p.k = kk;
+        p.part_a = ws.part_ab;
+        p.part_b = ws.part_ab + static_cast<int64_t>(2 * (kStreamMaxK + 1)) * L.grid;
+        p.state = ws.st_state;
+        p.sync = ws.sync;
+        p.per_block_release = a.per_block_release;
+        p.abort = &ws.sc->abort;
+        p.status = &ws.sc->dc;
+        p.spin_limit = kSpinLimitTicks;
+        p.phase_ticks = ev.on ? ws.sc->phase_ticks : nullptr;
+        SG_TRY(stream_launch(L, p, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.k1, st));
+        SG_TRY(launch_basis_lists(n, a.seed, cyc, a.s, a.zeta, ws.st_lists, st));
+        SG_TRY(launch_sketch_apply(n, ws.r, a.seed, cyc, a.s, a.zeta, ws.part_sk, ws.g, st));
+        SG_TRY(launch_basis_sketch(n, ws.B, ldb, 1, a.precision, a.d + 1, a.s, a.zeta, ws.st_lists, ws.st_part,
+                                   ws.SB, st));
+        SG_TRY(launch_relation(1, a.d, kk, a.s, ws.H, ws.SB, &ws.sc->dc, ws.SAB, st));
+        if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
+        rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
+        if (rc) return rc;
+        if (ev.on) SG_TRY(hipEventRecord(ev.l1, st));
+        SG_TRY(launch_combine(n, &ws.sc->d_eff, a.d, ws.B, ldb, ws.y, a.x, st, nullptr, a.precision));
+        if (ev.on) SG_TRY(hipEventRecord(ev.c1, st));
+        ++cycles;
+    }
+    rep.cycles = cycles;
+    if (cycles > 0) {
+        rep.path = SGMRES_PATH_STREAM;
+        rep.launch_block = kStreamBlock;
+        rep.launch_rows = L.hst ? -L.P : L.P;
+        rep.launch_grid = L.grid;
+    }
+    if (ev.on)
+        for (int q = 0; q < 8; ++q) rep.phase_us[q] = 1e-2 * static_cast<double>(ws.host_sc->phase_ticks[q]);
+    if (info) *info = rep;
+    return status;
+}
+
 int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     std::lock_guard<std::mutex> lock(g_mutex);
     Workspace* wsp = nullptr;
@@ -456,13 +623,24 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     const bool cheb = a.basis == SGMRES_BASIS_CHEBYSHEV;
     ChebCoef cf{};
     if (cheb && !cheb_coefficients(a.cheb_c, a.cheb_dx, a.cheb_dy, &cf)) return SGMRES_EINVAL;
-    ArnoldiLaunch L{};
-    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L, a.precision)
-              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0, a.precision);
-    if (rc == SGMRES_EINVAL && !cheb && kk <= kBatchMaxK && !a.block && !a.rows_per_thread) {
+    if (a.path == SGMRES_PATH_STREAM) return cheb ? SGMRES_EINVAL : solve_stream(a, ws, info);
+    if (a.path == SGMRES_PATH_PART_SPLIT) {
+        if (cheb || kk > kBatchMaxK) return SGMRES_EINVAL;
         SolveArgs b = a;
         b.k = kk;
         return solve_large(b, info);
+    }
+    ArnoldiLaunch L{};
+    rc = cheb ? prepare_cheb(ws, n, a.d, a.s, a.zeta, a.block, a.rows_per_thread, &L, a.precision)
+              : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0, a.precision);
+    if (rc == SGMRES_EINVAL && !cheb && !a.block && !a.rows_per_thread) {
+        // beyond the resident capacity: the streaming kernel, else the part-split one
+        if (kk <= kStreamMaxK && basis_sketch_fits(a.s, a.zeta)) return solve_stream(a, ws, info);
+        if (kk <= kBatchMaxK) {
+            SolveArgs b = a;
+            b.k = kk;
+            return solve_large(b, info);
+        }
     }
     if (rc) return rc;
     rc = check_csr(ws, a.A, st);
@@ -623,6 +801,11 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     a.basis = opts ? opts->basis : SGMRES_BASIS_ARNOLDI;
     a.precision = opts ? opts->precision : SGMRES_PREC_FP64;
     a.halo_off = opts ? opts->halo_off : 0;
+    a.path = opts ? opts->path : 0;
+    a.stream_state = opts ? opts->stream_state : 0;
+    if ((a.path != 0 && a.path != SGMRES_PATH_STREAM && a.path != SGMRES_PATH_PART_SPLIT) || a.stream_state < 0 ||
+        a.stream_state > 2)
+        return SGMRES_EINVAL;
     if (a.precision != SGMRES_PREC_FP64 && a.precision != SGMRES_PREC_FP32 && a.precision != SGMRES_PREC_BF16_BASIS)
         return SGMRES_EINVAL;
     if (a.basis != SGMRES_BASIS_ARNOLDI && a.basis != SGMRES_BASIS_CHEBYSHEV) return SGMRES_EINVAL;
@@ -1168,7 +1351,7 @@ void sgmres_release_workspace(void) {
                         w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_ab, w.part_sk,
                         w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sell_K, w.sell_sp, w.sell_col,
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
-                        w.t_scratch};
+                        w.t_scratch, w.st_lists, w.st_part, w.st_state};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);

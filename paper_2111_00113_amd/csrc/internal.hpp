@@ -117,6 +117,58 @@ size_t chebyshev_lds_bytes(int block, int R, int s, int zeta);
 hipError_t chebyshev_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
 hipError_t chebyshev_launch(const ArnoldiLaunch& L, ChebParams params, hipStream_t stream);
 
+// ---- streaming basis kernel (stream.hip) ----------------------------------
+// k-truncated Arnoldi for systems beyond the resident capacity and for blocks
+// of NR right-hand sides sharing A (pairs q = i * NR + rhs; see stream_kernel.hpp).
+constexpr int kStreamBlock = 1024;
+constexpr int kStreamMaxK = 4;
+struct StreamParams {
+    int64_t n;
+    const int64_t* sp;   // sliced ELL copy of A: slice starts,
+    const int32_t* ci;   // columns
+    const void* val;     // and values in the arithmetic type
+    const double* r;     // residuals, n * NR (pair order)
+    const double* beta;  // NR norms of r
+    void* B;             // d + 1 columns of n * NR entries (storage type), column stride ldb
+    int64_t ldb;
+    double* H;           // per right-hand side (k+1) x d, H[(rhs * d + j) * (k+1) + a]
+    int d, k;
+    unsigned long long* part_a;  // NR (k+1) x G tagged partials (two words each), zero at launch
+    unsigned long long* part_b;
+    void* state;         // HBM-state instances: n * NR entries (arithmetic type)
+    void* sync;          // SyncWords, zero at launch
+    int per_block_release;
+    int* abort;
+    int* status;         // NR = 1: [0] columns built, [1] flags (OR)
+    int* dc_rhs;         // NR > 1: columns built per right-hand side
+    int* flags_rhs;      // NR > 1: flags per right-hand side (OR)
+    uint64_t spin_limit;
+    unsigned long long* phase_ticks;
+};
+struct StreamLaunch {
+    const void* fn;
+    int NR, P, hst, grid;
+};
+// precision SGMRES_PREC_*; nr right-hand sides (1 or a divisor of 64)
+hipError_t stream_configure(int64_t n, int nr, int k, int precision, StreamLaunch* out);
+hipError_t stream_launch(const StreamLaunch& L, StreamParams params, hipStream_t stream);
+
+// ---- sketch of a finished basis (sketch_basis.hip) --------------------------
+// lists: the cycle's sparse sign pattern per 512-row chunk, basis_lists_words
+// 32-bit words; part: basis_sketch_grid(n) * nvec * s doubles; SB: nvec * s
+// (vector v = column v / nr, right-hand side v % nr; column-major s x nvec).
+// Requires basis_sketch_fits(s, zeta) (s <= 1024).
+int64_t basis_lists_words(int64_t n, int s, int zeta);
+int basis_sketch_grid(int64_t n);
+bool basis_sketch_fits(int s, int zeta);
+hipError_t launch_basis_lists(int64_t n, uint64_t seed, uint32_t cycle, int s, int zeta, uint32_t* lists,
+                              hipStream_t stream);
+hipError_t launch_basis_sketch(int64_t n, const void* B, int64_t ldb, int nr, int precision, int nvec, int s,
+                               int zeta, const uint32_t* lists, double* part, double* SB, hipStream_t stream);
+// S A B per right-hand side from S B and H (Arnoldi relation); dc_dev: 1 or nr ints
+hipError_t launch_relation(int nr, int d, int k, int s, const double* H, const double* SB, const int* dc_dev,
+                           double* SAB, hipStream_t stream);
+
 // ---- batched solve (batched.hip) ------------------------------------------
 // One descriptor per system (device copy); the basis, scratch vectors and the
 // sketch lists of a system live at its own offsets in the batch workspace.

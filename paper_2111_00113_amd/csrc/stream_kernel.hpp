@@ -1,0 +1,335 @@
+// Streaming k-truncated Arnoldi basis kernel: one cooperative launch per
+// cycle for systems beyond the resident kernels' capacity, and for blocks of
+// right-hand sides that share one matrix (arXiv:2111.00113, Algorithm 1 basis
+// loop; truncated-Arnoldi recurrence of Section 1.2.2 with two classical
+// Gram-Schmidt passes).
+//
+// Work items are (row, right-hand side) pairs q = i * NR + rhs, which is also
+// where the pair's entry sits in a basis column: column j of B holds the NR
+// bases' j-th vectors interleaved, so the gathers of one row's NR entries are
+// one contiguous run and the NR right-hand sides share every read of A.  A
+// tile is P * BLOCK consecutive pairs; thread t of a block takes pairs
+// tile * P * BLOCK + p * BLOCK + t, p < P, so its right-hand side is t % NR.
+// The window (the last k basis vectors) is read back from B; A is read through
+// its sliced ELL copy (entry e of row i at sp[i / 64] + 64 e + i % 64).
+//
+// Per step j (two tagged reductions and one grid barrier):
+//   phase 1  m = A b_j; per right-hand side partials <m,m>, W^T m  (tagged)
+//   phase 2  h = W^T m; w = m - W h; partials <w,w>, W^T w           (tagged)
+//   phase 3  h2 = W^T w; nu^2 = <w,w> - |h2|^2 (window orthonormal to
+//            rounding); b_{j+1} = (w - W h2) / nu; H column j   -- barrier --
+// With REG state (one tile per block) m and w stay in registers for the whole
+// step; otherwise (HST) each block walks its tiles and parks them in a state
+// buffer between phases.  The sketch is not formed here: S B is formed from
+// the finished basis and S A B from it through the Arnoldi relation
+// A b_j = sum_a H[a, j] b_{j-a} + nu_j b_{j+1} (so the last step also forms
+// b_{d+1}).
+#pragma once
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace sg {
+namespace stream_detail {
+
+constexpr int kBlock = kStreamBlock;
+constexpr int kNW = kBlock / kWave;
+constexpr int kNV = kStreamMaxK + 1;  // values per reduction: a norm and the window dots
+
+__device__ __forceinline__ double gs_sub(double x, double h, double v) { return __builtin_fma(-h, v, x); }
+__device__ __forceinline__ float gs_sub(float x, float h, float v) { return __builtin_fmaf(-h, v, x); }
+
+// Block sum per right-hand side of nv per-thread values (thread t holds values
+// of right-hand side t % NR), in a fixed order: the lanes of one right-hand
+// side inside a wavefront by an xor butterfly (the same bits in each of them),
+// then the wavefronts in order.  put(v, rhs, sum) is called once per value by
+// one thread.  red: kNW * nv * NR doubles.  Ends with a __syncthreads().
+template <int NR, typename Put>
+__device__ __forceinline__ void block_sum_rhs(const double (&vals)[kNV], int nv, double* red, Put put) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int v = 0; v < kNV; ++v) {
+        if (v < nv) {
+            double x = vals[v];
+#pragma unroll
+            for (int off = NR; off < kWave; off <<= 1) x += __shfl_xor(x, off, kWave);
+            if (lane < NR) red[(v * NR + lane) * kNW + wid] = x;
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nv * NR; idx += kBlock) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNW; ++q) acc += red[idx * kNW + q];
+        put(idx / NR, idx % NR, acc);
+    }
+    __syncthreads();
+}
+
+template <typename TC, typename TS, int NR, int P, bool HST>
+__global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
+    static_assert(kWave % NR == 0, "a wavefront holds whole rows of right-hand sides");
+    static_assert(P % 4 == 0 || P < 4, "pairs are walked in groups of four");
+    constexpr int T = P * kBlock;  // pairs per tile
+    constexpr int PG = P < 4 ? P : 4;
+    __shared__ double red[kNW * kNV * NR];
+    __shared__ double coefA[kNV * NR];  // [v * NR + rhs]: v = 0 <m,m>, 1 + a: h_a
+    __shared__ double coefB[kNV * NR];  // v = 0 <w,w>, 1 + a: h2_a
+    __shared__ double nus[NR];
+    __shared__ int dead[NR];
+    __shared__ int dcs[NR];
+    __shared__ unsigned sync_lds[3];
+
+    const int G = gridDim.x;
+    const int blk = xcd_logical_block(blockIdx.x, G);
+    const int tid = threadIdx.x;
+    const int wid_s = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int rhs = tid % NR;
+    const int64_t n = p.n;
+    const int64_t npairs = n * NR;
+    const int64_t nt = (npairs + T - 1) / T;
+    const int64_t t0 = HST ? (static_cast<int64_t>(blk) * nt) / G : blk;
+    const int64_t t1 = HST ? (static_cast<int64_t>(blk + 1) * nt) / G : blk + 1;
+    const int d = p.d, k = p.k;
+    const TC* Av = static_cast<const TC*>(p.val);
+    TS* Bs = static_cast<TS*>(p.B);
+    TC* state = static_cast<TC*>(p.state);
+    const int64_t ldb = p.ldb;
+    constexpr double uround = BasisPrec<TC>::unit_roundoff;
+    // columns start on 256-byte boundaries and blocks own whole cache lines
+    // of them: other blocks' entries of a column written during this launch
+    // are read with plain loads (no cache can hold a stale copy), else
+    // device-coherently
+    const bool fresh = ((reinterpret_cast<uintptr_t>(p.B) | static_cast<uintptr_t>(ldb * sizeof(TS))) & 255u) == 0;
+    auto ldB = [&](const TS* q) -> TC { return from_basis<TC>(fresh ? *q : load_coherent(q)); };
+
+    GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u, 0u,
+                 p.per_block_release != 0};
+    bar.setup(sync_lds);
+
+    const bool timing = p.phase_ticks != nullptr && blk == 0 && tid == 0;
+    uint64_t t_last = timing ? __builtin_amdgcn_s_memrealtime() : 0;
+    auto tick = [&](int q) {
+        if (timing) {
+            const uint64_t t = __builtin_amdgcn_s_memrealtime();
+            p.phase_ticks[q] += t - t_last;
+            t_last = t;
+        }
+    };
+
+    // ---- b_1 = r / |r| (a right-hand side with r = 0 is dead from the start)
+    if (tid < NR) {
+        dead[tid] = !(p.beta[tid] > 0.0);
+        dcs[tid] = dead[tid] ? 0 : d;
+    }
+    __syncthreads();
+    {
+        const double beta = p.beta[rhs];
+        const bool dz = dead[rhs] != 0;
+        for (int64_t tl = t0; tl < t1; ++tl) {
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>(pp * kBlock + tid);
+                if (q < npairs) Bs[q] = to_basis<TS>(dz ? TC(0) : static_cast<TC>(p.r[q] / beta));
+            }
+        }
+    }
+    bar.sync();  // b_1 complete everywhere
+
+    TC mreg[HST ? 1 : P];
+    int flags = 0;
+    int dc = d;
+    for (int j = 0; j < d; ++j) {
+        const int kw = min(j + 1, k);
+        const TS* bj = Bs + static_cast<int64_t>(j) * ldb;
+        const unsigned tag = static_cast<unsigned>(j + 1);
+        tick(0);
+
+        // ---- phase 1: m = A b_j, partials <m,m> and W^T m ------------------
+        double acc[kNV];
+#pragma unroll
+        for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
+        for (int64_t tl = t0; tl < t1; ++tl) {
+#pragma unroll
+            for (int g0 = 0; g0 < P; g0 += PG) {
+                // the PG pairs' rows, slice positions and widths (one slice per
+                // wavefront and pair: uniform, scalar)
+                int64_t spos[PG];
+                int sK[PG];
+                int lrow[PG];
+                int kmax = 0;
+#pragma unroll
+                for (int u = 0; u < PG; ++u) {
+                    // the wavefront's first pair; its NR-pair rows lie in one slice
+                    const int64_t qw = tl * T + static_cast<int64_t>(g0 + u) * kBlock + wid_s * kWave;
+                    lrow[u] = static_cast<int>(((static_cast<uint32_t>((g0 + u) * kBlock + tid)) / NR) & (kWave - 1));
+                    spos[u] = 0;
+                    sK[u] = 0;
+                    if (qw < npairs) {
+                        const int64_t sl = (qw / NR) / kWave;
+                        const int64_t a = p.sp[sl];
+                        spos[u] = a;
+                        sK[u] = static_cast<int>((p.sp[sl + 1] - a) / kWave);
+                    }
+                    kmax = max(kmax, sK[u]);
+                }
+                TC m[PG];
+#pragma unroll
+                for (int u = 0; u < PG; ++u) m[u] = TC(0);
+                for (int e = 0; e < kmax; ++e) {
+                    int c[PG];
+                    TC v[PG];
+#pragma unroll
+                    for (int u = 0; u < PG; ++u) {
+                        c[u] = 0;
+                        v[u] = TC(0);
+                        if (e < sK[u]) {
+                            const uint32_t a = static_cast<uint32_t>(e * kWave + lrow[u]);
+                            c[u] = (p.ci + spos[u])[a];
+                            v[u] = (Av + spos[u])[a];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < PG; ++u)
+                        if (e < sK[u]) m[u] += v[u] * ldB(bj + (static_cast<uint32_t>(c[u]) * NR + rhs));
+                }
+#pragma unroll
+                for (int u = 0; u < PG; ++u) {
+                    const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>((g0 + u) * kBlock + tid);
+                    if (q < npairs) {
+                        acc[0] += static_cast<double>(m[u] * m[u]);
+                        for (int a = 0; a < kw; ++a) {
+                            const TC wa = from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+                            acc[1 + a] += static_cast<double>(wa * m[u]);
+                        }
+                    }
+                    if constexpr (HST) {
+                        if (q < npairs) state[q] = m[u];
+                    } else {
+                        mreg[g0 + u] = m[u];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        block_sum_rhs<NR>(acc, kw + 1, red, [&](int v, int r, double val) {
+            tagged_store(p.part_a + 2 * (static_cast<int64_t>(v * NR + r) * G + blk), val, tag);
+        });
+        tick(1);
+
+        // ---- phase 2: h, w = m - W h, partials <w,w> and W^T w ------------
+        grid_sum_tagged(p.part_a, G, (kw + 1) * NR, tag, coefA, p.abort, p.spin_limit);
+        tick(2);
+#pragma unroll
+        for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
+        for (int64_t tl = t0; tl < t1; ++tl) {
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>(pp * kBlock + tid);
+                if (q < npairs) {
+                    TC w;
+                    if constexpr (HST) w = state[q];
+                    else w = mreg[pp];
+                    TC wa[kStreamMaxK];
+#pragma unroll
+                    for (int a = 0; a < kStreamMaxK; ++a)
+                        if (a < kw) wa[a] = from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+#pragma unroll
+                    for (int a = 0; a < kStreamMaxK; ++a)
+                        if (a < kw) w -= static_cast<TC>(coefA[(1 + a) * NR + rhs]) * wa[a];
+                    acc[0] += static_cast<double>(w * w);
+#pragma unroll
+                    for (int a = 0; a < kStreamMaxK; ++a)
+                        if (a < kw) acc[1 + a] += static_cast<double>(wa[a] * w);
+                    if constexpr (HST) state[q] = w;
+                    else mreg[pp] = w;
+                }
+                // one pair's window loads in flight at a time: keeps the
+                // register state of many pairs from spilling
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        block_sum_rhs<NR>(acc, kw + 1, red, [&](int v, int r, double val) {
+            tagged_store(p.part_b + 2 * (static_cast<int64_t>(v * NR + r) * G + blk), val, tag);
+        });
+        tick(3);
+
+        // ---- phase 3: h2, nu, b_{j+1} -------------------------------------
+        grid_sum_tagged(p.part_b, G, (kw + 1) * NR, tag, coefB, p.abort, p.spin_limit);
+        tick(4);
+        if (tid < NR) {
+            double h2sq = 0.0;
+            for (int a = 0; a < kw; ++a) h2sq += coefB[(1 + a) * NR + tid] * coefB[(1 + a) * NR + tid];
+            const double nu2 = coefB[tid] - h2sq;
+            const bool brk = !(nu2 > 16.0 * uround * uround * coefA[tid]);
+            nus[tid] = brk ? 0.0 : sqrt(nu2);
+            if (!dead[tid] && brk) {
+                dead[tid] = 1;
+                dcs[tid] = j + 1;
+            }
+        }
+        __syncthreads();
+        if (blk == 0) {
+            for (int idx = tid; idx < NR * (k + 1); idx += kBlock) {
+                const int r = idx / (k + 1), a = idx % (k + 1);
+                double hv = 0.0;
+                if (a == k) hv = nus[r];
+                else if (a < kw) hv = coefA[(1 + a) * NR + r] + coefB[(1 + a) * NR + r];
+                p.H[(static_cast<int64_t>(r) * d + j) * (k + 1) + a] = hv;
+            }
+        }
+        if constexpr (NR == 1) {
+            if (nus[0] == 0.0) {
+                dc = j + 1;
+                flags |= SGMRES_FLAG_BREAKDOWN;
+                break;
+            }
+        }
+        {
+            const double nu = nus[rhs];
+            const bool dz = !(nu > 0.0);
+            const TC nu_t = static_cast<TC>(nu);
+            TS* bn = Bs + static_cast<int64_t>(j + 1) * ldb;
+            for (int64_t tl = t0; tl < t1; ++tl) {
+#pragma unroll
+                for (int pp = 0; pp < P; ++pp) {
+                    const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>(pp * kBlock + tid);
+                    if (q < npairs) {
+                        TC w;
+                        if constexpr (HST) w = state[q];
+                        else w = mreg[pp];
+                        TC wa[kStreamMaxK];
+#pragma unroll
+                        for (int a = 0; a < kStreamMaxK; ++a)
+                            if (a < kw) wa[a] = from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+#pragma unroll
+                        for (int a = 0; a < kStreamMaxK; ++a)
+                            if (a < kw) w = gs_sub(w, static_cast<TC>(coefB[(1 + a) * NR + rhs]), wa[a]);
+                        bn[q] = to_basis<TS>(dz ? TC(0) : w / nu_t);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        tick(5);
+        bar.arrive(kBlock - kWave);
+        bar.wait_relaxed();
+        tick(6);
+    }
+    if (blk == 0 && tid == 0) {
+        if constexpr (NR == 1) {
+            p.status[0] = dc;
+            p.status[1] |= flags;
+        }
+    }
+    if constexpr (NR > 1) {
+        if (blk == 0 && tid < NR) {
+            p.dc_rhs[tid] = dcs[tid];
+            p.flags_rhs[tid] |= (dcs[tid] < d) ? SGMRES_FLAG_BREAKDOWN : 0;
+        }
+    }
+}
+
+}  // namespace stream_detail
+}  // namespace sg

@@ -27,6 +27,7 @@ PATH_ARNOLDI_3BAR = 1
 PATH_ARNOLDI_HALO = 2
 PATH_CHEBYSHEV = 3
 PATH_PART_SPLIT = 4
+PATH_STREAM = 5
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16_BASIS = 2
@@ -75,6 +76,7 @@ class _Info(ctypes.Structure):
         ("launch_block", ctypes.c_int32),
         ("launch_rows", ctypes.c_int32),
         ("launch_grid", ctypes.c_int32),
+        ("t_sketch_ms", ctypes.c_double),
     ]
 
 
@@ -95,6 +97,8 @@ class _Options(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("batch_eager", ctypes.c_int32),
         ("halo_off", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("stream_state", ctypes.c_int32),
     ]
 
 
@@ -215,7 +219,7 @@ def _info(i: _Info) -> dict:
                 rest_est=i.rest_est, kappa_est=i.kappa_est, t_residual_ms=i.t_residual_ms,
                 t_basis_ms=i.t_basis_ms, t_lsq_ms=i.t_lsq_ms, t_combine_ms=i.t_combine_ms,
                 phase_us=list(i.phase_us), path=i.path, launch_block=i.launch_block,
-                launch_rows=i.launch_rows, launch_grid=i.launch_grid)
+                launch_rows=i.launch_rows, launch_grid=i.launch_grid, t_sketch_ms=i.t_sketch_ms)
 
 
 def _raise(fn, rc):
@@ -226,7 +230,8 @@ def _raise(fn, rc):
 
 def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
                  transposed=False, block_size=0, rows_per_thread=0, profile=False, barrier_mode=0,
-                 spmv_mode=0, cheb_box=None, precision="fp64", halo_off=False, stream=None):
+                 spmv_mode=0, cheb_box=None, precision="fp64", halo_off=False, path=0, stream_state=0,
+                 stream=None):
     """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
 
     cheb_box=(c, dx, dy) selects the Chebyshev basis for a spectrum inside
@@ -235,15 +240,19 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     arithmetic, basis stored in bfloat16); the residual, least squares and x stay
     FP64, so restarting refines to FP64 accuracy.  halo_off=True keeps three grid
     barriers per truncated-Arnoldi step (the default uses two when few
-    nonzeros reach outside their block; results are bit-identical).  Returns (rc, info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED
-    (1); raises SGMRESError on the negative error codes."""
+    nonzeros reach outside their block; results are bit-identical).  path:
+    0 (automatic), PATH_STREAM or PATH_PART_SPLIT to force the kernel used for
+    systems beyond the resident capacity; stream_state: 0 auto, 1 registers,
+    2 HBM buffer (streaming path).  Returns (rc, info) with rc SGMRES_OK (0) or
+    SGMRES_NOT_CONVERGED (1); raises SGMRESError on the negative error codes."""
     _check_dev(b, torch.float64, A.n)
     _check_dev(x, torch.float64, A.n)
     info = _Info()
     basis, (cc, cdx, cdy) = (0, (0.0, 0.0, 0.0)) if cheb_box is None else (1, tuple(float(t) for t in cheb_box))
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
-                    barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec, 0, 1 if halo_off else 0)
+                    barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec, 0, 1 if halo_off else 0, path,
+                    stream_state)
     rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
                                ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     return _raise("sgmres_solve", rc), _info(info)
@@ -268,7 +277,7 @@ def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, z
     res = (_BatchResult * max(len(systems), 1))()
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 0, block_size, rows_per_thread, 0, 0, 0, 0, 0.0, 0.0, 0.0, prec,
-                    1 if eager else 0, 0)
+                    1 if eager else 0, 0, 0, 0)
     rc = lib().sgmres_solve_batched(len(systems), arr, d, k, s, seed, tol, restarts, ctypes.byref(opts), res,
                                     _stream(stream))
     _raise("sgmres_solve_batched", rc)
