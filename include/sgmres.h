@@ -139,7 +139,7 @@ typedef struct {
                            0 uses two when at most a quarter of the nonzeros reach outside
                            their row's block of the basis kernel (results are bit-identical) */
     int32_t path;       /* 0 auto: the resident kernels when the system fits them, else
-                           SGMRES_PATH_STREAM (k <= 4, s <= 1024), else the part-split
+                           SGMRES_PATH_STREAM (k <= 4, s <= 1024, n < 2^26), else the part-split
                            kernel (k <= 4); SGMRES_PATH_STREAM or SGMRES_PATH_PART_SPLIT
                            force that path (truncated Arnoldi only) */
     int32_t stream_state; /* streaming path: 0 auto, 1 keep m and w in registers (fails

@@ -462,7 +462,7 @@ int solve_stream(const SolveArgs& a, Workspace& ws, sgmres_info_t* info) {
     const int64_t n = a.A.n;
     const int kk = (a.k > a.d - 1) ? (a.d > 1 ? a.d - 1 : 1) : a.k;
     hipStream_t st = a.stream;
-    if (kk > kStreamMaxK || !basis_sketch_fits(a.s, a.zeta)) return SGMRES_EINVAL;
+    if (kk > kStreamMaxK || !basis_sketch_fits(n, a.s, a.zeta)) return SGMRES_EINVAL;
     StreamLaunch L{};
     if (stream_configure(n, 1, kk, a.precision, &L) != hipSuccess) return SGMRES_EINVAL;
     if (a.stream_state == 2 && !L.hst) {
@@ -585,7 +585,7 @@ int solve_stream(const SolveArgs& a, Workspace& ws, sgmres_info_t* info) {
         SG_TRY(stream_launch(L, p, st));
         if (ev.on) SG_TRY(hipEventRecord(ev.k1, st));
         SG_TRY(launch_basis_lists(n, a.seed, cyc, a.s, a.zeta, ws.st_lists, st));
-        SG_TRY(launch_sketch_apply(n, ws.r, a.seed, cyc, a.s, a.zeta, ws.part_sk, ws.g, st));
+        SG_TRY(launch_residual_sketch(n, ws.r, 1, a.s, a.zeta, ws.st_lists, ws.st_part, ws.g, st));
         SG_TRY(launch_basis_sketch(n, ws.B, ldb, 1, a.precision, a.d + 1, a.s, a.zeta, ws.st_lists, ws.st_part,
                                    ws.SB, st));
         SG_TRY(launch_relation(1, a.d, kk, a.s, ws.H, ws.SB, &ws.sc->dc, ws.SAB, st));
@@ -635,7 +635,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
               : prepare_arnoldi(ws, n, a.d, kk, a.s, a.zeta, a.block, a.rows_per_thread, &L, 0, a.precision);
     if (rc == SGMRES_EINVAL && !cheb && !a.block && !a.rows_per_thread) {
         // beyond the resident capacity: the streaming kernel, else the part-split one
-        if (kk <= kStreamMaxK && basis_sketch_fits(a.s, a.zeta)) return solve_stream(a, ws, info);
+        if (kk <= kStreamMaxK && basis_sketch_fits(n, a.s, a.zeta)) return solve_stream(a, ws, info);
         if (kk <= kBatchMaxK) {
             SolveArgs b = a;
             b.k = kk;

@@ -157,14 +157,18 @@ hipError_t stream_launch(const StreamLaunch& L, StreamParams params, hipStream_t
 // lists: the cycle's sparse sign pattern per 512-row chunk, basis_lists_words
 // 32-bit words; part: basis_sketch_grid(n) * nvec * s doubles; SB: nvec * s
 // (vector v = column v / nr, right-hand side v % nr; column-major s x nvec).
-// Requires basis_sketch_fits(s, zeta) (s <= 1024).
+// Requires basis_sketch_fits(n, s, zeta) (s <= 1024, n < 2^26).
 int64_t basis_lists_words(int64_t n, int s, int zeta);
 int basis_sketch_grid(int64_t n);
-bool basis_sketch_fits(int s, int zeta);
+bool basis_sketch_fits(int64_t n, int s, int zeta);
 hipError_t launch_basis_lists(int64_t n, uint64_t seed, uint32_t cycle, int s, int zeta, uint32_t* lists,
                               hipStream_t stream);
 hipError_t launch_basis_sketch(int64_t n, const void* B, int64_t ldb, int nr, int precision, int nvec, int s,
                                int zeta, const uint32_t* lists, double* part, double* SB, hipStream_t stream);
+// g (nr x s, right-hand side-major) = S r for nr interleaved FP64 residuals
+// (n * nr entries); part as above with nvec = nr
+hipError_t launch_residual_sketch(int64_t n, const double* r, int nr, int s, int zeta, const uint32_t* lists,
+                                  double* part, double* g, hipStream_t stream);
 // S A B per right-hand side from S B and H (Arnoldi relation); dc_dev: 1 or nr ints
 hipError_t launch_relation(int nr, int d, int k, int s, const double* H, const double* SB, const int* dc_dev,
                            double* SAB, hipStream_t stream);

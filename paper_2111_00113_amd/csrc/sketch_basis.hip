@@ -6,12 +6,14 @@
 //            by sketch row (ascending row inside each list, as in the basis
 //            kernels), written once per cycle to HBM
 //   vectors  per workgroup and group of 16 vectors: each chunk's tile of the
-//            16 vectors (512 rows, staged in LDS row-major, so a row's 16
-//            entries are one conflict-free read) is summed list by list into
-//            per-lane accumulators: lane group g (16 lanes, one per vector)
-//            owns sketch rows g, g + 64, ...; chunks in order, each list in
-//            order, so the block partial of every (vector, sketch row) has a
-//            fixed order of additions
+//            16 vectors (512 rows, staged in LDS row-major as doubles) is
+//            summed list by list: thread e owns sketch row e and adds the rows
+//            of list e (16 values each, eight 16-byte LDS reads) into its 16
+//            accumulators; chunks in order, each list in order, so the block
+//            partial of every (vector, sketch row) has a fixed order of
+//            additions.  List entries carry the row's tile offset and the sign
+//            bit, and list padding points at a zero row, so an entry costs one
+//            decode for 16 values
 //   finish   SB = (sum of the block partials in block order) / sqrt(zeta)
 //   relation S A b_j = sum_a H[a, j] S b_{j-a} + nu_j S b_{j+1}
 //
@@ -28,21 +30,35 @@ constexpr int kLsBlock = 256;
 constexpr int kLsRows = 2;
 constexpr int kChunk = kLsBlock * kLsRows;  // rows per chunk (512)
 constexpr int kVecBlock2 = 1024;
-constexpr int kCG = 16;                     // vectors per group (lanes per lane group)
-constexpr int kLaneGroups = kVecBlock2 / kCG;
-constexpr int kMaxU = 16;                   // sketch rows per lane group: s <= 1024
-constexpr int kTileStride = kCG + 1;        // doubles per staged row (padding against bank conflicts)
+constexpr int kMaxS = 1024;  // sketch rows: one thread each
 
-__device__ __forceinline__ double as_double(double v) { return v; }
-__device__ __forceinline__ double as_double(float v) { return static_cast<double>(v); }
-__device__ __forceinline__ double as_double(bf16_t v) { return static_cast<double>(from_basis<float>(v)); }
+// A chunk's tile of one group of kCG vectors is staged in LDS as doubles,
+// row-major with kTileStride entries per row (rows start on 16-byte
+// boundaries), plus one row of zeros (row kChunk) that list padding points at.
+// Thread e owns sketch row e (s <= 1024) and keeps one accumulator per vector
+// of the group.
+constexpr int kCG = 16;                          // vectors per group
+constexpr int kTileStride = kCG + 2;             // doubles per staged row (16-byte aligned rows)
+constexpr int kTileRows = kChunk + 1;
+constexpr int kRowUnits = kTileStride / 2;       // 16-byte units per staged row
+constexpr uint32_t kSignBit = 0x8000u;
 
-// per-chunk record in 32-bit words: lstart (s + 1), lcount (s), then the lists
-// (uint16, zeta * 512 + 3 s entries, groups of four)
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) { return static_cast<double>(v); }
+__device__ __forceinline__ double widen(bf16_t v) { return static_cast<double>(from_basis<float>(v)); }
+
+// Per-chunk record in 32-bit words: lstart (s + 1 entries, list starts in
+// uint16 entries, multiples of four), a spare word when s + 1 is odd, then the
+// lists: 16-bit entries in groups of four (each group one aligned 8-byte
+// word), entry = the row's offset in the tile in 16-byte units
+// (row * kRowUnits) | kSignBit when the sign is -1; the padding of a list's
+// last group points at the zero row.
+__host__ __device__ inline int64_t lists_offset(int s) { return (static_cast<int64_t>(s) + 2) & ~int64_t(1); }
 __host__ __device__ inline int64_t list_words(int s, int zeta) {
-    const int64_t w = (2 * static_cast<int64_t>(s) + 1) + (static_cast<int64_t>(zeta) * kChunk + 3 * s + 1) / 2;
+    const int64_t w = lists_offset(s) + (static_cast<int64_t>(zeta) * kChunk + 3 * s + 1) / 2;
     return (w + 63) / 64 * 64;
 }
+constexpr int kRecRegs = 12;  // record words per thread while the next chunk is fetched
 
 __global__ __launch_bounds__(kLsBlock) void lists_kernel(int64_t n, uint64_t seed, uint32_t cycle, int s, int zeta,
                                                         uint32_t* __restrict__ out) {
@@ -58,83 +74,140 @@ __global__ __launch_bounds__(kLsBlock) void lists_kernel(int64_t n, uint64_t see
     sketch_lists_build<kLsRows, kLsBlock, true>(seed, cycle, c0 + threadIdx.x, n, s, zeta, raw, lstart, lcount,
                                                 lists);
     uint32_t* rec = out + static_cast<int64_t>(blockIdx.x) * list_words(s, zeta);
-    for (int q = threadIdx.x; q < 2 * s + 1; q += kLsBlock) rec[q] = static_cast<uint32_t>(lstart[q]);
-    const int len = lstart[s];  // padded to groups of four
-    const uint32_t* lw = reinterpret_cast<const uint32_t*>(lists);
-    for (int q = threadIdx.x; q < (len + 1) / 2; q += kLsBlock) rec[2 * s + 1 + q] = lw[q];
+    for (int q = threadIdx.x; q <= s; q += kLsBlock) rec[q] = static_cast<uint32_t>(lstart[q]);
+    // one thread per list rewrites its entries (list order kept) and padding
+    uint16_t* dst = reinterpret_cast<uint16_t*>(rec + lists_offset(s));
+    for (int e = threadIdx.x; e < s; e += kLsBlock) {
+        const int a = lstart[e], b = lstart[e + 1], len = lcount[e];
+        for (int q = a; q < b; ++q) {
+            uint32_t t = static_cast<uint32_t>(kChunk * kRowUnits);  // zero row
+            if (q - a < len) {
+                const uint32_t key = lists[q];
+                t = (key >> 1) * kRowUnits | ((key & 1u) ? kSignBit : 0u);
+            }
+            dst[q] = static_cast<uint16_t>(t);
+        }
+    }
 }
 
+// TS: basis type.  Block blk takes a contiguous range of chunks; for each group
+// of kCG vectors (outer) and chunk (inner) it stages the chunk's tile and list
+// record, and thread e adds the tile rows of list e, each with its sign, into
+// its kCG accumulators (one 16-byte LDS read per two vectors, one FMA per
+// vector and entry, entries in list order).
 template <typename TS, int NR>
 __global__ __launch_bounds__(kVecBlock2) void vectors_kernel(int64_t n, const TS* __restrict__ B, int64_t ldb,
                                                              int nvec, int s, int zeta,
                                                              const uint32_t* __restrict__ recs,
                                                              double* __restrict__ part) {
+    static_assert(NR == 1 || NR % kCG == 0, "a group's vectors share one basis column");
     extern __shared__ __align__(16) unsigned char lds[];
-    double* tile = reinterpret_cast<double*>(lds);  // kChunk rows x kTileStride
-    uint32_t* rec = reinterpret_cast<uint32_t*>(tile + kChunk * kTileStride);
+    double* tile = reinterpret_cast<double*>(lds);  // kTileRows x kTileStride
+    uint32_t* rec = reinterpret_cast<uint32_t*>(tile + kTileRows * kTileStride);
+    constexpr int kTileRegs = kChunk * kCG / kVecBlock2;
     const int tid = threadIdx.x;
-    const int lg = tid / kCG;
-    const int c = tid % kCG;
     const int G = gridDim.x;
     const int blk = blockIdx.x;
     const int64_t nch = (n + kChunk - 1) / kChunk;
     const int64_t ch0 = (static_cast<int64_t>(blk) * nch) / G;
-    const int64_t ch1 = (static_cast<int64_t>(blk + 1) * nch) / G;
-    const int64_t lw = list_words(s, zeta);
-    const int U = (s + kLaneGroups - 1) / kLaneGroups;
+    const int64_t nchb = (static_cast<int64_t>(blk + 1) * nch) / G - ch0;  // chunks of this block
+    const int lw = static_cast<int>(list_words(s, zeta));
     const int64_t E = static_cast<int64_t>(nvec) * s;
-    for (int v0 = 0; v0 < nvec; v0 += kCG) {
-        double acc[kMaxU];
+    const int nvg = (nvec + kCG - 1) / kCG;
+    const int64_t nitems = static_cast<int64_t>(nvg) * nchb;  // (vector group, chunk), chunks fastest
+    for (int q = tid; q < kTileStride; q += kVecBlock2) tile[kChunk * kTileStride + q] = 0.0;
+
+    // the next item's tile and list record are fetched into registers while
+    // the current one is summed
+    TS treg[kTileRegs];
+    uint32_t rreg[kRecRegs];
+    auto fetch = [&](int64_t it) {
+        const int v0 = static_cast<int>(it / nchb) * kCG;
+        const int64_t ch = ch0 + it % nchb;
+        const int64_t r0 = ch * kChunk;
 #pragma unroll
-        for (int u = 0; u < kMaxU; ++u) acc[u] = 0.0;
-        for (int64_t ch = ch0; ch < ch1; ++ch) {
-            __syncthreads();  // the previous chunk's tile and lists are consumed
-            const uint32_t* src = recs + ch * lw;
-            const int used = 2 * s + 1 + (static_cast<int>(src[s]) + 1) / 2;  // lstart[s]: padded length
-            for (int q = tid; q < used; q += kVecBlock2) rec[q] = src[q];
-            const int64_t r0 = ch * kChunk;
-            for (int idx = tid; idx < kChunk * kCG; idx += kVecBlock2) {
-                int cc, l;
-                if constexpr (NR == 1) {
-                    cc = idx / kChunk;
-                    l = idx % kChunk;
-                } else {
-                    cc = idx % kCG;
-                    l = idx / kCG;
-                }
-                const int v = v0 + cc;
-                const int64_t i = r0 + l;
-                double x = 0.0;
-                if (v < nvec && i < n)
-                    x = as_double(B[static_cast<int64_t>(v / NR) * ldb + i * NR + (v % NR)]);
-                tile[l * kTileStride + cc] = x;
+        for (int u = 0; u < kTileRegs; ++u) {
+            const int idx = tid + u * kVecBlock2;
+            int cc, l;
+            if constexpr (NR == 1) {
+                cc = idx / kChunk;
+                l = idx % kChunk;
+            } else {
+                cc = idx % kCG;
+                l = idx / kCG;
             }
-            __syncthreads();
-            const int* lstart = reinterpret_cast<const int*>(rec);
-            const int* lcount = lstart + (s + 1);
-            const uint16_t* lists = reinterpret_cast<const uint16_t*>(rec + 2 * s + 1);
+            const int v = v0 + cc;
+            const int64_t i = r0 + l;
+            treg[u] = (v < nvec && i < n) ? B[static_cast<int64_t>(v / NR) * ldb + i * NR + (v % NR)] : TS{};
+        }
+        const uint32_t* src = recs + ch * lw;
 #pragma unroll
-            for (int u = 0; u < kMaxU; ++u) {
-                const int e = lg + kLaneGroups * u;
-                if (u < U && e < s) {
-                    const int len = lcount[e];
-                    const uint16_t* L = lists + lstart[e];
-                    double a = acc[u];
-                    for (int q = 0; q < len; ++q) {
-                        const unsigned key = L[q];
-                        const double x = tile[(key >> 1) * kTileStride + c];
-                        a += (key & 1u) ? -x : x;
-                    }
-                    acc[u] = a;
-                }
+        for (int u = 0; u < kRecRegs; ++u) {
+            const int q = tid + u * kVecBlock2;
+            rreg[u] = q < lw ? src[q] : 0u;
+        }
+    };
+    auto stage = [&](int64_t it) {
+        const int v0 = static_cast<int>(it / nchb) * kCG;
+        const int64_t r0 = (ch0 + it % nchb) * kChunk;
+#pragma unroll
+        for (int u = 0; u < kTileRegs; ++u) {
+            const int idx = tid + u * kVecBlock2;
+            int cc, l;
+            if constexpr (NR == 1) {
+                cc = idx / kChunk;
+                l = idx % kChunk;
+            } else {
+                cc = idx % kCG;
+                l = idx / kCG;
+            }
+            tile[l * kTileStride + cc] = (v0 + cc < nvec && r0 + l < n) ? widen(treg[u]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRecRegs; ++u) {
+            const int q = tid + u * kVecBlock2;
+            if (q < lw) rec[q] = rreg[u];
+        }
+    };
+    const double2* tile2 = reinterpret_cast<const double2*>(tile);
+    double acc[kCG];
+#pragma unroll
+    for (int c = 0; c < kCG; ++c) acc[c] = 0.0;
+    auto add_row = [&](uint32_t key) {
+        const double sg = (key & kSignBit) ? -1.0 : 1.0;
+        const double2* row = tile2 + (key & (kSignBit - 1u));
+#pragma unroll
+        for (int h = 0; h < kCG / 2; ++h) {
+            const double2 x = row[h];
+            acc[2 * h] = __builtin_fma(sg, x.x, acc[2 * h]);
+            acc[2 * h + 1] = __builtin_fma(sg, x.y, acc[2 * h + 1]);
+        }
+    };
+    if (nitems > 0) fetch(0);
+    for (int64_t it = 0; it < nitems; ++it) {
+        __syncthreads();  // the previous item's tile and lists are consumed
+        stage(it);
+        __syncthreads();
+        if (it + 1 < nitems) fetch(it + 1);
+        if (tid < s) {
+            const int* lstart = reinterpret_cast<const int*>(rec);
+            const uint2* L4 = reinterpret_cast<const uint2*>(rec + lists_offset(s));
+            const int g0 = lstart[tid] / 4, g1 = lstart[tid + 1] / 4;
+            for (int g = g0; g < g1; ++g) {  // groups of four entries, in list order
+                const uint2 w = L4[g];
+                add_row(w.x & 0xffffu);
+                add_row(w.x >> 16);
+                add_row(w.y & 0xffffu);
+                add_row(w.y >> 16);
             }
         }
-        const int v = v0 + c;
-        if (v < nvec) {
+        if (it % nchb == nchb - 1) {
+            const int v0 = static_cast<int>(it / nchb) * kCG;
 #pragma unroll
-            for (int u = 0; u < kMaxU; ++u) {
-                const int e = lg + kLaneGroups * u;
-                if (u < U && e < s) part[static_cast<int64_t>(blk) * E + static_cast<int64_t>(v) * s + e] = acc[u];
+            for (int c = 0; c < kCG; ++c) {
+                if (tid < s && v0 + c < nvec)
+                    part[static_cast<int64_t>(blk) * E + static_cast<int64_t>(v0 + c) * s + tid] = acc[c];
+                acc[c] = 0.0;
             }
         }
     }
@@ -207,7 +280,7 @@ template <typename TS, int NR>
 hipError_t launch_vectors(int64_t n, const TS* B, int64_t ldb, int nvec, int s, int zeta, const uint32_t* lists,
                           double* part, double* SB, hipStream_t stream) {
     const int G = basis_sketch_grid(n);
-    const size_t lds = sizeof(double) * kChunk * kTileStride + sizeof(uint32_t) * list_words(s, zeta);
+    const size_t lds = sizeof(double) * kTileRows * kTileStride + sizeof(uint32_t) * list_words(s, zeta);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(vectors_kernel<TS, NR>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -220,18 +293,21 @@ hipError_t launch_vectors(int64_t n, const TS* B, int64_t ldb, int nvec, int s, 
     return hipGetLastError();
 }
 
-bool basis_sketch_fits(int s, int zeta) {
-    return s >= 1 && s <= kLaneGroups * kMaxU &&
-           sizeof(double) * kChunk * kTileStride + sizeof(uint32_t) * list_words(s, zeta) <= 160 * 1024;
+bool basis_sketch_fits(int64_t n, int s, int zeta) {
+    return n < (int64_t(1) << 26) && s >= 1 && s <= kMaxS &&
+           list_words(s, zeta) <= static_cast<int64_t>(kRecRegs) * kVecBlock2 &&
+           sizeof(double) * kTileRows * kTileStride + sizeof(uint32_t) * list_words(s, zeta) <= 160 * 1024;
 }
 
 hipError_t launch_basis_sketch(int64_t n, const void* B, int64_t ldb, int nr, int precision, int nvec, int s,
                                int zeta, const uint32_t* lists, double* part, double* SB, hipStream_t stream) {
     if (nr == 1) {
         if (precision == SGMRES_PREC_FP64)
-            return launch_vectors<double, 1>(n, static_cast<const double*>(B), ldb, nvec, s, zeta, lists, part, SB, stream);
+            return launch_vectors<double, 1>(n, static_cast<const double*>(B), ldb, nvec, s, zeta, lists, part, SB,
+                                             stream);
         if (precision == SGMRES_PREC_FP32)
-            return launch_vectors<float, 1>(n, static_cast<const float*>(B), ldb, nvec, s, zeta, lists, part, SB, stream);
+            return launch_vectors<float, 1>(n, static_cast<const float*>(B), ldb, nvec, s, zeta, lists, part, SB,
+                                            stream);
         if (precision == SGMRES_PREC_BF16_BASIS)
             return launch_vectors<bf16_t, 1>(n, static_cast<const bf16_t*>(B), ldb, nvec, s, zeta, lists, part, SB,
                                              stream);
@@ -240,11 +316,20 @@ hipError_t launch_basis_sketch(int64_t n, const void* B, int64_t ldb, int nr, in
             return launch_vectors<double, 32>(n, static_cast<const double*>(B), ldb, nvec, s, zeta, lists, part, SB,
                                               stream);
         if (precision == SGMRES_PREC_FP32)
-            return launch_vectors<float, 32>(n, static_cast<const float*>(B), ldb, nvec, s, zeta, lists, part, SB, stream);
+            return launch_vectors<float, 32>(n, static_cast<const float*>(B), ldb, nvec, s, zeta, lists, part, SB,
+                                             stream);
         if (precision == SGMRES_PREC_BF16_BASIS)
             return launch_vectors<bf16_t, 32>(n, static_cast<const bf16_t*>(B), ldb, nvec, s, zeta, lists, part, SB,
                                               stream);
     }
+    return hipErrorInvalidValue;
+}
+
+// g = S r for nr interleaved FP64 residuals (one column), with the cycle's lists
+hipError_t launch_residual_sketch(int64_t n, const double* r, int nr, int s, int zeta, const uint32_t* lists,
+                                  double* part, double* g, hipStream_t stream) {
+    if (nr == 1) return launch_vectors<double, 1>(n, r, n, 1, s, zeta, lists, part, g, stream);
+    if (nr == 32) return launch_vectors<double, 32>(n, r, n * 32, 32, s, zeta, lists, part, g, stream);
     return hipErrorInvalidValue;
 }
 
