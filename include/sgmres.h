@@ -310,16 +310,22 @@ typedef struct {
  * system independently, with the method of sgmres_solve_ex for truncated
  * Arnoldi: the same sketch (keyed by seed, cycle and the row within the system)
  * and the same stopping rule per system, so system i gets what sgmres_solve_ex
- * gives for it alone, up to rounding.  Systems of at least 2^19 rows fill the
- * chip alone: they are solved one after another by the resident kernels of
- * sgmres_solve_ex.  The others run together, one persistent launch per cycle,
+ * gives for it alone, up to rounding.  Systems that share one matrix (the
+ * same three CSR pointers) and have at least 65,536 rows are solved as blocks
+ * of up to 32 right-hand sides (Section 1.3.3's setting of many right-hand
+ * sides, each with its own basis): one streaming basis launch per cycle builds
+ * every basis of the block, reading each nonzero of A once per step for all of
+ * them (SGMRES_PATH_STREAM; s <= 1024); opts->path = SGMRES_PATH_PART_SPLIT
+ * keeps them on the per-system kernels.  Other systems of at least 2^19 rows
+ * fill the chip alone: they are solved one after another by the resident
+ * kernels of sgmres_solve_ex.  The rest run together, one persistent launch per cycle,
  * each split into parts of at most 16384 rows taken by workgroups from a queue;
  * each cycle's kernels are replayed from a captured hipGraph.  opts: zeta,
  * kappa_max, precision (mixed precision
  * with FP64 refinement as in sgmres_solve_ex), block_size / rows_per_thread
  * (0 = 512 x 4 for batches under 2^20 rows, else chosen by timing the first
  * cycle of each candidate; the choice is kept
- * per problem class), batch_eager; other fields are ignored.
+ * per problem class), batch_eager, path; other fields are ignored.
  *   nsys     number of systems (0 returns SGMRES_OK)
  *   systems  host array of nsys systems; every n >= d, 1 <= k <= 4
  *   results  host array of nsys results, may be NULL

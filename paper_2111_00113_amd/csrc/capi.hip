@@ -129,6 +129,22 @@ struct Workspace {
     size_t st_part_cap = 0;
     double* st_state = nullptr;
     size_t st_state_cap = 0;
+    // block of right-hand sides: interleaved F, X, R; per right-hand side
+    // scalars and counters; pointer tables for pack / unpack
+    double* mr_F = nullptr;
+    size_t mr_F_cap = 0;
+    double* mr_X = nullptr;
+    size_t mr_X_cap = 0;
+    double* mr_R = nullptr;
+    size_t mr_R_cap = 0;
+    double* mr_part = nullptr;
+    size_t mr_part_cap = 0;
+    double* mr_scal = nullptr;  // nf, beta, rho, beta for the kernel (32 each), rest / kappa pairs (64)
+    size_t mr_scal_cap = 0;
+    int* mr_int = nullptr;  // dc (32), flags (32), d_eff / lsq flags pairs (64)
+    size_t mr_int_cap = 0;
+    void** mr_ptr = nullptr;  // 32 sources, 32 destinations
+    size_t mr_ptr_cap = 0;
 };
 
 std::mutex g_mutex;
@@ -858,6 +874,7 @@ constexpr size_t kArenaAlign = 256;
 constexpr int64_t kBatchTuneRows = int64_t(1) << 20;  // smaller batches use 512 x 4
 constexpr int64_t kBatchResidentRows = int64_t(1) << 19;  // such systems go to the resident kernels
 constexpr int64_t kBatchPartRows = 16384;              // rows per part of a large system
+constexpr int64_t kBlockMinRows = int64_t(1) << 16;  // systems sharing A from this size on: block solve
 
 using BatchKey = std::tuple<int, int, int, int, int, int, int>;
 std::map<BatchKey, BatchCand> g_batch_tuned;
@@ -1129,6 +1146,196 @@ int batch_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, i
     return all;
 }
 
+// A block of nb <= 32 right-hand sides sharing A, solved together: one
+// streaming basis launch per cycle builds all nb bases, reading each nonzero
+// of A once for all of them (pairs (row, right-hand side) interleaved), then
+// per right-hand side the sketched least squares and x += B y.  A right-hand
+// side that has converged (or run out of restarts) rides along as a zero
+// basis.  Caller holds g_mutex and has checked A.
+constexpr int kBlockRhs = 32;
+int block_solve_locked(const sgmres_csr_t& A, int nb, const sgmres_system_t* sys, int d, int k, int s, uint64_t seed,
+                       double tol, int restarts, int zeta, double kappa_max, int prec, sgmres_batch_result_t* res,
+                       hipStream_t st) {
+    constexpr int NR = kBlockRhs;
+    if (nb < 1 || nb > NR) return SGMRES_EINVAL;
+    const int64_t n = A.n;
+    const int kk = (k > d - 1) ? (d > 1 ? d - 1 : 1) : k;
+    if (kk > kStreamMaxK || !basis_sketch_fits(n, s, zeta)) return SGMRES_EINVAL;
+    Workspace* wsp = nullptr;
+    int rc = workspace(&wsp);
+    if (rc) return rc;
+    Workspace& ws = *wsp;
+    StreamLaunch L{};
+    if (stream_configure(n, NR, kk, prec, &L) != hipSuccess) return SGMRES_EINVAL;
+    const size_t np = static_cast<size_t>(n) * NR;
+    const int64_t ldb = static_cast<int64_t>((np + 127) / 128 * 128);
+    const size_t eb = basis_elem_bytes(prec);
+    SG_TRY(ensure(ws.mr_F, ws.mr_F_cap, np));
+    SG_TRY(ensure(ws.mr_X, ws.mr_X_cap, np));
+    SG_TRY(ensure(ws.mr_R, ws.mr_R_cap, np));
+    SG_TRY(ensure(ws.mr_part, ws.mr_part_cap, static_cast<size_t>(multi_grid(n, NR)) * NR));
+    SG_TRY(ensure(ws.mr_scal, ws.mr_scal_cap, static_cast<size_t>(6 * NR)));
+    SG_TRY(ensure(ws.mr_int, ws.mr_int_cap, static_cast<size_t>(4 * NR)));
+    SG_TRY(ensure(ws.mr_ptr, ws.mr_ptr_cap, static_cast<size_t>(2 * NR)));
+    SG_TRY(ensure(ws.B, ws.B_cap, (static_cast<size_t>(ldb) * (d + 1) * eb + 7) / 8));
+    SG_TRY(ensure(ws.H, ws.H_cap, static_cast<size_t>(NR) * (kk + 1) * d));
+    SG_TRY(ensure(ws.SB, ws.SB_cap, static_cast<size_t>(NR) * s * (d + 1)));
+    SG_TRY(ensure(ws.SAB, ws.SAB_cap, static_cast<size_t>(NR) * s * d));
+    SG_TRY(ensure(ws.g, ws.g_cap, static_cast<size_t>(NR) * s));
+    SG_TRY(ensure(ws.y, ws.y_cap, static_cast<size_t>(NR) * d));
+    SG_TRY(ensure(ws.tau, ws.tau_cap, static_cast<size_t>(d)));
+    SG_TRY(ensure(ws.part_ab, ws.part_ab_cap, static_cast<size_t>(4 * (kStreamMaxK + 1) * NR) * L.grid));
+    SG_TRY(ensure(ws.st_lists, ws.st_lists_cap, static_cast<size_t>(basis_lists_words(n, s, zeta))));
+    SG_TRY(ensure(ws.st_part, ws.st_part_cap,
+                  static_cast<size_t>(basis_sketch_grid(n)) * (d + 1) * NR * static_cast<size_t>(s)));
+    if (L.hst) SG_TRY(ensure(ws.st_state, ws.st_state_cap, np));
+    rc = build_sell(ws, A, prec, st);
+    if (rc) return rc;
+
+    double* nf_d = ws.mr_scal;
+    double* beta_d = nf_d + NR;
+    double* rho_d = beta_d + NR;
+    double* betak_d = rho_d + NR;
+    double* rk_d = betak_d + NR;  // (rest, kappa) per right-hand side
+    int* dc_d = ws.mr_int;
+    int* fl_d = dc_d + NR;
+    int* de_d = fl_d + NR;  // (d_eff, lsq flags) per right-hand side
+    std::vector<void*> ptrs(2 * NR, nullptr);
+    for (int r = 0; r < nb; ++r) {
+        ptrs[r] = const_cast<double*>(sys[r].b);
+        ptrs[NR + r] = sys[r].x;
+    }
+    SG_TRY(hipMemcpyAsync(ws.mr_ptr, ptrs.data(), sizeof(void*) * 2 * NR, hipMemcpyHostToDevice, st));
+    SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.mr_int), 4 * NR, 0u, st));
+    SG_TRY(launch_pack(n, NR, reinterpret_cast<const double* const*>(ws.mr_ptr), ws.mr_F, st));
+    SG_TRY(launch_pack(n, NR, reinterpret_cast<const double* const*>(ws.mr_ptr + NR), ws.mr_X, st));
+    SG_TRY(launch_residual_multi(n, NR, A.row_ptr, A.col_idx, A.val, ws.mr_F, nullptr, ws.mr_R, ws.mr_part, nullptr,
+                                 nf_d, nullptr, st));
+    std::vector<double> hs(6 * NR);
+    std::vector<int> hi(4 * NR);
+    auto read_back = [&]() -> int {
+        SG_TRY(hipMemcpyAsync(hs.data(), ws.mr_scal, sizeof(double) * 6 * NR, hipMemcpyDeviceToHost, st));
+        SG_TRY(hipMemcpyAsync(hi.data(), ws.mr_int, sizeof(int) * 4 * NR, hipMemcpyDeviceToHost, st));
+        SG_TRY(hipStreamSynchronize(st));
+        return SGMRES_OK;
+    };
+    // b = 0 gives x = 0 (as sgmres_solve): pack those initial guesses as zero
+    rc = read_back();
+    if (rc) return rc;
+    bool zero_b = false;
+    for (int r = 0; r < nb; ++r)
+        if (hs[r] == 0.0) {
+            ptrs[NR + r] = nullptr;
+            zero_b = true;
+        }
+    if (zero_b) {
+        SG_TRY(hipMemcpyAsync(ws.mr_ptr + NR, ptrs.data() + NR, sizeof(void*) * NR, hipMemcpyHostToDevice, st));
+        SG_TRY(launch_pack(n, NR, reinterpret_cast<const double* const*>(ws.mr_ptr + NR), ws.mr_X, st));
+        for (int r = 0; r < nb; ++r) ptrs[NR + r] = sys[r].x;
+        SG_TRY(hipMemcpyAsync(ws.mr_ptr + NR, ptrs.data() + NR, sizeof(void*) * NR, hipMemcpyHostToDevice, st));
+        SG_TRY(hipStreamSynchronize(st));
+    }
+    std::vector<int> cycles(NR, 0), steps(NR, 0), flags(NR, 0), code(NR, SGMRES_NOT_CONVERGED);
+    std::vector<char> done(NR, 1);
+    for (int r = 0; r < nb; ++r) done[r] = 0;
+    std::vector<double> relres(NR, 0.0), betak(NR, 0.0);
+    SG_TRY(hipMemsetAsync(&ws.sc->abort, 0, sizeof(int), st));
+    for (int c = 0;; ++c) {
+        SG_TRY(launch_residual_multi(n, NR, A.row_ptr, A.col_idx, A.val, ws.mr_F, ws.mr_X, ws.mr_R, ws.mr_part, nf_d,
+                                     beta_d, rho_d, st));
+        rc = read_back();
+        if (rc) return rc;
+        if (c > 0) {
+            SG_TRY(hipMemcpyAsync(ws.host_sc, ws.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+            SG_TRY(hipStreamSynchronize(st));
+            if (ws.host_sc->abort) return SGMRES_ETIMEOUT;
+        }
+        int active = 0;
+        for (int r = 0; r < nb; ++r) {
+            if (done[r]) continue;
+            if (c > 0) {
+                steps[r] += hi[r];
+                flags[r] |= hi[NR + r] | hi[2 * NR + 2 * r + 1];
+            }
+            const double rho = hs[2 * NR + r];
+            relres[r] = rho;
+            if (!std::isfinite(rho) || !std::isfinite(hs[r])) {
+                code[r] = SGMRES_ENONFINITE;
+                done[r] = 1;
+            } else if (rho <= tol) {
+                code[r] = SGMRES_OK;
+                done[r] = 1;
+            } else if (cycles[r] > restarts) {
+                code[r] = SGMRES_NOT_CONVERGED;
+                done[r] = 1;
+            } else {
+                ++active;
+            }
+        }
+        if (!active) break;
+        for (int r = 0; r < NR; ++r) betak[r] = (r < nb && !done[r]) ? hs[NR + r] : 0.0;
+        SG_TRY(hipMemcpyAsync(betak_d, betak.data(), sizeof(double) * NR, hipMemcpyHostToDevice, st));
+        const uint32_t cyc = static_cast<uint32_t>(c);
+        SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, st));
+        SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.part_ab),
+                               static_cast<int64_t>(8 * (kStreamMaxK + 1) * NR) * L.grid, 0u, st));
+        SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(dc_d), 2 * NR, 0u, st));
+        StreamParams p{};
+        p.n = n;
+        p.sp = ws.sell_sp;
+        p.ci = ws.sell_col;
+        p.val = ws.sell_val;
+        p.r = ws.mr_R;
+        p.beta = betak_d;
+        p.B = ws.B;
+        p.ldb = ldb;
+        p.H = ws.H;
+        p.d = d;
+        p.k = kk;
+        p.part_a = ws.part_ab;
+        p.part_b = ws.part_ab + static_cast<int64_t>(2 * (kStreamMaxK + 1) * NR) * L.grid;
+        p.state = ws.st_state;
+        p.sync = ws.sync;
+        p.abort = &ws.sc->abort;
+        p.dc_rhs = dc_d;
+        p.flags_rhs = fl_d;
+        p.spin_limit = kSpinLimitTicks;
+        SG_TRY(stream_launch(L, p, st));
+        SG_TRY(launch_basis_lists(n, seed, cyc, s, zeta, ws.st_lists, st));
+        SG_TRY(launch_residual_sketch(n, ws.mr_R, NR, s, zeta, ws.st_lists, ws.st_part, ws.g, st));
+        SG_TRY(launch_basis_sketch(n, ws.B, ldb, NR, prec, (d + 1) * NR, s, zeta, ws.st_lists, ws.st_part, ws.SB, st));
+        SG_TRY(launch_relation(NR, d, kk, s, ws.H, ws.SB, dc_d, ws.SAB, st));
+        SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(de_d), 2 * NR, 0u, st));
+        for (int r = 0; r < nb; ++r) {
+            if (done[r]) continue;
+            double* C = ws.SAB + static_cast<int64_t>(r) * d * s;
+            double* gr = ws.g + static_cast<int64_t>(r) * s;
+            double* yr = ws.y + static_cast<int64_t>(r) * d;
+            if (s <= kLsqPipeMaxS)
+                SG_TRY(launch_lsq_pipeline(s, d, dc_d + r, 0, C, gr, ws.tau, kappa_max, yr, rk_d + 2 * r, de_d + 2 * r,
+                                           ws.lsq_sync, &ws.sc->abort, kSpinLimitTicks, st));
+            else
+                SG_TRY(launch_lsq(s, dc_d + r, 0, C, gr, kappa_max, yr, rk_d + 2 * r, de_d + 2 * r, st));
+            ++cycles[r];
+        }
+        SG_TRY(launch_combine_multi(n, NR, d, de_d, 2, ws.B, ldb, ws.y, ws.mr_X, prec, st));
+    }
+    SG_TRY(launch_unpack(n, NR, ws.mr_X, reinterpret_cast<double* const*>(ws.mr_ptr + NR), st));
+    SG_TRY(hipStreamSynchronize(st));
+    int all = SGMRES_OK;
+    for (int r = 0; r < nb; ++r) {
+        if (code[r] != SGMRES_OK) all = SGMRES_NOT_CONVERGED;
+        if (res) {
+            res[r].status = code[r];
+            res[r].cycles = cycles[r];
+            res[r].steps = steps[r];
+            res[r].flags = flags[r];
+            res[r].relres = relres[r];
+        }
+    }
+    return all;
+}
+
 }  // namespace
 }  // namespace sg
 
@@ -1351,7 +1558,8 @@ void sgmres_release_workspace(void) {
                         w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_ab, w.part_sk,
                         w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sell_K, w.sell_sp, w.sell_col,
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
-                        w.t_scratch, w.st_lists, w.st_part, w.st_state};
+                        w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
+                        w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);
@@ -1374,11 +1582,38 @@ int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k,
     for (int i = 0; i < nsys; ++i) {
         const sgmres_system_t& y = systems[i];
         if (!csr_ok(&y.A) || !y.b || !y.x || bad_sizes(y.A.n, d, k, s, zeta)) return SGMRES_EINVAL;
-        (y.A.n >= kBatchResidentRows ? big : small).push_back(i);
+    }
+    // Systems that share one matrix (the same CSR arrays) with at least
+    // kBlockMinRows rows go, up to 32 at a time, to the block solve (one
+    // streaming basis launch per cycle for all of them, each nonzero of A read
+    // once per step for the whole block)
+    std::vector<std::vector<int>> blocks;
+    {
+        std::map<std::tuple<const void*, const void*, const void*, int64_t>, std::vector<int>> by_matrix;
+        for (int i = 0; i < nsys; ++i) {
+            const sgmres_csr_t& A = systems[i].A;
+            by_matrix[std::make_tuple(static_cast<const void*>(A.row_ptr), static_cast<const void*>(A.col_idx),
+                                      static_cast<const void*>(A.val), A.n)]
+                .push_back(i);
+        }
+        std::vector<char> in_block(nsys, 0);
+        const bool blockable = k <= kStreamMaxK && !(opts && opts->path == SGMRES_PATH_PART_SPLIT);
+        for (auto& kv : by_matrix) {
+            std::vector<int>& v = kv.second;
+            std::sort(v.begin(), v.end());
+            const int64_t n = std::get<3>(kv.first);
+            if (!blockable || v.size() < 2 || n < kBlockMinRows || !basis_sketch_fits(n, s, zeta)) continue;
+            for (size_t q = 0; q < v.size(); q += kBlockRhs) {
+                blocks.emplace_back(v.begin() + q, v.begin() + std::min(v.size(), q + kBlockRhs));
+                for (size_t u = q; u < std::min(v.size(), q + kBlockRhs); ++u) in_block[v[u]] = 1;
+            }
+        }
+        for (int i = 0; i < nsys; ++i)
+            if (!in_block[i]) (systems[i].A.n >= kBatchResidentRows ? big : small).push_back(i);
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     int all = SGMRES_OK;
-    if (!big.empty()) {
+    if (!big.empty() || !blocks.empty()) {
         // every CSR is checked before anything is solved
         std::lock_guard<std::mutex> lock(g_mutex);
         Workspace* wsp = nullptr;
@@ -1391,6 +1626,22 @@ int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k,
         rc = copy_scalars(*wsp, st);
         if (rc) return rc;
         if (wsp->host_sc->csr_bad) return SGMRES_ECSR;
+    }
+    for (const std::vector<int>& blk : blocks) {
+        std::vector<sgmres_system_t> sub(blk.size());
+        std::vector<sgmres_batch_result_t> sres(blk.size());
+        for (size_t q = 0; q < blk.size(); ++q) sub[q] = systems[blk[q]];
+        const double kmax = (opts && opts->kappa_max > 0) ? opts->kappa_max : 1e14;
+        int rc;
+        {
+            std::lock_guard<std::mutex> lock(g_mutex);
+            rc = block_solve_locked(sub[0].A, static_cast<int>(sub.size()), sub.data(), d, k, s, seed, tol, restarts,
+                                    zeta, kmax, prec, sres.data(), st);
+        }
+        if (rc < 0) return rc;
+        if (rc != SGMRES_OK) all = SGMRES_NOT_CONVERGED;
+        if (results)
+            for (size_t q = 0; q < blk.size(); ++q) results[blk[q]] = sres[q];
     }
     for (int i : big) {
         sgmres_options_t o{};

@@ -173,6 +173,21 @@ hipError_t launch_residual_sketch(int64_t n, const double* r, int nr, int s, int
 hipError_t launch_relation(int nr, int d, int k, int s, const double* H, const double* SB, const int* dc_dev,
                            double* SAB, hipStream_t stream);
 
+// ---- blocks of right-hand sides, interleaved (multi.hip) -------------------
+constexpr int kMultiMaxGrid = 2048;
+int multi_grid(int64_t n, int nr);  // workgroups of the residual (slots of part)
+// dst[i nr + r] = src[r][i] (src[r] null: 0); dst[r][i] = src[i nr + r] (dst[r] null: skipped)
+hipError_t launch_pack(int64_t n, int nr, const double* const* src, double* dst, hipStream_t stream);
+hipError_t launch_unpack(int64_t n, int nr, const double* src, double* const* dst, hipStream_t stream);
+// R = F - A X (X null: R = F); out[r] = |R_r|, rel[r] = out[r] / nf[r] when nf
+// is given; part: multi_grid(n, nr) * nr doubles
+hipError_t launch_residual_multi(int64_t n, int nr, const int32_t* rp, const int32_t* ci, const double* val,
+                                 const double* F, const double* X, double* R, double* part, const double* nf,
+                                 double* out, double* rel, hipStream_t stream);
+// X += B[:, :d_eff[r dstride]] y_r per right-hand side (B interleaved, column stride ldb)
+hipError_t launch_combine_multi(int64_t n, int nr, int d, const int* d_eff, int dstride, const void* B, int64_t ldb,
+                                const double* y, double* X, int precision, hipStream_t stream);
+
 // ---- batched solve (batched.hip) ------------------------------------------
 // One descriptor per system (device copy); the basis, scratch vectors and the
 // sketch lists of a system live at its own offsets in the batch workspace.

@@ -259,13 +259,16 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
 
 
 def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
-                         precision="fp64", block_size=0, rows_per_thread=0, eager=False, stream=None):
+                         precision="fp64", block_size=0, rows_per_thread=0, eager=False, path=0, stream=None):
     """Restarted sGMRES on many independent systems in one launch per cycle.
 
     systems: list of (DeviceCSR A, b, x) with b, x float64 GPU tensors (x is the
     initial guess, updated in place); several systems may share one A.  Returns
     (rc, results) with rc SGMRES_OK when all converged, SGMRES_NOT_CONVERGED
-    otherwise, and one dict per system (status, cycles, steps, flags, relres)."""
+    otherwise, and one dict per system (status, cycles, steps, flags, relres).
+    Systems sharing one DeviceCSR (n >= 65,536) are solved as blocks of up to
+    32 right-hand sides by the streaming kernel; path=PATH_PART_SPLIT keeps
+    them on the part-split kernel instead."""
     arr = (_System * max(len(systems), 1))()
     keep = []
     for i, (A, b, x) in enumerate(systems):
@@ -277,7 +280,7 @@ def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, z
     res = (_BatchResult * max(len(systems), 1))()
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 0, block_size, rows_per_thread, 0, 0, 0, 0, 0.0, 0.0, 0.0, prec,
-                    1 if eager else 0, 0, 0, 0)
+                    1 if eager else 0, 0, path, 0)
     rc = lib().sgmres_solve_batched(len(systems), arr, d, k, s, seed, tol, restarts, ctypes.byref(opts), res,
                                     _stream(stream))
     _raise("sgmres_solve_batched", rc)
