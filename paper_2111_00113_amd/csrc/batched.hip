@@ -537,10 +537,26 @@ hipError_t batch_configure(int block, int R, int d, int s, int zeta, int precisi
     return hipSuccess;
 }
 
+// A cooperative launch: the runtime starts the grid only when every workgroup
+// can be resident at once (grid <= occupancy x CUs), which the parts of a
+// system waiting for each other rely on (a launch that cannot be placed
+// fails instead of leaving a part to wait for a partner that never starts).
+// The attribute form is also what a stream capture records as a cooperative
+// kernel node.
 hipError_t batch_launch(const BatchLaunch& L, const BatchParams& p, hipStream_t stream) {
     BatchParams q = p;
     void* args[] = {&q};
-    return hipLaunchKernel(L.fn, dim3(L.grid), dim3(L.block), args, L.lds, stream);
+    hipLaunchAttribute attr{};
+    attr.id = hipLaunchAttributeCooperative;
+    attr.val.cooperative = 1;
+    hipLaunchConfig_t cfg{};
+    cfg.gridDim = dim3(L.grid);
+    cfg.blockDim = dim3(L.block);
+    cfg.dynamicSmemBytes = L.lds;
+    cfg.stream = stream;
+    cfg.attrs = &attr;
+    cfg.numAttrs = 1;
+    return hipLaunchKernelExC(&cfg, L.fn, args);
 }
 
 hipError_t launch_batch_advance(int* ctr, BatchState* st, unsigned* gcnt, int nsys, hipStream_t stream) {

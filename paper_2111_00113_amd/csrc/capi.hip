@@ -1082,7 +1082,7 @@ int batch_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, i
     bp.ntask = static_cast<int>(tasks.size());
 
     SG_TRY(launch_batch_reset(ws.bt_st, ws.bt_gcnt, nsys, ctr, st));
-    const bool eager = opts && opts->batch_eager;
+    bool eager = opts && opts->batch_eager;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if (!eager) {
@@ -1096,8 +1096,14 @@ int batch_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, i
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
+            // a runtime that cannot record the cooperative launch: launch the
+            // cycles directly (same kernels, same bits)
+            if (exec) (void)hipGraphExecDestroy(exec);
             if (graph) (void)hipGraphDestroy(graph);
-            return to_code(e);
+            exec = nullptr;
+            graph = nullptr;
+            (void)hipGetLastError();
+            eager = true;
         }
     }
     int status = SGMRES_OK;
