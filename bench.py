@@ -332,6 +332,7 @@ def main() -> int:
                          "batch: many systems per launch against one-at-a-time FP64 solves")
     ap.add_argument("--batch-count", type=int, default=256, help="systems in the many-systems workload")
     ap.add_argument("--block-rhs", type=int, default=32, help="right-hand sides of the n = 2^20 block")
+    ap.add_argument("--halo-off", action="store_true", help="truncated Arnoldi: three grid barriers per step")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "part-split"],
                     help="basis kernel for systems beyond the resident capacity (auto: streaming)")
     ap.add_argument("--stream-state", type=int, default=0, choices=[0, 1, 2],
@@ -385,7 +386,8 @@ def main() -> int:
         rc, info = sg.sgmres_solve(dA, fb, x, d, k, s, p["seed"], p["tol"], p["restarts"], zeta=p["zeta"],
                                    profile=profile, block_size=args.block_size,
                                    rows_per_thread=args.rows_per_thread, spmv_mode=args.spmv_mode, cheb_box=box,
-                                   precision=args.precision, path=path, stream_state=args.stream_state)
+                                   precision=args.precision, path=path, stream_state=args.stream_state,
+                                   halo_off=args.halo_off)
         if rc != sg.OK:
             raise RuntimeError(f"solve did not converge: {info}")
         return info

@@ -178,6 +178,28 @@ int sgmres_solve_ex(const sgmres_csr_t *A, const double *b, double *x, int d, in
                     uint64_t seed, double tol, int restarts, const sgmres_options_t *opts,
                     sgmres_info_t *info, void *stream);
 
+/* Plan: a matrix's set-up, done once and reused by many solves.
+ * sgmres_plan_create validates A's CSR arrays
+ * (SGMRES_ECSR if malformed) and builds on the current device the sliced ELL
+ * copy the basis kernels read (FP64 values; also FP32 values with
+ * SGMRES_PLAN_FP32) and, with SGMRES_PLAN_TRANSPOSE, CSR(A^T) and its copies,
+ * so sgmres_solve_plan with opts->transposed solves A^T x = b without
+ * rebuilding the transpose (the adjoint solve of a differentiable step).  The
+ * plan keeps pointers to A's arrays, which must stay unchanged while it lives;
+ * it owns everything else and frees it in sgmres_plan_destroy.  A plan is used
+ * on the device it was created on (SGMRES_EINVAL otherwise).  sgmres_solve_plan
+ * takes the arguments of sgmres_solve_ex after the matrix and gives the same
+ * bits; it returns SGMRES_EINVAL when the plan lacks the copy the precision or
+ * the transposition asks for. */
+#define SGMRES_PLAN_TRANSPOSE 1
+#define SGMRES_PLAN_FP32 2
+typedef struct sgmres_plan sgmres_plan_t;
+int sgmres_plan_create(const sgmres_csr_t *A, int flags, sgmres_plan_t **plan, void *stream);
+int sgmres_plan_destroy(sgmres_plan_t *plan);
+int sgmres_solve_plan(const sgmres_plan_t *plan, const double *b, double *x, int d, int k, int s,
+                      uint64_t seed, double tol, int restarts, const sgmres_options_t *opts,
+                      sgmres_info_t *info, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Hot-path steps, callable one by one (they compose into sgmres_solve).
  * ------------------------------------------------------------------------- */

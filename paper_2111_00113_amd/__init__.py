@@ -8,6 +8,7 @@ Python binding; the library is loaded lazily on first use.
 
 from .sgmres import (  # noqa: F401
     DeviceCSR,
+    Plan,
     SGMRESError,
     OK,
     NOT_CONVERGED,

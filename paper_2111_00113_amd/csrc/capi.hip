@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <new>
 #include <tuple>
 #include <unordered_map>
 #include <vector>
@@ -145,6 +146,31 @@ struct Workspace {
     size_t mr_int_cap = 0;
     void** mr_ptr = nullptr;  // 32 sources, 32 destinations
     size_t mr_ptr_cap = 0;
+    // the sliced ELL copy the basis kernels read this call: the workspace's own
+    // (build_sell) or a plan's
+    const int64_t* cur_sp = nullptr;
+    const int32_t* cur_col = nullptr;
+    const void* cur_val = nullptr;
+};
+
+// Sliced ELL copy of one matrix with values in one arithmetic type (plan-owned).
+struct SellCopy {
+    int64_t* sp = nullptr;
+    int32_t* col = nullptr;
+    void* val = nullptr;
+};
+
+// A matrix's cached set-up (sgmres_plan_create): validated once, its sliced ELL
+// copies and optionally CSR(A^T) with its copies.
+struct Plan {
+    int device = 0;
+    int flags = 0;
+    sgmres_csr_t A{};
+    sgmres_csr_t At{};
+    int32_t* t_rp = nullptr;
+    int32_t* t_ci = nullptr;
+    double* t_val = nullptr;
+    SellCopy sell[2][2];  // [A, A^T][FP64 values, FP32 values]
 };
 
 std::mutex g_mutex;
@@ -228,8 +254,21 @@ struct SolveArgs {
     int halo_off;   // nonzero: three grid barriers per Arnoldi step always
     int path;       // 0 auto, SGMRES_PATH_STREAM / SGMRES_PATH_PART_SPLIT forced
     int stream_state;  // 0 auto, 1 registers, 2 HBM buffer
+    const Plan* plan;  // null, or the plan whose copies of A (or A^T) the solve reads
+    int plan_t;        // with a plan: 1 for A^T
     hipStream_t stream;
 };
+
+// A was validated and its sliced ELL copy built by a plan: point the workspace
+// at the copy for this precision (SGMRES_EINVAL when the plan lacks it).
+int use_plan_sell(Workspace& ws, const SolveArgs& a) {
+    const SellCopy& c = a.plan->sell[a.plan_t][a.precision == SGMRES_PREC_FP64 ? 0 : 1];
+    if (!c.sp) return SGMRES_EINVAL;
+    ws.cur_sp = c.sp;
+    ws.cur_col = c.col;
+    ws.cur_val = c.val;
+    return SGMRES_OK;
+}
 
 // Coefficients of the rescaled Chebyshev recurrence for the box [c +- dx, +-dy]
 // (Section 4.4): with rho = max(dx, dy), gamma = (dx^2 - dy^2) / (4 rho^2) and
@@ -302,8 +341,33 @@ int build_sell(Workspace& ws, const sgmres_csr_t& A, int precision, hipStream_t 
     SG_TRY(hipMemcpyAsync(ws.sell_sp, sp.data(), sizeof(int64_t) * (nsl + 1), hipMemcpyHostToDevice, st));
     SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, ws.sell_sp, ws.sell_col, ws.sell_val, precision, st));
     SG_TRY(hipStreamSynchronize(st));  // sp (host vector) is read by the copy above
+    ws.cur_sp = ws.sell_sp;
+    ws.cur_col = ws.sell_col;
+    ws.cur_val = ws.sell_val;
     return SGMRES_OK;
 }
+
+// The same copy into plan-owned arrays (K: nsl ints of scratch).
+int build_sell_copy(SellCopy& c, int* K_dev, const sgmres_csr_t& A, int precision, hipStream_t st) {
+    const int64_t n = A.n;
+    const int64_t nsl = (n + 63) / 64;
+    SG_TRY(launch_sell_width(n, A.row_ptr, K_dev, st));
+    std::vector<int> K(static_cast<size_t>(nsl));
+    SG_TRY(hipMemcpyAsync(K.data(), K_dev, sizeof(int) * nsl, hipMemcpyDeviceToHost, st));
+    SG_TRY(hipStreamSynchronize(st));
+    std::vector<int64_t> sp(static_cast<size_t>(nsl + 1), 0);
+    for (int64_t i = 0; i < nsl; ++i) sp[i + 1] = sp[i] + 64 * static_cast<int64_t>(K[i]);
+    const int64_t total = sp[nsl] > 0 ? sp[nsl] : 1;
+    const size_t es = precision == SGMRES_PREC_FP64 ? 8 : 4;
+    SG_TRY(hipMalloc(reinterpret_cast<void**>(&c.sp), sizeof(int64_t) * (nsl + 1)));
+    SG_TRY(hipMalloc(reinterpret_cast<void**>(&c.col), sizeof(int32_t) * total));
+    SG_TRY(hipMalloc(&c.val, es * total));
+    SG_TRY(hipMemcpyAsync(c.sp, sp.data(), sizeof(int64_t) * (nsl + 1), hipMemcpyHostToDevice, st));
+    SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, c.sp, c.col, c.val, precision, st));
+    SG_TRY(hipStreamSynchronize(st));
+    return SGMRES_OK;
+}
+
 
 // One basis cycle on the residual in ws.r (norm already in ws.sc->beta).
 // B is stored in the launch's basis type; A is read through the sliced ELL
@@ -320,9 +384,9 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
     ArnoldiParams p{};
     p.n = A.n;
     p.rp = A.row_ptr;
-    p.sp = ws.sell_sp;
-    p.ci = ws.sell_col;
-    p.val = ws.sell_val;
+    p.sp = ws.cur_sp;
+    p.ci = ws.cur_col;
+    p.val = ws.cur_val;
     p.r = ws.r;
     p.beta = &ws.sc->beta;
     p.B = B;
@@ -362,9 +426,9 @@ int run_cheb_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int s, int zeta,
     ChebParams p{};
     p.n = A.n;
     p.rp = A.row_ptr;
-    p.sp = ws.sell_sp;
-    p.ci = ws.sell_col;
-    p.val = ws.sell_val;
+    p.sp = ws.cur_sp;
+    p.ci = ws.cur_col;
+    p.val = ws.cur_val;
     p.r = ws.r;
     p.beta = &ws.sc->beta;
     p.B = B;
@@ -491,7 +555,7 @@ int solve_stream(const SolveArgs& a, Workspace& ws, sgmres_info_t* info) {
     } else if (a.stream_state == 1 && L.hst) {
         return SGMRES_EINVAL;
     }
-    int rc = check_csr(ws, a.A, st);
+    int rc = a.plan ? SGMRES_OK : check_csr(ws, a.A, st);
     if (rc) return rc;
     const size_t eb = basis_elem_bytes(a.precision);
     // columns padded to 128 entries (256-byte aligned), d + 1 of them
@@ -510,7 +574,7 @@ int solve_stream(const SolveArgs& a, Workspace& ws, sgmres_info_t* info) {
     SG_TRY(ensure(ws.st_part, ws.st_part_cap,
                   static_cast<size_t>(basis_sketch_grid(n)) * (a.d + 1) * static_cast<size_t>(a.s)));
     if (L.hst) SG_TRY(ensure(ws.st_state, ws.st_state_cap, static_cast<size_t>(n)));
-    rc = build_sell(ws, a.A, a.precision, st);
+    rc = a.plan ? use_plan_sell(ws, a) : build_sell(ws, a.A, a.precision, st);
     if (rc) return rc;
 
     SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
@@ -579,9 +643,9 @@ int solve_stream(const SolveArgs& a, Workspace& ws, sgmres_info_t* info) {
         if (ev.on) SG_TRY(hipEventRecord(ev.b0, st));
         StreamParams p{};
         p.n = n;
-        p.sp = ws.sell_sp;
-        p.ci = ws.sell_col;
-        p.val = ws.sell_val;
+        p.sp = ws.cur_sp;
+        p.ci = ws.cur_col;
+        p.val = ws.cur_val;
         p.r = ws.r;
         p.beta = &ws.sc->beta;
         p.B = ws.B;
@@ -659,7 +723,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         }
     }
     if (rc) return rc;
-    rc = check_csr(ws, a.A, st);
+    rc = a.plan ? SGMRES_OK : check_csr(ws, a.A, st);
     if (rc) return rc;
     bool halo = false;
     // Two grid barriers per Arnoldi step when at most a quarter of the
@@ -696,7 +760,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     if (cheb) SG_TRY(ensure(ws.colnorm, ws.colnorm_cap, static_cast<size_t>(a.d)));
     // the basis cycles read A through its sliced ELL copy, values in the
     // cycles' arithmetic type (FP32 in the mixed-precision modes)
-    rc = build_sell(ws, a.A, a.precision, st);
+    rc = a.plan ? use_plan_sell(ws, a) : build_sell(ws, a.A, a.precision, st);
     if (rc) return rc;
 
     // |b|, and clear the per-solve counters
@@ -791,7 +855,15 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
 }
 
 int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s, uint64_t seed,
-                double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream) {
+                double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream,
+                const Plan* plan = nullptr) {
+    if (plan) {
+        const bool t = opts && opts->transposed;
+        if (t && !plan->t_rp) return SGMRES_EINVAL;
+        A = t ? &plan->At : &plan->A;
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return SGMRES_EINVAL;
+    }
     if (!csr_ok(A) || !b || !x) return SGMRES_EINVAL;
     const int zeta = (opts && opts->zeta) ? opts->zeta : 8;
     const double kappa_max = (opts && opts->kappa_max > 0) ? opts->kappa_max : 1e14;
@@ -833,6 +905,11 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
         a.cheb_dy = opts->cheb_dy;
     }
     a.stream = static_cast<hipStream_t>(stream);
+    if (plan) {
+        a.plan = plan;
+        a.plan_t = (opts && opts->transposed) ? 1 : 0;
+        return solve_impl(a, info);
+    }
     if (opts && opts->transposed) {
         Workspace* wsp = nullptr;
         {
@@ -1288,9 +1365,9 @@ int block_solve_locked(const sgmres_csr_t& A, int nb, const sgmres_system_t* sys
         SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(dc_d), 2 * NR, 0u, st));
         StreamParams p{};
         p.n = n;
-        p.sp = ws.sell_sp;
-        p.ci = ws.sell_col;
-        p.val = ws.sell_val;
+        p.sp = ws.cur_sp;
+        p.ci = ws.cur_col;
+        p.val = ws.cur_val;
         p.r = ws.mr_R;
         p.beta = betak_d;
         p.B = ws.B;
@@ -1364,6 +1441,106 @@ int sgmres_solve_transposed(const sgmres_csr_t* A, const double* b, double* x, i
 int sgmres_solve_ex(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s, uint64_t seed,
                     double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream) {
     return solve_entry(A, b, x, d, k, s, seed, tol, restarts, opts, info, stream);
+}
+
+struct sgmres_plan {
+    sg::Plan p;
+};
+
+int sgmres_plan_create(const sgmres_csr_t* A, int flags, sgmres_plan_t** out, void* stream) {
+    if (!out) return SGMRES_EINVAL;
+    *out = nullptr;
+    if (!csr_ok(A) || (flags & ~(SGMRES_PLAN_TRANSPOSE | SGMRES_PLAN_FP32))) return SGMRES_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* ws = nullptr;
+    int rc = workspace(&ws);
+    if (rc) return rc;
+    rc = check_csr(*ws, *A, st);
+    if (rc) return rc;
+    sgmres_plan* h = new (std::nothrow) sgmres_plan();
+    if (!h) return SGMRES_ENOMEM;
+    Plan& P = h->p;
+    P.flags = flags;
+    P.A = *A;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete h;
+        return SGMRES_EHIP;
+    }
+    P.device = dev;
+    const int64_t n = A->n;
+    int* K = nullptr;
+    int32_t* tscr = nullptr;
+    auto cleanup = [&](int code) -> int {
+        if (K) (void)hipFree(K);
+        if (tscr) (void)hipFree(tscr);
+        if (code != SGMRES_OK) {
+            for (auto& row : P.sell)
+                for (SellCopy& c : row) {
+                    if (c.sp) (void)hipFree(c.sp);
+                    if (c.col) (void)hipFree(c.col);
+                    if (c.val) (void)hipFree(c.val);
+                }
+            if (P.t_rp) (void)hipFree(P.t_rp);
+            if (P.t_ci) (void)hipFree(P.t_ci);
+            if (P.t_val) (void)hipFree(P.t_val);
+            delete h;
+        }
+        return code;
+    };
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&K), sizeof(int) * ((n + 63) / 64));
+    if (e != hipSuccess) return cleanup(to_code(e));
+    rc = build_sell_copy(P.sell[0][0], K, P.A, SGMRES_PREC_FP64, st);
+    if (!rc && (flags & SGMRES_PLAN_FP32)) rc = build_sell_copy(P.sell[0][1], K, P.A, SGMRES_PREC_FP32, st);
+    if (rc) return cleanup(rc);
+    if (flags & SGMRES_PLAN_TRANSPOSE) {
+        const size_t nnz = static_cast<size_t>(A->nnz);
+        e = hipMalloc(reinterpret_cast<void**>(&P.t_rp), sizeof(int32_t) * (n + 1));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&P.t_ci), sizeof(int32_t) * (nnz ? nnz : 1));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&P.t_val), sizeof(double) * (nnz ? nnz : 1));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tscr), sizeof(int32_t) * transpose_scratch_ints(n));
+        if (e == hipSuccess)
+            e = launch_csr_transpose(n, A->nnz, A->row_ptr, A->col_idx, A->val, P.t_rp, P.t_ci, P.t_val, tscr, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return cleanup(to_code(e));
+        P.At = sgmres_csr_t{n, A->nnz, P.t_rp, P.t_ci, P.t_val};
+        rc = build_sell_copy(P.sell[1][0], K, P.At, SGMRES_PREC_FP64, st);
+        if (!rc && (flags & SGMRES_PLAN_FP32)) rc = build_sell_copy(P.sell[1][1], K, P.At, SGMRES_PREC_FP32, st);
+        if (rc) return cleanup(rc);
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return cleanup(to_code(e));
+    cleanup(SGMRES_OK);
+    *out = h;
+    return SGMRES_OK;
+}
+
+int sgmres_plan_destroy(sgmres_plan_t* plan) {
+    if (!plan) return SGMRES_OK;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Plan& P = plan->p;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(P.device);
+    for (auto& row : P.sell)
+        for (SellCopy& c : row) {
+            if (c.sp) (void)hipFree(c.sp);
+            if (c.col) (void)hipFree(c.col);
+            if (c.val) (void)hipFree(c.val);
+        }
+    if (P.t_rp) (void)hipFree(P.t_rp);
+    if (P.t_ci) (void)hipFree(P.t_ci);
+    if (P.t_val) (void)hipFree(P.t_val);
+    (void)hipSetDevice(cur);
+    delete plan;
+    return SGMRES_OK;
+}
+
+int sgmres_solve_plan(const sgmres_plan_t* plan, const double* b, double* x, int d, int k, int s, uint64_t seed,
+                      double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream) {
+    if (!plan) return SGMRES_EINVAL;
+    return solve_entry(nullptr, b, x, d, k, s, seed, tol, restarts, opts, info, stream, &plan->p);
 }
 
 int sgmres_sketch_pattern(uint64_t seed, uint32_t cycle, int64_t i0, int64_t count, int s, int zeta,

@@ -147,11 +147,15 @@ def lib():
     L.sgmres_basis_combine.argtypes = [i64, i32, vp, i64, vp, vp, vp]
     L.sgmres_csr_transpose.argtypes = [P(_CSR), vp, vp, vp, vp]
     L.sgmres_csr_outer_grad.argtypes = [P(_CSR), vp, vp, dbl, vp, vp]
+    L.sgmres_plan_create.argtypes = [P(_CSR), i32, ctypes.POINTER(vp), vp]
+    L.sgmres_plan_destroy.argtypes = [vp]
+    L.sgmres_solve_plan.argtypes = [vp, vp, vp, i32, i32, i32, u64, dbl, i32, P(_Options), P(_Info), vp]
     L.sgmres_release_workspace.argtypes = []
     L.sgmres_release_workspace.restype = None
     L.sgmres_version.argtypes = []
     L.sgmres_version.restype = ctypes.c_char_p
     for name in ("sgmres_solve", "sgmres_solve_transposed", "sgmres_solve_ex", "sgmres_sketch_pattern",
+                 "sgmres_plan_create", "sgmres_plan_destroy", "sgmres_solve_plan",
                  "sgmres_sketch_apply", "sgmres_sketch_apply_noalloc", "sgmres_residual", "sgmres_arnoldi_cycle", "sgmres_sketched_lsq",
                  "sgmres_basis_combine", "sgmres_csr_transpose", "sgmres_csr_outer_grad"):
         getattr(L, name).restype = ctypes.c_int
@@ -231,7 +235,7 @@ def _raise(fn, rc):
 def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
                  transposed=False, block_size=0, rows_per_thread=0, profile=False, barrier_mode=0,
                  spmv_mode=0, cheb_box=None, precision="fp64", halo_off=False, path=0, stream_state=0,
-                 stream=None):
+                 plan=None, stream=None):
     """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
 
     cheb_box=(c, dx, dy) selects the Chebyshev basis for a spectrum inside
@@ -243,19 +247,63 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     nonzeros reach outside their block; results are bit-identical).  path:
     0 (automatic), PATH_STREAM or PATH_PART_SPLIT to force the kernel used for
     systems beyond the resident capacity; stream_state: 0 auto, 1 registers,
-    2 HBM buffer (streaming path).  Returns (rc, info) with rc SGMRES_OK (0) or
-    SGMRES_NOT_CONVERGED (1); raises SGMRESError on the negative error codes."""
-    _check_dev(b, torch.float64, A.n)
-    _check_dev(x, torch.float64, A.n)
+    2 HBM buffer (streaming path).  plan: a Plan of A (its copies of A and A^T
+    are reused instead of being rebuilt; A may then be None).  Returns (rc,
+    info) with rc SGMRES_OK (0) or SGMRES_NOT_CONVERGED (1); raises SGMRESError
+    on the negative error codes."""
+    n = plan.A.n if plan is not None else A.n
+    _check_dev(b, torch.float64, n)
+    _check_dev(x, torch.float64, n)
     info = _Info()
     basis, (cc, cdx, cdy) = (0, (0.0, 0.0, 0.0)) if cheb_box is None else (1, tuple(float(t) for t in cheb_box))
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
                     barrier_mode, spmv_mode, basis, cc, cdx, cdy, prec, 0, 1 if halo_off else 0, path,
                     stream_state)
+    if plan is not None:
+        rc = lib().sgmres_solve_plan(plan.handle, b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
+                                     ctypes.byref(opts), ctypes.byref(info), _stream(stream))
+        return _raise("sgmres_solve_plan", rc), _info(info)
     rc = lib().sgmres_solve_ex(ctypes.byref(A._c()), b.data_ptr(), x.data_ptr(), d, k, s, seed, tol, restarts,
                                ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     return _raise("sgmres_solve", rc), _info(info)
+
+
+class Plan:
+    """A matrix's set-up on the GPU (sgmres_plan_create): validated CSR, the
+    sliced ELL copy of A (and of A^T with transpose=True; FP32 value copies
+    with fp32=True), reused by every sgmres_solve(..., plan=...).  Keeps a
+    reference to A's tensors; call close() (or use as a context manager) to
+    free the device copies."""
+
+    PLAN_TRANSPOSE = 1
+    PLAN_FP32 = 2
+
+    def __init__(self, A: "DeviceCSR", transpose: bool = False, fp32: bool = False, stream=None):
+        self.A = A
+        self.handle = None
+        h = ctypes.c_void_p()
+        flags = (self.PLAN_TRANSPOSE if transpose else 0) | (self.PLAN_FP32 if fp32 else 0)
+        rc = lib().sgmres_plan_create(ctypes.byref(A._c()), flags, ctypes.byref(h), _stream(stream))
+        _raise("sgmres_plan_create", rc)
+        self.handle = h
+
+    def close(self):
+        if self.handle is not None:
+            lib().sgmres_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, zeta=8, kappa_max=1e14,
