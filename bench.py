@@ -219,7 +219,7 @@ def batch_bench(args, sg, synth, torch, np) -> int:
     torch.cuda.set_device(0)
     d, k, s, tol, restarts = 100, 2, 200, 1e-10, 50
     log(f"generating {args.batch_count} systems")
-    W = synth.batch_workload(args.batch_count)
+    W = synth.batch_workload(args.batch_count if args.mode == "batch" else 0)
     systems = [(sg.DeviceCSR.from_host(A, dev), torch.as_tensor(b, device=dev),
                 torch.zeros(A.n, dtype=torch.float64, device=dev)) for A, b in W]
     rows = sum(A.n for A, _ in W)
@@ -256,12 +256,13 @@ def batch_bench(args, sg, synth, torch, np) -> int:
         torch.cuda.synchronize()
         return time.perf_counter() - t0, cyc
 
+    groups = (("many", systems), ("block", block)) if args.mode == "batch" else (("block", block),)
     for prec in ("fp32", "fp64"):  # warm-up (also times the workgroup shapes once)
-        batched(systems, prec)
-        batched(block, prec)
-    one_at_a_time(systems[:4])
+        for _, sysl in groups:
+            batched(sysl, prec)
+    one_at_a_time(groups[0][1][:4])
     out = {}
-    for name, sysl in (("many", systems), ("block", block)):
+    for name, sysl in groups:
         t32 = t64 = None
         for _ in range(args.steps):
             e32, r32 = batched(sysl, "fp32")
@@ -277,6 +278,18 @@ def batch_bench(args, sg, synth, torch, np) -> int:
             cycles_fp32=sum(r["cycles"] for r in r32), cycles_fp64=sum(r["cycles"] for r in r64),
             cycles_one_at_a_time=cseq, max_relres_fp32=max(r["relres"] for r in r32))
         log(f"{name}: {out[name]}")
+    if args.mode == "block":
+        b = out["block"]
+        print(json.dumps({
+            "metric": (f"block of {len(block)} right-hand sides sharing A, systems/s at rel. residual 1e-10 "
+                       f"(n = 2^20 random sparse, d={d}, k={k}, s={s})"),
+            "value": b["fp64_batched_systems_per_s"], "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": b["fp64_batched_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": (f"random_dominant(2^20, 6 off-diagonals, seed 2) with {len(block)} right-hand "
+                                    f"sides default_rng(2); d={d}, k={k}, s={s}, zeta=8, tol=1e-10")},
+            "rhs_block": b}), flush=True)
+        return 0
     m = out["many"]
     # the line reports the FP64 batched solve (faster than FP32 cycles here: those
     # need a refinement cycle); whole-solve algorithmic bytes of its basis steps
@@ -327,9 +340,10 @@ def main() -> int:
     ap.add_argument("--cheb-box", default="4,4,0", help="c,dx,dy of the spectral box for --basis chebyshev")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="basis cycles in FP64, FP32, or FP32 with a bfloat16 basis (FP64 refinement)")
-    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "batch"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "batch", "block"],
                     help="solve: the sGMRES metric; grad: differentiable solve (forward + adjoint); "
-                         "batch: many systems per launch against one-at-a-time FP64 solves")
+                         "batch: many systems per launch against one-at-a-time FP64 solves; "
+                         "block: only the block of right-hand sides of the batch workload")
     ap.add_argument("--batch-count", type=int, default=256, help="systems in the many-systems workload")
     ap.add_argument("--block-rhs", type=int, default=32, help="right-hand sides of the n = 2^20 block")
     ap.add_argument("--halo-off", action="store_true", help="truncated Arnoldi: three grid barriers per step")
@@ -365,7 +379,7 @@ def main() -> int:
     import paper_2111_00113_amd as sg
     import synth
 
-    if args.mode == "batch":
+    if args.mode in ("batch", "block"):
         return batch_bench(args, sg, synth, torch, np)
 
     log(f"building workload {args.workload}")
