@@ -144,10 +144,13 @@ struct StreamParams {
     int* flags_rhs;      // NR > 1: flags per right-hand side (OR)
     uint64_t spin_limit;
     unsigned long long* phase_ticks;
+    int nl;              // register state: newest basis columns kept in the LDS ring (0..4)
 };
 struct StreamLaunch {
     const void* fn;
     int NR, P, hst, grid;
+    int nl;              // LDS ring columns (register state)
+    size_t lds;          // dynamic LDS bytes
 };
 // precision SGMRES_PREC_*; nr right-hand sides (1 or a divisor of 64)
 hipError_t stream_configure(int64_t n, int nr, int k, int precision, StreamLaunch* out);

@@ -67,8 +67,18 @@ __device__ __forceinline__ void block_sum_rhs(const double (&vals)[kNV], int nv,
     __syncthreads();
 }
 
+// LDS ring slots of an instance: as many tile columns (P * 1024 entries of TC)
+// as fit in 150 KiB, at most the window length; none with HBM state
+template <typename TC, int P, bool HST>
+__host__ __device__ constexpr int ring_slots() {
+    return HST ? 0 : ((150 * 1024) / (P * kBlock * static_cast<int>(sizeof(TC))) < kStreamMaxK
+                          ? (150 * 1024) / (P * kBlock * static_cast<int>(sizeof(TC)))
+                          : kStreamMaxK);
+}
+
 template <typename TC, typename TS, int NR, int P, bool HST>
 __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
+    constexpr int NL = ring_slots<TC, P, HST>();
     static_assert(kWave % NR == 0, "a wavefront holds whole rows of right-hand sides");
     static_assert(P % 8 == 0 || P <= 8, "pairs are walked in groups");
     constexpr int T = P * kBlock;  // pairs per tile
@@ -106,6 +116,13 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
     // device-coherently
     const bool fresh = ((reinterpret_cast<uintptr_t>(p.B) | static_cast<uintptr_t>(ldb * sizeof(TS))) & 255u) == 0;
     auto ldB = [&](const TS* q) -> TC { return from_basis<TC>(fresh ? *q : load_coherent(q)); };
+    // Register state: the newest nl basis columns of the block's tile also sit
+    // in an LDS ring (slot c % nl holds column c, as the rounded stored values),
+    // so window entries a < nl and the SpMV's gathers of the tile's own rows
+    // (NR = 1) are LDS reads instead of HBM reads
+    extern __shared__ __align__(16) unsigned char ring_raw[];
+    TC* ring = reinterpret_cast<TC*>(ring_raw);
+    const int64_t tbase = t0 * T;  // first pair of the block's (only) tile in register mode
 
     GridSync bar{static_cast<SyncWords*>(p.sync), p.abort, p.spin_limit, static_cast<unsigned>(G), 0u, 0u, 0u, 0u, 0u,
                  p.per_block_release != 0};
@@ -134,7 +151,11 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>(pp * kBlock + tid);
-                if (q < npairs) Bs[q] = to_basis<TS>(dz ? TC(0) : static_cast<TC>(p.r[q] / beta));
+                if (q < npairs) {
+                    const TS b1 = to_basis<TS>(dz ? TC(0) : static_cast<TC>(p.r[q] / beta));
+                    Bs[q] = b1;
+                    if constexpr (NL > 0) ring[pp * kBlock + tid] = from_basis<TC>(b1);
+                }
             }
         }
     }
@@ -147,6 +168,15 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
         const int kw = min(j + 1, k);
         const TS* bj = Bs + static_cast<int64_t>(j) * ldb;
         const unsigned tag = static_cast<unsigned>(j + 1);
+        // window entry a (0 = newest; a < min(j + 1, k)) of the thread's pair
+        // at local index loc: ring slot (j - a) % NL when a < NL, else B
+        int soff[NL > 0 ? NL : 1];
+#pragma unroll
+        for (int a = 0; a < (NL > 0 ? NL : 1); ++a) soff[a] = (((j - a) % NL + NL) % NL) * T;
+        auto ldW = [&](int a, uint32_t q, int loc) -> TC {
+            if (a < NL) return ring[soff[a] + loc];
+            return from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+        };
         tick(0);
 
         // ---- phase 1: m = A b_j, partials <m,m> and W^T m ------------------
@@ -195,7 +225,17 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                     }
 #pragma unroll
                     for (int u = 0; u < PG; ++u)
-                        if (e < sK[u]) m[u] += v[u] * ldB(bj + (static_cast<uint32_t>(c[u]) * NR + rhs));
+                        if (e < sK[u]) {
+                            TC bv;
+                            if constexpr (NR == 1 && NL > 0) {
+                                const uint32_t lc = static_cast<uint32_t>(c[u] - tbase);
+                                bv = lc < static_cast<uint32_t>(T) ? ring[soff[0] + lc]
+                                                                   : ldB(bj + static_cast<uint32_t>(c[u]));
+                            } else {
+                                bv = ldB(bj + (static_cast<uint32_t>(c[u]) * NR + rhs));
+                            }
+                            m[u] += v[u] * bv;
+                        }
                 }
 #pragma unroll
                 for (int u = 0; u < PG; ++u) {
@@ -203,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                     if (q < npairs) {
                         acc[0] += static_cast<double>(m[u] * m[u]);
                         for (int a = 0; a < kw; ++a) {
-                            const TC wa = from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+                            const TC wa = ldW(a, q, (g0 + u) * kBlock + tid);
                             acc[1 + a] += static_cast<double>(wa * m[u]);
                         }
                     }
@@ -237,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                     TC wa[kStreamMaxK];
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
-                        if (a < kw) wa[a] = from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+                        if (a < kw) wa[a] = ldW(a, q, pp * kBlock + tid);
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
                         if (a < kw) w -= static_cast<TC>(coefA[(1 + a) * NR + rhs]) * wa[a];
@@ -305,11 +345,15 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                         TC wa[kStreamMaxK];
 #pragma unroll
                         for (int a = 0; a < kStreamMaxK; ++a)
-                            if (a < kw) wa[a] = from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+                            if (a < kw) wa[a] = ldW(a, q, pp * kBlock + tid);
 #pragma unroll
                         for (int a = 0; a < kStreamMaxK; ++a)
                             if (a < kw) w = gs_sub(w, static_cast<TC>(coefB[(1 + a) * NR + rhs]), wa[a]);
-                        bn[q] = to_basis<TS>(dz ? TC(0) : w / nu_t);
+                        const TS st = to_basis<TS>(dz ? TC(0) : w / nu_t);
+                        bn[q] = st;
+                        // (the slot of column j + 1 - nl: window entry nl at the next
+                        // step, which then reads it from B)
+                        if constexpr (NL > 0) ring[((j + 1) % NL) * T + pp * kBlock + tid] = from_basis<TC>(st);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
