@@ -57,11 +57,18 @@ __device__ __forceinline__ float gs_sub(float x, float h, float v) { return __bu
 // block partials, H and the sketch sums are FP64 in every variant.
 // HALO: two grid barriers per step instead of three.  The new column b_{j+1}
 // is not published by a third barrier: each block keeps its own rows of it in
-// LDS and recomputes the entries its SpMV needs from other blocks' rows as
-// (w - W h2) / nu from w (written to HBM before the second barrier) and the
-// window columns, with the owner's operations in the owner's order, so the
-// values are the owner's bits.  Chosen when few nonzeros reach outside their
-// block (requires SKB = false).
+// LDS, and the entries its SpMV needs from other blocks' rows come
+//   - FP32 arithmetic: from their owners, which store each such entry with
+//     its column number as tag in one 64-bit word of the halo buffer (rows
+//     marked in the xbits bitmap); the reader reloads until the tag matches.
+//     The owner cannot overwrite the word before every reader has passed the
+//     next second barrier.
+//   - FP64 arithmetic: recomputed by the reader as (w - W h2) / nu from w
+//     (the halo buffer, written before the second barrier) and the window
+//     columns, with the owner's operations in the owner's order, so the
+//     values are the owner's bits.  (Publishing a double takes two tagged
+//     words; measured slower: 9.84 -> 9.21 solves/s at n = 2^20.)
+// Chosen when few nonzeros reach outside their block (requires SKB = false).
 template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO = false>
 __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     extern __shared__ double smem[];
@@ -95,7 +102,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     constexpr double uround = BasisPrec<TC>::unit_roundoff;
     static_assert(!HALO || !SKB, "the halo mode keeps b_{j+1} where S b_j would be staged");
     TC* bst = reinterpret_cast<TC*>(vals);  // HALO: own rows of the current column
-    TC* wbuf = static_cast<TC*>(p.wbuf);
+    constexpr bool kPub = sizeof(TC) == 4;  // HALO: publish (else recompute) halo entries
+    TC* wbuf = static_cast<TC*>(p.hbuf);
+    unsigned long long* pub = static_cast<unsigned long long*>(p.hbuf);
     const int64_t row_lo = static_cast<int64_t>(blk) * RB;
     const int64_t row_hi = min(n, row_lo + RB);
     // A basis column is written once per cycle, before anything reads it, and
@@ -132,6 +141,16 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 spos[r] = a;
                 sK[r] = static_cast<int>((p.sp[sl + 1] - a) / kWave);
             }
+        }
+    }
+
+    // HALO, publishing: bit r set when own row r is gathered by another block
+    unsigned xmask = 0;
+    if constexpr (HALO && kPub) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+            if (row < n && ((p.xbits[row >> 5] >> (row & 31)) & 1u)) xmask |= 1u << r;
         }
     }
 
@@ -273,8 +292,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 #pragma unroll
         for (int r = 0; r < R; ++r) kmax = max(kmax, sK[r]);
         if constexpr (HALO) {
-            // own rows from LDS; other blocks' rows of b_j recomputed from w and
-            // the window of step j-1 (b_1 is in HBM, published at init)
+            // own rows from LDS; other blocks' rows of b_j from their owners'
+            // tagged words, or recomputed from w and the window of step j-1
+            // (b_1 is in HBM, published at init)
+            const unsigned tag_b = static_cast<unsigned>(j);
             const int kwp = min(j, p.k);
             const TC nup = static_cast<TC>(coef[2 * p.k + 2]);
             const double* h2p = coef + p.k + 2;
@@ -331,6 +352,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                             bv = bst[cc - row_lo];
                         } else if (j == 0) {
                             bv = from_basis<TC>(load_coherent(bj + cc));
+                        } else if constexpr (kPub) {
+                            bv = tagged_get(pub + cc, tag_b, p.abort, p.spin_limit);
                         } else {
                             // w is rewritten every step: read device-coherently; the
                             // window columns as described at ldB.  The first four
@@ -434,7 +457,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
                 for (int r = 0; r < R; ++r) w[r] -= h * Wg(j, a, r);
             }
         }
-        if constexpr (HALO) {
+        if constexpr (HALO && !kPub) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
@@ -500,13 +523,19 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         for (int r = 0; r < R; ++r) {
             const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
             const TS st = to_basis<TS>(bnew[r] / nu_t);
-            if (row < n) {
-                // the halo mode gathers own rows from LDS: nothing rereads the
-                // column from L2 in the next step
-                if constexpr (HALO) store_stream(bn + row, st);
-                else bn[row] = st;
-            }
             bnew[r] = from_basis<TC>(st);
+            if (row < n) {
+                // the halo mode gathers own rows from LDS and other blocks'
+                // through the halo buffer: nothing rereads the column from L2
+                // in the next step
+                if constexpr (HALO) {
+                    store_stream(bn + row, st);
+                    if constexpr (kPub)
+                        if ((xmask >> r) & 1u) tagged_put(pub + row, bnew[r], static_cast<unsigned>(j + 1));
+                } else {
+                    bn[row] = st;
+                }
+            }
         }
         if constexpr (KW > 0) {
 #pragma unroll
@@ -523,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
             // recomputation of other blocks' rows in the next step
 #pragma unroll
             for (int r = 0; r < R; ++r) bst[r * BLOCK + tid] = bnew[r];
-            if (tid == 0) coef[2 * p.k + 2] = nu;
+            if (!kPub && tid == 0) coef[2 * p.k + 2] = nu;
             __syncthreads();
         } else {
             bar.arrive(kArriver);

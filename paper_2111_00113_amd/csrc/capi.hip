@@ -83,8 +83,12 @@ struct Workspace {
     size_t colnorm_cap = 0;
     float* valf = nullptr;  // FP32 copy of A's values (mixed-precision cycles)
     size_t valf_cap = 0;
-    double* wbuf = nullptr;  // two-barrier Arnoldi: w of the current step (n)
-    size_t wbuf_cap = 0;
+    // two-barrier Arnoldi: halo buffer (n 64-bit words: tagged entries of the
+    // rows other blocks gather, or w), and the bitmap of those rows
+    unsigned long long* hbuf = nullptr;
+    size_t hbuf_cap = 0;
+    unsigned* xbits = nullptr;
+    size_t xbits_cap = 0;
     // sliced ELL copy of A for the resident basis kernels
     int* sell_K = nullptr;
     size_t sell_K_cap = 0;
@@ -375,8 +379,12 @@ int build_sell_copy(SellCopy& c, int* K_dev, const sgmres_csr_t& A, int precisio
 int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zeta, uint64_t seed,
               uint32_t cycle, const ArnoldiLaunch& L, void* B, int64_t ldb, double* SB, double* SAB,
               double* H, double* g, hipStream_t stream, hipEvent_t ev_start = nullptr,
-              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0) {
+              int per_block_release = 0, bool phase_timing = false, int spmv_mode = 0, int halo = 0) {
     SG_TRY(launch_fill_u32(ws.sync, static_cast<int64_t>(sync_words_bytes() / sizeof(unsigned)), 0u, stream));
+    // halo mode (1: recomputed entries, 2: published entries, FP32
+    // arithmetic, whose tags start at 1)
+    if (halo == 2)
+        SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.hbuf), 2 * A.n, 0u, stream));
     // tags of the step partials start at 1: clear the slots of earlier launches
     SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.part_ab), static_cast<int64_t>(8 * (k + 1)) * L.grid, 0u,
                            stream));
@@ -411,7 +419,8 @@ int run_cycle(Workspace& ws, const sgmres_csr_t& A, int d, int k, int s, int zet
     p.spin_limit = kSpinLimitTicks;
     p.phase_ticks = phase_timing ? ws.sc->phase_ticks : nullptr;
     p.spmv_mode = spmv_mode;
-    p.wbuf = ws.wbuf;
+    p.hbuf = halo ? ws.hbuf : nullptr;
+    p.xbits = halo ? ws.xbits : nullptr;
     SG_TRY(arnoldi_launch(L, p, stream));
     return SGMRES_OK;
 }
@@ -727,19 +736,23 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     if (rc) return rc;
     bool halo = false;
     // Two grid barriers per Arnoldi step when at most a quarter of the
-    // nonzeros reach outside their row's block (their b_j entries are then
+    // nonzeros reach outside their row's block (those entries of b_j are then
+    // published by their owners as tagged words, rows marked in the bitmap, or
     // recomputed by the block that needs them).
     if (!cheb && !a.halo_off && a.spmv_mode == 0) {
+        const size_t xwords = static_cast<size_t>((n + 31) / 32);
+        SG_TRY(ensure(ws.xbits, ws.xbits_cap, xwords));
+        SG_TRY(launch_fill_u32(ws.xbits, static_cast<int64_t>(xwords), 0u, st));
         SG_TRY(hipMemsetAsync(&ws.sc->offblock, 0, sizeof(unsigned long long), st));
         SG_TRY(launch_offblock_count(n, a.A.row_ptr, a.A.col_idx, static_cast<int64_t>(L.R) * L.block,
-                                     &ws.sc->offblock, st));
+                                     &ws.sc->offblock, ws.xbits, st));
         rc = copy_scalars(ws, st);
         if (rc) return rc;
         if (4 * ws.host_sc->offblock <= static_cast<unsigned long long>(a.A.nnz)) {
             ArnoldiShape hs{n, a.d, kk, a.s, a.zeta, L.block, L.R, L.KW == 0, 0, 0, a.precision, 1};
             ArnoldiLaunch H{};
             if (arnoldi_configure(hs, &H) == hipSuccess && H.R == L.R && H.block == L.block && H.KW == L.KW) {
-                SG_TRY(ensure(ws.wbuf, ws.wbuf_cap, (static_cast<size_t>(n) * 8 + 7) / 8));
+                SG_TRY(ensure(ws.hbuf, ws.hbuf_cap, static_cast<size_t>(n)));
                 L = H;
                 halo = true;
             }
@@ -830,7 +843,7 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
         else
             rc = run_cycle(ws, a.A, a.d, kk, a.s, a.zeta, a.seed, static_cast<uint32_t>(cycles), L, ws.B, ldb,
                            ws.SB, ws.SAB, ws.H, ws.g, st, ev.on ? ev.b0 : nullptr, a.per_block_release, ev.on,
-                           a.spmv_mode);
+                           a.spmv_mode, halo ? (a.precision == SGMRES_PREC_FP64 ? 1 : 2) : 0);
         if (rc) return rc;
         if (ev.on) SG_TRY(hipEventRecord(ev.b1, st));
         rc = run_lsq(ws, a.s, a.d, &ws.sc->dc, 0, ws.SAB, ws.g, a.kappa_max, ws.y, st);
@@ -1739,7 +1752,7 @@ void sgmres_release_workspace(void) {
         if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
         void* ptrs[] = {w.bt_sys, w.bt_st, w.bt_task, w.bt_slots, w.bt_slot_off, w.bt_gcnt, w.bt_arena,
                         w.r, w.B, w.SB, w.SAB, w.H, w.g, w.y, w.tau, w.lsq_sync, w.part_ab, w.part_sk,
-                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.wbuf, w.sell_K, w.sell_sp, w.sell_col,
+                        w.part_vec, w.part_nrm, w.colnorm, w.valf, w.hbuf, w.xbits, w.sell_K, w.sell_sp, w.sell_col,
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
                         w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr};

@@ -342,6 +342,36 @@ __device__ __forceinline__ void grid_sum_tagged(const unsigned long long* part, 
     __syncthreads();
 }
 
+// Tagged single floats: a basis entry published by its owner without a grid
+// barrier, as one relaxed 64-bit word (tag in the high half, the float's bits
+// in the low half), read by other workgroups that wait for its tag.
+__device__ __forceinline__ void tagged_put(unsigned long long* slot, float v, unsigned tag) {
+    __hip_atomic_store(slot, (static_cast<unsigned long long>(tag) << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reload until the tag is `tag`; bounded like the other waits (abort[0] raised
+// after `limit` ticks, or already raised: the value is then meaningless).
+__device__ __forceinline__ float tagged_get(const unsigned long long* slot, unsigned tag, int* abort,
+                                            uint64_t limit) {
+    const unsigned long long want = static_cast<unsigned long long>(tag);
+    unsigned long long wd = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_expect((wd >> 32) != want, 0)) {
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        for (;;) {
+            __builtin_amdgcn_s_sleep(1);
+            wd = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((wd >> 32) == want) break;
+            if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    return __uint_as_float(static_cast<unsigned>(wd & 0xffffffffull));
+}
+
 // --------------------------------------------------------------------------
 // Split-phase grid barrier for a cooperative launch (all blocks resident).
 //

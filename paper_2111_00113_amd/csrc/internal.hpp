@@ -37,7 +37,11 @@ struct ArnoldiParams {
     uint64_t spin_limit;
     unsigned long long* phase_ticks;  // null, or 8 accumulators (block 0's time per phase)
     int spmv_mode;                    // 0 row per thread, 1 CSR-stream through LDS
-    void* wbuf;                       // halo mode: n entries (arithmetic type), w of the current step
+    // halo mode, n 64-bit words: FP32 arithmetic, the tagged basis entries of
+    // the rows other blocks gather (bit i of xbits[i / 32]; zero at launch);
+    // FP64, w of the current step
+    void* hbuf;
+    const unsigned* xbits;
 };
 
 struct ArnoldiShape {
@@ -308,7 +312,7 @@ hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rp, const int
 // out[0] += nonzeros (i, c) of A with c / RB != i / RB (columns outside the
 // row's block of RB rows)
 hipError_t launch_offblock_count(int64_t n, const int32_t* rp, const int32_t* ci, int64_t RB,
-                                 unsigned long long* out, hipStream_t stream);
+                                 unsigned long long* out, unsigned* xbits, hipStream_t stream);
 // dval[q] = alpha * u[row(q)] * v[col(q)] on the sparsity pattern of A
 hipError_t launch_csr_outer(int64_t n, const int32_t* rp, const int32_t* ci, const double* u, const double* v,
                             double alpha, double* dval, hipStream_t stream);

@@ -283,15 +283,24 @@ hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B,
     return hipGetLastError();
 }
 
+// Nonzeros whose column lies outside their row's block of RB rows (summed
+// into *out), and, when xbits is given, bit c of xbits set for every such
+// column c (the rows that other blocks gather; OR is order-independent)
 __global__ void offblock_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                int64_t RB, unsigned long long* __restrict__ out) {
+                                int64_t RB, unsigned long long* __restrict__ out, unsigned* __restrict__ xbits) {
     __shared__ double tmp[kVecBlock / kWave];
     __shared__ double sum[1];
     double cnt = 0.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int64_t b = i / RB;
-        for (int q = rp[i]; q < rp[i + 1]; ++q) cnt += (ci[q] / RB != b) ? 1.0 : 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            const int c = ci[q];
+            if (c / RB != b) {
+                cnt += 1.0;
+                if (xbits) atomicOr(xbits + (c >> 5), 1u << (c & 31));
+            }
+        }
     }
     const double v[1] = {cnt};
     block_sum<1>(v, 1, tmp, sum);
@@ -299,8 +308,8 @@ __global__ void offblock_kernel(int64_t n, const int32_t* __restrict__ rp, const
 }
 
 hipError_t launch_offblock_count(int64_t n, const int32_t* rp, const int32_t* ci, int64_t RB,
-                                 unsigned long long* out, hipStream_t stream) {
-    offblock_kernel<<<vec_grid(n), kVecBlock, 0, stream>>>(n, rp, ci, RB, out);
+                                 unsigned long long* out, unsigned* xbits, hipStream_t stream) {
+    offblock_kernel<<<vec_grid(n), kVecBlock, 0, stream>>>(n, rp, ci, RB, out, xbits);
     return hipGetLastError();
 }
 
