@@ -230,12 +230,15 @@ def batch_bench(args, sg, synth, torch, np) -> int:
     block = [(dA1, torch.as_tensor(b, device=dev), torch.zeros(A1.n, dtype=torch.float64, device=dev)) for b in B1]
     del W, B1
 
+    bpath = {"part-split": sg.PATH_PART_SPLIT, "multi": sg.PATH_MULTI}.get(args.path, 0)
+
     def batched(sysl, prec):
         for _, _, x in sysl:
             x.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, res = sg.sgmres_solve_batched(sysl, d, k, s, 0, tol, restarts, precision=prec)
+        rc, res = sg.sgmres_solve_batched(sysl, d, k, s, 0, tol, restarts, precision=prec, path=bpath,
+                                          rows_per_thread=args.rows_per_thread)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         if rc != sg.OK or max(r["relres"] for r in res) > tol:
@@ -308,7 +311,8 @@ def batch_bench(args, sg, synth, torch, np) -> int:
                                 f"zeta=8, tol=1e-10"), "rows": rows, "nnz": nnz},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "batched_cycle_kernel (whole solve: algorithmic basis bytes / solve time)"},
+                     "kernel": ("batched_cycle_kernel" if bpath == sg.PATH_PART_SPLIT else "arnoldi_multi_kernel")
+                     + " (whole solve: algorithmic basis bytes / solve time)"},
         "many_systems": m, "rhs_block": out["block"],
     }), flush=True)
     return 0
@@ -347,7 +351,7 @@ def main() -> int:
     ap.add_argument("--batch-count", type=int, default=256, help="systems in the many-systems workload")
     ap.add_argument("--block-rhs", type=int, default=32, help="right-hand sides of the n = 2^20 block")
     ap.add_argument("--halo-off", action="store_true", help="truncated Arnoldi: three grid barriers per step")
-    ap.add_argument("--path", default="auto", choices=["auto", "stream", "part-split"],
+    ap.add_argument("--path", default="auto", choices=["auto", "stream", "part-split", "multi"],
                     help="basis kernel for systems beyond the resident capacity (auto: streaming)")
     ap.add_argument("--stream-state", type=int, default=0, choices=[0, 1, 2],
                     help="streaming path: 0 auto, 1 m and w in registers, 2 in an HBM buffer")
@@ -393,7 +397,7 @@ def main() -> int:
     cheb = args.basis == "chebyshev"
     box = tuple(float(t) for t in args.cheb_box.split(",")) if cheb else None
 
-    path = {"auto": 0, "stream": sg.PATH_STREAM, "part-split": sg.PATH_PART_SPLIT}[args.path]
+    path = {"auto": 0, "stream": sg.PATH_STREAM, "part-split": sg.PATH_PART_SPLIT, "multi": 0}[args.path]
 
     def solve(profile: bool) -> dict:
         x.zero_()

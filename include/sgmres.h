@@ -113,6 +113,9 @@ typedef struct {
 #define SGMRES_PATH_STREAM 5       /* streaming truncated Arnoldi (n above the resident
                                       capacity): window read back from B, S B formed
                                       from the finished basis and S A B = (S B) H */
+#define SGMRES_PATH_MULTI 6        /* batched solve: several systems per resident
+                                      truncated-Arnoldi launch, one group of
+                                      workgroups each */
 
 /* Options of sgmres_solve_ex; zero-initialise for the defaults. */
 typedef struct {

@@ -24,6 +24,7 @@ from .sgmres import (  # noqa: F401
     PATH_CHEBYSHEV,
     PATH_PART_SPLIT,
     PATH_STREAM,
+    PATH_MULTI,
     LIB_PATH,
     lib,
     sgmres_solve,

@@ -69,8 +69,10 @@ __device__ __forceinline__ float gs_sub(float x, float h, float v) { return __bu
 //     values are the owner's bits.  (Publishing a double takes two tagged
 //     words; measured slower: 9.84 -> 9.21 solves/s at n = 2^20.)
 // Chosen when few nonzeros reach outside their block (requires SKB = false).
-template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO = false>
-__global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
+// One cycle of one system on the G blocks of its grid (or group of blocks);
+// blk: this block's logical index among them.
+template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO>
+__device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G, const int blk) {
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
     constexpr int RB = R * BLOCK;  // rows per block
@@ -89,8 +91,6 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
     uint16_t* lists = reinterpret_cast<uint16_t*>(lcount + s + 1);  // 8-byte aligned (2s + 2 ints)
     __shared__ unsigned sync_lds[3];
 
-    const int G = gridDim.x;
-    const int blk = xcd_logical_block(blockIdx.x, G);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
@@ -593,6 +593,27 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
         p.status[0] = dc;
         p.status[1] |= flags;
     }
+}
+
+template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO = false>
+__global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
+    arnoldi_body<R, KW, BLOCK, SKB, TC, TS, HALO>(p, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+// Several independent systems in one cooperative launch (the batched solve):
+// logical block lb belongs to group grp[lb] (-1: idle padding), and group g
+// runs one cycle of the system described by ps[g] on its ps[g].G blocks, the
+// logical blocks [ps[g].blk0, ps[g].blk0 + ps[g].G), which the XCD-aware
+// numbering keeps on as few XCDs as possible.  Each group has its own grid
+// barrier words, partial sums and status; groups never wait for each other.
+template <int R, int KW, int BLOCK, typename TC, typename TS>
+__global__ __launch_bounds__(BLOCK) void arnoldi_multi_kernel(const ArnoldiParams* __restrict__ ps,
+                                                              const int* __restrict__ grp) {
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int g = __builtin_amdgcn_readfirstlane(grp[lb]);
+    if (g < 0) return;
+    const ArnoldiParams& p = ps[g];
+    arnoldi_body<R, KW, BLOCK, false, TC, TS, false>(p, p.G, lb - p.blk0);
 }
 
 // Kernel instance for (BLOCK, R, KW); (R, KW) = (8, 8) is never selected

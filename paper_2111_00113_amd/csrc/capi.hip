@@ -115,6 +115,23 @@ struct Workspace {
     unsigned char* bt_arena = nullptr;
     size_t bt_arena_cap = 0;
     hipStream_t capture_stream = nullptr;
+    // batched solve, several systems per resident basis launch: persistent
+    // per-system arena (sliced ELL copies, residuals, small matrices), the
+    // per-wave basis / partial-sum / barrier arena, descriptors
+    unsigned char* wv_sys_arena = nullptr;
+    size_t wv_sys_arena_cap = 0;
+    unsigned char* wv_wave_arena = nullptr;
+    size_t wv_wave_arena_cap = 0;
+    int* wv_K = nullptr;
+    size_t wv_K_cap = 0;
+    ArnoldiParams* wv_ps = nullptr;
+    size_t wv_ps_cap = 0;
+    int* wv_idx = nullptr;  // per wave: group of each logical block, then the system of each group
+    size_t wv_idx_cap = 0;
+    BatchSys* wv_sys = nullptr;
+    size_t wv_sys_cap = 0;
+    BatchState* wv_st = nullptr;
+    size_t wv_st_cap = 0;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
@@ -1242,6 +1259,289 @@ int batch_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, i
     return all;
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve, several systems per resident basis launch.  Each system runs
+// the cycles of sgmres_solve (same sketch keys, same stopping rule), its basis
+// cycle on its own group of G_i = ceil(n_i / rows) workgroups of the
+// multi-system kernel.  Systems are packed, largest first, into waves of at
+// most `capacity` workgroups (first fit); a round runs one cycle of every
+// active system, wave after wave on the stream:
+//   basis launch (all groups of the wave) -> least squares (one workgroup per
+//   system) -> per system x += B y, r = b - A x, |r|, |r|/|b|
+// and ends with one read of the per-system states, which decides the next
+// round.  The basis arena (B, partial sums, barrier words) is sized for one
+// wave and reused by the next (stream order).
+// Caller holds g_mutex; sizes were validated and the CSR arrays checked.
+int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, int s, uint64_t seed, double tol,
+                      int restarts, int zeta, double kappa_max, int prec, int R, sgmres_batch_result_t* results,
+                      hipStream_t st) {
+    const int kk = (k > d - 1) ? (d > 1 ? d - 1 : 1) : k;
+    MultiLaunch L{};
+    if (arnoldi_multi_configure(R, kk, s, zeta, prec, &L) != hipSuccess) return SGMRES_EINVAL;
+    for (int i = 0; i < nsys; ++i)
+        if ((systems[i].A.n + L.rows - 1) / L.rows > L.capacity) return SGMRES_EINVAL;
+    Workspace* wsp = nullptr;
+    int rc = workspace(&wsp);
+    if (rc) return rc;
+    Workspace& ws = *wsp;
+    const size_t eb = basis_elem_bytes(prec);
+    const size_t ev = prec == SGMRES_PREC_FP64 ? 8 : 4;  // sliced ELL value bytes
+
+    // ---- sliced ELL copies: widths of every system, one read, then fills ----
+    std::vector<int64_t> koff(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i) koff[i + 1] = koff[i] + (systems[i].A.n + 63) / 64;
+    SG_TRY(ensure(ws.wv_K, ws.wv_K_cap, static_cast<size_t>(koff[nsys])));
+    for (int i = 0; i < nsys; ++i) SG_TRY(launch_sell_width(systems[i].A.n, systems[i].A.row_ptr, ws.wv_K + koff[i], st));
+    std::vector<int> K(static_cast<size_t>(koff[nsys]));
+    SG_TRY(hipMemcpyAsync(K.data(), ws.wv_K, sizeof(int) * K.size(), hipMemcpyDeviceToHost, st));
+    SG_TRY(hipStreamSynchronize(st));
+    // per-system arena: sp, col, val, r, SAB, H, g, y
+    std::vector<std::vector<int64_t>> sp(nsys);
+    std::vector<size_t> off(nsys + 1, 0);
+    for (int i = 0; i < nsys; ++i) {
+        const int64_t n = systems[i].A.n, nsl = (n + 63) / 64;
+        sp[i].assign(static_cast<size_t>(nsl + 1), 0);
+        for (int64_t q = 0; q < nsl; ++q) sp[i][q + 1] = sp[i][q] + 64 * static_cast<int64_t>(K[koff[i] + q]);
+        const size_t tot = static_cast<size_t>(sp[i][nsl] > 0 ? sp[i][nsl] : 1);
+        size_t b = align_up(8 * (nsl + 1)) + align_up(4 * tot) + align_up(ev * tot) + align_up(8 * static_cast<size_t>(n));
+        b += align_up(8 * static_cast<size_t>(s) * d) + align_up(8 * static_cast<size_t>(kk + 1) * d) +
+             align_up(8 * static_cast<size_t>(s)) + align_up(8 * static_cast<size_t>(d));
+        off[i + 1] = off[i] + b;
+    }
+    SG_TRY(ensure(ws.wv_sys_arena, ws.wv_sys_arena_cap, off[nsys]));
+    SG_TRY(ensure(ws.wv_sys, ws.wv_sys_cap, static_cast<size_t>(nsys)));
+    SG_TRY(ensure(ws.wv_st, ws.wv_st_cap, static_cast<size_t>(nsys)));
+    SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    struct SysBufs {
+        int64_t* sp;
+        int32_t* col;
+        void* val;
+        double *r, *SAB, *H, *g, *y;
+    };
+    std::vector<SysBufs> sb(nsys);
+    std::vector<BatchSys> desc(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        const sgmres_csr_t& A = systems[i].A;
+        const int64_t n = A.n, nsl = (n + 63) / 64;
+        const size_t tot = static_cast<size_t>(sp[i][nsl] > 0 ? sp[i][nsl] : 1);
+        unsigned char* q = ws.wv_sys_arena + off[i];
+        SysBufs& B = sb[i];
+        B.sp = reinterpret_cast<int64_t*>(q);
+        q += align_up(8 * (nsl + 1));
+        B.col = reinterpret_cast<int32_t*>(q);
+        q += align_up(4 * tot);
+        B.val = q;
+        q += align_up(ev * tot);
+        B.r = reinterpret_cast<double*>(q);
+        q += align_up(8 * static_cast<size_t>(n));
+        B.SAB = reinterpret_cast<double*>(q);
+        q += align_up(8 * static_cast<size_t>(s) * d);
+        B.H = reinterpret_cast<double*>(q);
+        q += align_up(8 * static_cast<size_t>(kk + 1) * d);
+        B.g = reinterpret_cast<double*>(q);
+        q += align_up(8 * static_cast<size_t>(s));
+        B.y = reinterpret_cast<double*>(q);
+        SG_TRY(hipMemcpyAsync(B.sp, sp[i].data(), sizeof(int64_t) * (nsl + 1), hipMemcpyHostToDevice, st));
+        SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, B.sp, B.col, B.val, prec, st));
+        BatchSys& D = desc[i];
+        D = BatchSys{};
+        D.n = n;
+        D.rp = A.row_ptr;
+        D.ci = A.col_idx;
+        D.val = A.val;
+        D.b = systems[i].b;
+        D.x = systems[i].x;
+        D.r = B.r;
+        D.SAB = B.SAB;
+        D.g = B.g;
+        D.y = B.y;
+    }
+    SG_TRY(hipMemcpyAsync(ws.wv_sys, desc.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+    SG_TRY(hipStreamSynchronize(st));  // the host vectors above are read by the copies
+    SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.wv_st), static_cast<int64_t>(sizeof(BatchState) / 4) * nsys,
+                           0u, st));
+    SG_TRY(hipMemsetAsync(&ws.sc->abort, 0, sizeof(int), st));
+
+    // ---- |b| and the first residual --------------------------------------
+    for (int i = 0; i < nsys; ++i) {
+        const sgmres_csr_t& A = systems[i].A;
+        BatchState* t = ws.wv_st + i;
+        SG_TRY(launch_residual(A.n, nullptr, nullptr, nullptr, systems[i].b, nullptr, sb[i].r, ws.part_vec, st));
+        SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(A.n), &t->nf, nullptr, st));
+        SG_TRY(launch_residual(A.n, A.row_ptr, A.col_idx, A.val, systems[i].b, systems[i].x, sb[i].r, ws.part_vec, st));
+        SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(A.n), &t->beta, &t->nf, st));
+    }
+    std::vector<BatchState> hs(nsys);
+    auto read_states = [&]() -> int {
+        SG_TRY(hipMemcpyAsync(hs.data(), ws.wv_st, sizeof(BatchState) * nsys, hipMemcpyDeviceToHost, st));
+        return copy_scalars(ws, st);  // synchronises
+    };
+    rc = read_states();
+    if (rc) return rc;
+    // status per system: 0 active, else the final code + 1 (codes are <= 0 or 1)
+    std::vector<int> code(nsys, 0), done(nsys, 0), cycles(nsys, 0), steps(nsys, 0);
+    for (int i = 0; i < nsys; ++i) {
+        if (!std::isfinite(hs[i].nf)) {
+            code[i] = SGMRES_ENONFINITE;
+            done[i] = 1;
+        } else if (hs[i].nf == 0.0) {
+            SG_TRY(launch_fill(systems[i].x, systems[i].A.n, 0.0, st));
+            hs[i].rho = 0.0;
+            code[i] = SGMRES_OK;
+            done[i] = 1;
+        }
+    }
+
+    // ---- rounds -----------------------------------------------------------
+    const int cap = L.capacity;
+    const size_t sync_u32 = sync_words_bytes() / sizeof(unsigned);
+    const size_t pab_u64 = static_cast<size_t>(4 * (kk + 1)) * cap;
+    const size_t psk_dbl = static_cast<size_t>(2 * s * d + s) * cap;
+    // B of one wave: at most cap groups, each column padded to 128 entries
+    const size_t b_bytes = align_up(static_cast<size_t>(cap * L.rows + 128 * static_cast<int64_t>(cap)) * d * eb);
+    const size_t wave_bytes = align_up(sync_u32 * 4 * cap) + align_up(8 * pab_u64) + align_up(8 * psk_dbl) + b_bytes;
+    SG_TRY(ensure(ws.wv_wave_arena, ws.wv_wave_arena_cap, wave_bytes));
+    unsigned* w_sync = reinterpret_cast<unsigned*>(ws.wv_wave_arena);
+    unsigned long long* w_pab = reinterpret_cast<unsigned long long*>(ws.wv_wave_arena + align_up(sync_u32 * 4 * cap));
+    double* w_psk = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(w_pab) + align_up(8 * pab_u64));
+    unsigned char* w_B = reinterpret_cast<unsigned char*>(w_psk) + align_up(8 * psk_dbl);
+
+    std::vector<int> order(nsys);
+    for (int i = 0; i < nsys; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return systems[a].A.n > systems[b].A.n; });
+    int status_all = SGMRES_OK;
+    for (;;) {
+        // decide every undecided system from its last residual (as sgmres_solve)
+        std::vector<int> active;
+        for (int i : order) {
+            if (done[i]) continue;
+            const double rho = hs[i].rho;
+            if (!std::isfinite(rho)) code[i] = SGMRES_ENONFINITE, done[i] = 1;
+            else if (rho <= tol) code[i] = SGMRES_OK, done[i] = 1;
+            else if (cycles[i] > restarts) code[i] = SGMRES_NOT_CONVERGED, done[i] = 1;
+            else active.push_back(i);
+        }
+        if (active.empty()) break;
+        // first-fit waves, largest systems first
+        std::vector<std::vector<int>> waves;
+        {
+            std::vector<int> room;
+            for (int i : active) {
+                const int G = static_cast<int>((systems[i].A.n + L.rows - 1) / L.rows);
+                size_t w = 0;
+                while (w < waves.size() && room[w] < G) ++w;
+                if (w == waves.size()) {
+                    waves.emplace_back();
+                    room.push_back(cap);
+                }
+                waves[w].push_back(i);
+                room[w] -= G;
+            }
+        }
+        const size_t nw = waves.size();
+        SG_TRY(ensure(ws.wv_ps, ws.wv_ps_cap, nw * cap));
+        SG_TRY(ensure(ws.wv_idx, ws.wv_idx_cap, nw * 2 * cap));
+        std::vector<ArnoldiParams> ps(nw * cap);
+        std::vector<int> idx(nw * 2 * cap, -1);
+        std::vector<int> grids(nw);
+        struct Slot {
+            int sys;
+            int64_t ldb;
+            void* B;
+        };
+        std::vector<std::vector<Slot>> slots(nw);
+        for (size_t w = 0; w < nw; ++w) {
+            int blk0 = 0;
+            size_t boff = 0;
+            for (size_t g = 0; g < waves[w].size(); ++g) {
+                const int i = waves[w][g];
+                const sgmres_csr_t& A = systems[i].A;
+                const int G = static_cast<int>((A.n + L.rows - 1) / L.rows);
+                const int64_t ldb = (A.n + 127) / 128 * 128;
+                void* B = w_B + boff;
+                boff += align_up(static_cast<size_t>(ldb) * d * eb);
+                ArnoldiParams& p = ps[w * cap + g];
+                p = ArnoldiParams{};
+                p.n = A.n;
+                p.rp = A.row_ptr;
+                p.sp = sb[i].sp;
+                p.ci = sb[i].col;
+                p.val = sb[i].val;
+                p.r = sb[i].r;
+                p.beta = &ws.wv_st[i].beta;
+                p.B = B;
+                p.ldb = ldb;
+                p.SB = nullptr;
+                p.SAB = sb[i].SAB;
+                p.H = sb[i].H;
+                p.g = sb[i].g;
+                p.d = d;
+                p.k = kk;
+                p.s = s;
+                p.zeta = zeta;
+                p.seed = seed;
+                p.cycle = static_cast<uint32_t>(cycles[i]);
+                p.part_a = w_pab + static_cast<size_t>(4 * (kk + 1)) * blk0;
+                p.part_b = p.part_a + static_cast<size_t>(2 * (kk + 1)) * G;
+                p.part_sk = w_psk + static_cast<size_t>(2 * s * d + s) * blk0;
+                p.sync = w_sync + sync_u32 * g;
+                p.per_block_release = 0;
+                p.abort = &ws.sc->abort;
+                p.status = &ws.wv_st[i].dc;
+                p.spin_limit = kSpinLimitTicks;
+                p.phase_ticks = nullptr;
+                p.spmv_mode = 0;
+                p.hbuf = nullptr;
+                p.xbits = nullptr;
+                p.G = G;
+                p.blk0 = blk0;
+                for (int b = 0; b < G; ++b) idx[w * 2 * cap + blk0 + b] = static_cast<int>(g);
+                idx[w * 2 * cap + cap + g] = i;
+                slots[w].push_back(Slot{i, ldb, B});
+                blk0 += G;
+            }
+            grids[w] = (blk0 + 7) / 8 * 8;
+        }
+        SG_TRY(hipMemcpyAsync(ws.wv_ps, ps.data(), sizeof(ArnoldiParams) * ps.size(), hipMemcpyHostToDevice, st));
+        SG_TRY(hipMemcpyAsync(ws.wv_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
+        for (size_t w = 0; w < nw; ++w) {
+            const int ng = static_cast<int>(waves[w].size());
+            SG_TRY(launch_fill_u32(w_sync, static_cast<int64_t>(sync_u32) * ng, 0u, st));
+            SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(w_pab), static_cast<int64_t>(2 * pab_u64), 0u, st));
+            SG_TRY(arnoldi_multi_launch(L, grids[w], ws.wv_ps + w * cap, ws.wv_idx + w * 2 * cap, st));
+            SG_TRY(launch_lsq_batched(ng, s, ws.wv_sys, ws.wv_st, kappa_max, st, ws.wv_idx + w * 2 * cap + cap));
+            for (const Slot& sl : slots[w]) {
+                const int i = sl.sys;
+                const sgmres_csr_t& A = systems[i].A;
+                BatchState* t = ws.wv_st + i;
+                SG_TRY(launch_combine(A.n, &t->d_eff, d, sl.B, sl.ldb, sb[i].y, systems[i].x, st, nullptr, prec));
+                SG_TRY(launch_residual(A.n, A.row_ptr, A.col_idx, A.val, systems[i].b, systems[i].x, sb[i].r,
+                                       ws.part_vec, st));
+                SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(A.n), &t->beta, &t->nf, st));
+            }
+        }
+        rc = read_states();  // also orders the host vectors' copies above
+        if (rc) return rc;
+        if (ws.host_sc->abort) return SGMRES_ETIMEOUT;
+        for (int i : active) {
+            ++cycles[i];
+            steps[i] += hs[i].dc;
+        }
+    }
+    for (int i = 0; i < nsys; ++i) {
+        if (code[i] != SGMRES_OK) status_all = SGMRES_NOT_CONVERGED;
+        if (results) {
+            results[i].status = code[i];
+            results[i].cycles = cycles[i];
+            results[i].steps = steps[i];
+            results[i].flags = hs[i].flags | hs[i].lsq_flags;
+            results[i].relres = hs[i].rho;
+        }
+    }
+    return status_all;
+}
+
+
 // A block of nb <= 32 right-hand sides sharing A, solved together: one
 // streaming basis launch per cycle builds all nb bases, reading each nonzero
 // of A once for all of them (pairs (row, right-hand side) interleaved), then
@@ -1755,7 +2055,8 @@ void sgmres_release_workspace(void) {
                         w.part_vec, w.part_nrm, w.colnorm, w.valf, w.hbuf, w.xbits, w.sell_K, w.sell_sp, w.sell_col,
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
-                        w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr};
+                        w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr, w.wv_sys_arena, w.wv_wave_arena, w.wv_K,
+                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);
@@ -1861,8 +2162,35 @@ int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k,
     std::vector<sgmres_system_t> sub(small.size());
     std::vector<sgmres_batch_result_t> sres(small.size());
     for (size_t q = 0; q < small.size(); ++q) sub[q] = systems[small[q]];
-    int rc;
-    {
+    // the rest: several systems per resident basis launch (unless the
+    // part-split kernel is asked for, or no instance fits the shape)
+    const int path = opts ? opts->path : 0;
+    const int kk = (k > d - 1) ? (d > 1 ? d - 1 : 1) : k;
+    int rc = SGMRES_EINVAL;
+    if (path != SGMRES_PATH_PART_SPLIT && kk <= kMultiMaxK) {
+        const int R = (opts && opts->rows_per_thread == 2) ? 2 : 4;
+        const double kmax = (opts && opts->kappa_max > 0) ? opts->kappa_max : 1e14;
+        {
+            // every CSR is checked before anything is solved
+            std::lock_guard<std::mutex> lock(g_mutex);
+            Workspace* wsp = nullptr;
+            rc = workspace(&wsp);
+            if (rc) return rc;
+            SG_TRY(hipMemsetAsync(&wsp->sc->csr_bad, 0, sizeof(int), st));
+            for (const sgmres_system_t& y : sub)
+                SG_TRY(launch_csr_check(y.A.n, y.A.nnz, y.A.row_ptr, y.A.col_idx, &wsp->sc->csr_bad, st));
+            rc = copy_scalars(*wsp, st);
+            if (rc) return rc;
+            if (wsp->host_sc->csr_bad) return SGMRES_ECSR;
+        }
+        {
+            std::lock_guard<std::mutex> lock(g_mutex);
+            rc = wave_solve_locked(static_cast<int>(sub.size()), sub.data(), d, k, s, seed, tol, restarts, zeta,
+                                   kmax, prec, R, sres.data(), st);
+        }
+        if (rc == SGMRES_EINVAL && path == SGMRES_PATH_MULTI) return rc;
+    }
+    if (rc == SGMRES_EINVAL) {
         std::lock_guard<std::mutex> lock(g_mutex);
         rc = batch_solve_locked(static_cast<int>(sub.size()), sub.data(), d, k, s, seed, tol, restarts, opts,
                                 sres.data(), st);

@@ -42,6 +42,7 @@ struct ArnoldiParams {
     // FP64, w of the current step
     void* hbuf;
     const unsigned* xbits;
+    int G, blk0;  // several systems per launch: the group's blocks and first logical block
 };
 
 struct ArnoldiShape {
@@ -69,6 +70,22 @@ __host__ __device__ constexpr int arnoldi_vals_doubles(int RB, int zeta) {
 }
 
 size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta);
+// ---- several systems per basis launch (arnoldi_multi.hip) ------------------
+constexpr int kMultiBlock = 1024;  // threads per workgroup
+constexpr int kMultiMaxK = 4;      // register window of the instances
+struct MultiLaunch {
+    const void* fn;
+    int R;
+    int64_t rows;   // rows per workgroup (R * kMultiBlock)
+    int capacity;   // workgroups that can be resident at once
+    size_t lds;
+};
+hipError_t arnoldi_multi_configure(int R, int k, int s, int zeta, int precision, MultiLaunch* out);
+// grid: a multiple of 8 (XCD-aware block numbering) up to capacity; ps: one
+// ArnoldiParams per group (G, blk0 set); grp: group of each logical block
+hipError_t arnoldi_multi_launch(const MultiLaunch& L, int grid, const ArnoldiParams* ps, const int* grp,
+                                hipStream_t stream);
+
 hipError_t arnoldi_configure(const ArnoldiShape& shape, ArnoldiLaunch* out);
 hipError_t arnoldi_launch(const ArnoldiLaunch& L, ArnoldiParams params, hipStream_t stream);
 size_t sync_words_bytes();
@@ -284,7 +301,7 @@ hipError_t batch_launch(const BatchLaunch& L, const BatchParams& p, hipStream_t 
 hipError_t launch_batch_advance(int* ctr, BatchState* st, unsigned* gcnt, int nsys, hipStream_t stream);
 hipError_t launch_batch_reset(BatchState* st, unsigned* gcnt, int nsys, int* ctr, hipStream_t stream);
 hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
-                              hipStream_t stream);
+                              hipStream_t stream, const int* idx = nullptr);
 
 // ---- sliced ELL copy of A for the basis kernels (sell.hip) ----------------
 // K[i] = longest row of slice i (rows 64 i .. 64 i + 63); sp = exclusive prefix

@@ -145,13 +145,16 @@ __global__ __launch_bounds__(kLsqBlock) void lsq_kernel(int s, const int* __rest
     lsq_body(s, dc_dev ? *dc_dev : dc_host, C, g, kappa_max, y, dout, iout, v);
 }
 
-// One workgroup per system of a batch; systems no longer active are skipped.
+// One workgroup per system of a batch (system idx[b] for workgroup b when idx
+// is given); systems no longer active are skipped.
 __global__ __launch_bounds__(kLsqBlock) void lsq_batched_kernel(int s, const BatchSys* __restrict__ sys,
-                                                                BatchState* __restrict__ st, double kappa_max) {
+                                                                BatchState* __restrict__ st, double kappa_max,
+                                                                const int* __restrict__ idx) {
     extern __shared__ double v[];
-    BatchState* t = st + blockIdx.x;
+    const int i = idx ? idx[blockIdx.x] : static_cast<int>(blockIdx.x);
+    BatchState* t = st + i;
     if (t->status != 0 || t->next != 0) return;  // only systems that built a basis this cycle
-    const BatchSys& S = sys[blockIdx.x];
+    const BatchSys& S = sys[i];
     lsq_body(s, t->dc, S.SAB, S.g, kappa_max, S.y, &t->rest, &t->d_eff, v);
 }
 
@@ -573,9 +576,9 @@ hipError_t launch_lsq(int s, const int* dc_dev, int dc_host, double* C, double* 
 }
 
 hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
-                              hipStream_t stream) {
+                              hipStream_t stream, const int* idx) {
     if (nsys <= 0) return hipSuccess;
-    lsq_batched_kernel<<<nsys, kLsqBlock, sizeof(double) * s, stream>>>(s, sys, st, kappa_max);
+    lsq_batched_kernel<<<nsys, kLsqBlock, sizeof(double) * s, stream>>>(s, sys, st, kappa_max, idx);
     return hipGetLastError();
 }
 

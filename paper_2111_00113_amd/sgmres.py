@@ -28,6 +28,7 @@ PATH_ARNOLDI_HALO = 2
 PATH_CHEBYSHEV = 3
 PATH_PART_SPLIT = 4
 PATH_STREAM = 5
+PATH_MULTI = 6
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16_BASIS = 2
@@ -315,8 +316,11 @@ def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, z
     (rc, results) with rc SGMRES_OK when all converged, SGMRES_NOT_CONVERGED
     otherwise, and one dict per system (status, cycles, steps, flags, relres).
     Systems sharing one DeviceCSR (n >= 65,536) are solved as blocks of up to
-    32 right-hand sides by the streaming kernel; path=PATH_PART_SPLIT keeps
-    them on the part-split kernel instead."""
+    32 right-hand sides by the streaming kernel; the other systems below 2^19
+    rows run several to a resident basis launch (PATH_MULTI; rows_per_thread
+    2 or 4, default 4).  path=PATH_PART_SPLIT keeps every system on the
+    part-split kernel instead; path=PATH_MULTI requires the multi-system
+    launch."""
     arr = (_System * max(len(systems), 1))()
     keep = []
     for i, (A, b, x) in enumerate(systems):

@@ -1,10 +1,12 @@
-"""Batched solve (many systems, one launch per cycle) against the CPU oracle.
+"""Batched solve (many systems per launch) against the CPU oracle.
 
 Each system of a batch must get what the oracle's standalone restarted sGMRES
 gives for it: the same sketch (keyed by seed, cycle and the row within the
 system) and the same stopping rule.  FP64 bars as for the single-system path:
 x to 1e-8 relative and the true relative residual to 1e-10 absolute; the
-mixed-precision batch reaches 1e-10 with FP64 refinement.
+mixed-precision batch reaches 1e-10 with FP64 refinement.  Both batched
+kernels are covered: several systems per resident basis launch (the default,
+PATH_MULTI) and the part-split kernel (PATH_PART_SPLIT).
 """
 
 import numpy as np
@@ -48,6 +50,13 @@ def _mixed_batch(d):
     return [(A, synth.rhs(A.n, [0, i])) for i, A in enumerate(mats)]
 
 
+PATHS = ["multi", "part_split"]
+
+
+def _path(sg, name):
+    return {"multi": sg.PATH_MULTI, "part_split": sg.PATH_PART_SPLIT}[name]
+
+
 def _run(sg, batch, d, k, s, tol, restarts, **kw):
     print(f"[batched] {len(batch)} systems, n = {[A.n for A, _ in batch][:8]}, d={d} k={k} s={s} tol={tol} "
           f"restarts={restarts} {kw}", flush=True)
@@ -56,10 +65,11 @@ def _run(sg, batch, d, k, s, tol, restarts, **kw):
     return rc, res, [_np(x) for _, _, x in dev]
 
 
-def test_batched_one_cycle_parity(sg, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_batched_one_cycle_parity(sg, orc, path):
     d, k, s = 40, 2, 90
     batch = _mixed_batch(d)
-    rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0)
+    rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, path=_path(sg, path))
     assert rc == sg.NOT_CONVERGED  # tol 0: every system stops after its one cycle
     for (A, b), r, x in zip(batch, res, xs):
         rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=0.0, restarts=0)
@@ -68,10 +78,11 @@ def test_batched_one_cycle_parity(sg, orc):
         assert abs(r["relres"] - info_o["relres"]) <= 1e-10
 
 
-def test_batched_restarted_parity(sg, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_batched_restarted_parity(sg, orc, path):
     d, k, s = 40, 2, 90
     batch = _mixed_batch(d)
-    rc, res, xs = _run(sg, batch, d, k, s, 1e-10, 300)
+    rc, res, xs = _run(sg, batch, d, k, s, 1e-10, 300, path=_path(sg, path))
     assert rc == sg.OK
     for (A, b), r, x in zip(batch, res, xs):
         rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=1e-10, restarts=300)
@@ -84,15 +95,17 @@ def test_batched_restarted_parity(sg, orc):
         assert np.linalg.norm(x - x_o) <= 1e-8 * np.linalg.norm(x_o)
 
 
-def test_batched_multipart_parity(sg, orc):
-    # systems above 16384 rows are split over several workgroups that
-    # synchronise per step; results must match the oracle as for one part
+@pytest.mark.parametrize("path", PATHS)
+def test_batched_multipart_parity(sg, orc, path):
+    # systems above 16384 rows (part-split kernel) or 4096 rows (multi-system
+    # launch) are spread over several workgroups that synchronise per step;
+    # results must match the oracle as for one workgroup
     d, k, s = 40, 2, 90
     mats = [synth.random_dominant(70001, offdiag=6, seed=[6, 0]), synth.convection_diffusion(200, (50.0, 20.0)),
             synth.random_dominant(17000, offdiag=6, seed=[6, 2]), synth.random_dominant(3000, offdiag=6, seed=[6, 3])]
     batch = [(A, synth.rhs(A.n, [1, i])) for i, A in enumerate(mats)]
     for tol, restarts in ((0.0, 0), (1e-10, 200)):
-        rc, res, xs = _run(sg, batch, d, k, s, tol, restarts)
+        rc, res, xs = _run(sg, batch, d, k, s, tol, restarts, path=_path(sg, path))
         for (A, b), r, x in zip(batch, res, xs):
             rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=tol, restarts=restarts)
             print(f"n={A.n} tol={tol}: cycles {r['cycles']} (oracle {info_o['cycles']}), relres {r['relres']:.3e} "
@@ -113,7 +126,8 @@ def test_batched_graph_replays_match_eager(sg, orc):
     batch = _mixed_batch(d)
     out = []
     for eager in (False, True, False):
-        rc, res, xs = _run(sg, batch, d, k, s, 1e-12, 6, eager=eager, block_size=512, rows_per_thread=4)
+        rc, res, xs = _run(sg, batch, d, k, s, 1e-12, 6, eager=eager, block_size=512, rows_per_thread=4,
+                           path=sg.PATH_PART_SPLIT)
         out.append((xs, [r["relres"] for r in res], [r["cycles"] for r in res]))
     for o in out[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(o[0], out[0][0]))
@@ -121,12 +135,13 @@ def test_batched_graph_replays_match_eager(sg, orc):
 
 
 def test_batched_shapes_agree(sg, orc):
-    # every workgroup shape solves the batch (the autotuner picks among them)
+    # every workgroup shape of the part-split kernel solves the batch (the
+    # autotuner picks among them)
     d, k, s = 40, 2, 90
     batch = _mixed_batch(d)[:3]
     ref = None
     for block, R in [(256, 4), (512, 2), (512, 4), (1024, 1), (1024, 2), (1024, 4)]:
-        rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, block_size=block, rows_per_thread=R)
+        rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, block_size=block, rows_per_thread=R, path=sg.PATH_PART_SPLIT)
         if ref is None:
             ref = xs
         for x, xr in zip(xs, ref):
@@ -147,11 +162,12 @@ def test_batched_block_of_right_hand_sides(sg, orc):
         assert r["cycles"] == info_o["cycles"]
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_batched_mixed_precision_refinement(sg, orc, prec):
+def test_batched_mixed_precision_refinement(sg, orc, prec, path):
     d, k, s = 40, 2, 90
     batch = _mixed_batch(d)
-    rc, res, xs = _run(sg, batch, d, k, s, 1e-10, 300, precision=prec)
+    rc, res, xs = _run(sg, batch, d, k, s, 1e-10, 300, precision=prec, path=_path(sg, path))
     assert rc == sg.OK
     for (A, b), r, x in zip(batch, res, xs):
         rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=1e-10, restarts=300)
@@ -163,7 +179,8 @@ def test_batched_mixed_precision_refinement(sg, orc, prec):
         assert err <= 1e-6
 
 
-def test_batched_edge_cases(sg, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_batched_edge_cases(sg, orc, path):
     d, k, s = 20, 2, 44
     A = synth.random_dominant(3000, offdiag=6, seed=1)
     dA = sg.DeviceCSR.from_host(A)
@@ -172,7 +189,8 @@ def test_batched_edge_cases(sg, orc):
     bad[7] = float("nan")
     good = _t(synth.rhs(A.n, 2))
     xs = [torch.ones(A.n, dtype=torch.float64, device=DEV) for _ in range(3)]
-    rc, res = sg.sgmres_solve_batched([(dA, z, xs[0]), (dA, bad, xs[1]), (dA, good, xs[2])], d, k, s, 0, 1e-10, 50)
+    rc, res = sg.sgmres_solve_batched([(dA, z, xs[0]), (dA, bad, xs[1]), (dA, good, xs[2])], d, k, s, 0, 1e-10, 50,
+                                      path=_path(sg, path))
     assert rc == sg.NOT_CONVERGED
     assert res[0]["status"] == sg.OK and float(xs[0].abs().max()) == 0.0  # b = 0 gives x = 0
     assert res[1]["status"] == -5  # SGMRES_ENONFINITE for that system only
@@ -185,12 +203,14 @@ def test_batched_edge_cases(sg, orc):
         assert e.value.rc == -1
 
 
-def test_batched_workload_subset(sg, orc):
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_workload_subset(sg, orc, prec, path):
     """The first 24 systems of the many-systems workload (n in [16384, 262144],
-    7 nonzeros per row, d = 100, k = 2, s = 200), FP32 cycles with FP64
-    refinement to 1e-10; residuals confirmed by the oracle."""
+    7 nonzeros per row, d = 100, k = 2, s = 200), FP64, and FP32 cycles with
+    FP64 refinement, to 1e-10; residuals confirmed by the oracle."""
     batch = synth.batch_workload(24)
-    rc, res, xs = _run(sg, batch, 100, 2, 200, 1e-10, 50, precision="fp32")
+    rc, res, xs = _run(sg, batch, 100, 2, 200, 1e-10, 50, precision=prec, path=_path(sg, path))
     assert rc == sg.OK
     for (A, b), r, x in zip(batch, res, xs):
         _, nrm = orc.residual(A, b, x)
@@ -218,3 +238,54 @@ def test_batched_routes_large_systems_to_resident_kernels(sg, orc):
         _, nrm = orc.residual(A, f, _np(x))
         assert nrm / np.linalg.norm(f) <= 1e-10
         assert abs(r["relres"] - nrm / np.linalg.norm(f)) <= 1e-12
+
+
+def test_multi_matches_single_system_solve_bits(sg, orc):
+    """A system solved in a multi-system launch runs the resident kernel's
+    cycle on its own group of workgroups: the basis, least squares and update
+    are those of sgmres_solve with the same launch shape (1024 x 4, three
+    barriers), so x agrees bit for bit; other systems in the same launch do
+    not change it."""
+    d, k, s = 40, 2, 90
+    batch = _mixed_batch(d)
+    rc, res, xs = _run(sg, batch, d, k, s, 1e-10, 300, path=sg.PATH_MULTI)
+    alone_rc, alone_res, alone_xs = _run(sg, batch[4:5], d, k, s, 1e-10, 300, path=sg.PATH_MULTI)
+    assert np.array_equal(alone_xs[0], xs[4]) and alone_res[0] == res[4]
+    for (A, b), r, x in zip(batch, res, xs):
+        x1 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc1, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(b), x1, d, k, s, 3, 1e-10, 300, block_size=1024,
+                                    rows_per_thread=4, halo_off=True)
+        err = np.linalg.norm(_np(x1) - x) / np.linalg.norm(x)
+        print(f"n={A.n}: cycles {r['cycles']} / {info['cycles']}, |x_multi - x_single|/|x| = {err:.2e}", flush=True)
+        assert r["cycles"] == info["cycles"] and r["steps"] == info["steps"]
+        assert err <= 1e-13
+
+
+@pytest.mark.parametrize("R", [2, 4])
+def test_multi_rows_per_thread(sg, orc, R):
+    """Both multi-system instances (two or four rows per thread) against the
+    oracle, one cycle; the two differ only in the order of partial sums."""
+    d, k, s = 40, 2, 90
+    batch = _mixed_batch(d)
+    rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, path=sg.PATH_MULTI, rows_per_thread=R)
+    for (A, b), r, x in zip(batch, res, xs):
+        rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=0.0, restarts=0)
+        assert r["cycles"] == 1 and r["steps"] == info_o["steps"]
+        assert np.linalg.norm(x - x_o) <= 1e-8 * np.linalg.norm(x_o), A.n
+        assert abs(r["relres"] - info_o["relres"]) <= 1e-10
+
+
+def test_multi_waves(sg, orc):
+    """More groups than fit one launch: 40 systems of 40,000-70,000 rows (10 to
+    18 workgroups of 4096 rows each, about 560 in all) run in several waves;
+    each against the oracle's one cycle."""
+    d, k, s = 30, 2, 70
+    rng = np.random.default_rng(11)
+    mats = [synth.random_dominant(int(n), offdiag=6, seed=[9, i]) for i, n in enumerate(rng.integers(40000, 70001, 40))]
+    batch = [(A, synth.rhs(A.n, [3, i])) for i, A in enumerate(mats)]
+    rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, path=sg.PATH_MULTI)
+    for (A, b), r, x in list(zip(batch, res, xs))[::7]:
+        rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=0.0, restarts=0)
+        assert r["cycles"] == 1
+        assert np.linalg.norm(x - x_o) <= 1e-8 * np.linalg.norm(x_o), A.n
+        assert abs(r["relres"] - info_o["relres"]) <= 1e-10
