@@ -30,6 +30,10 @@ CFLAGS = [
     "-Wno-unused-function",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no floating-point contraction: fused multiply-adds are written out
+    # (madd, gs_sub), so kernel instances that must agree bit for bit do the
+    # same operations whatever the compiler schedules
+    "-ffp-contract=off",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 

@@ -229,13 +229,13 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
             double v[KW + 1];
             TC t = TC(0);
 #pragma unroll
-            for (int r = 0; r < R; ++r) t += x[r] * x[r];
+            for (int r = 0; r < R; ++r) t = madd(x[r], x[r], t);
             v[0] = static_cast<double>(t);
 #pragma unroll
             for (int a = 0; a < KW; ++a) {
                 TC u = TC(0);
 #pragma unroll
-                for (int r = 0; r < R; ++r) u += Wr(a, r) * x[r];
+                for (int r = 0; r < R; ++r) u = madd(Wr(a, r), x[r], u);
                 v[a + 1] = static_cast<double>(u);
             }
             // (no closing synchronisation: both callers synchronise the block
@@ -250,10 +250,10 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                     TC u = TC(0);
                     if (q == 0) {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) u += x[r] * x[r];
+                        for (int r = 0; r < R; ++r) u = madd(x[r], x[r], u);
                     } else if (q <= kw) {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) u += Wg(j, q - 1, r) * x[r];
+                        for (int r = 0; r < R; ++r) u = madd(Wg(j, q - 1, r), x[r], u);
                     }
                     v[c] = static_cast<double>(u);
                 }
@@ -371,7 +371,7 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                                            from_basis<TC>(ldB(Bp + cc - static_cast<int64_t>(a) * p.ldb)));
                             bv = from_basis<TC>(to_basis<TS>(t / nup));
                         }
-                        m[r] += v[r] * bv;
+                        m[r] = madd(v[r], bv, m[r]);
                     }
                 }
 #pragma unroll
@@ -401,7 +401,7 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                     if (q < sK[r]) {
                         const int cc = c[r];
                         const TS bv = (cc >= row_lo && cc < row_hi) ? bj[cc] : ldB(bj + cc);
-                        m[r] += v[r] * from_basis<TC>(bv);
+                        m[r] = madd(v[r], from_basis<TC>(bv), m[r]);
                     }
             }
         }
@@ -447,14 +447,14 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                 if (a < kw) {
                     const TC h = static_cast<TC>(coef[1 + a]);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) w[r] -= h * Wr(a, r);
+                    for (int r = 0; r < R; ++r) w[r] = gs_sub(w[r], h, Wr(a, r));
                 }
             }
         } else {
             for (int a = 0; a < kw; ++a) {
                 const TC h = static_cast<TC>(coef[1 + a]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) w[r] -= h * Wg(j, a, r);
+                for (int r = 0; r < R; ++r) w[r] = gs_sub(w[r], h, Wg(j, a, r));
             }
         }
         if constexpr (HALO && !kPub) {
@@ -480,7 +480,7 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
 
         // ---- phase 3: h2, nu, b_{j+1} -------------------------------------
         double h2sq = 0.0;
-        for (int a = 0; a < kw; ++a) h2sq += c2[1 + a] * c2[1 + a];
+        for (int a = 0; a < kw; ++a) h2sq = madd(c2[1 + a], c2[1 + a], h2sq);
         const double nu2 = c2[0] - h2sq;
         const double mm = coef[0];
         const bool breakdown = !(nu2 > 16.0 * uround * uround * mm);

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
             __syncthreads();
             for (int64_t row = r0 + tid; row < r1; row += BLOCK) {
                 double a = 0.0;
-                for (int c = 0; c < de; ++c) a += from_basis<double>(Bs[c * n + row]) * ylds[c];
+                for (int c = 0; c < de; ++c) a = madd(from_basis<double>(Bs[c * n + row]), ylds[c], a);
                 S.x[row] += a;
             }
             gsync();  // x complete before the residual gathers it
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
         double nf;
         if (cycle == 0) {
             double t = 0.0;
-            for (int64_t row = r0 + tid; row < r1; row += BLOCK) t += S.b[row] * S.b[row];
+            for (int64_t row = r0 + tid; row < r1; row += BLOCK) t = madd(S.b[row], S.b[row], t);
             const double v1[1] = {t};
             block_sum<1>(v1, 1, red_tmp, red_out);
             group_sum(1, nullptr);
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (q < rl[r]) ax[r] += v[r] * S.x[c[r]];
+                    if (q < rl[r]) ax[r] = madd(v[r], S.x[c[r]], ax[r]);
             }
             double rv[R];
 #pragma unroll
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                 if (row < r1) {
                     rv[r] = S.b[row] - ax[r];
                     S.r[row] = rv[r];
-                    rr += rv[r] * rv[r];
+                    rr = madd(rv[r], rv[r], rr);
                 }
             }
             if (build) {
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                     }
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        if (q < rl[r]) mv[r] += v[r] * from_basis<TC>(bj[c[r]]);
+                        if (q < rl[r]) mv[r] = madd(v[r], from_basis<TC>(bj[c[r]]), mv[r]);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -373,10 +373,10 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                     if (row < r1) {
                         const TC am = mv[r];
                         Ms[row] = am;
-                        dm[0] += static_cast<double>(am * am);
+                        dm[0] = dot_acc(dm[0], am, am);
 #pragma unroll
                         for (int a = 0; a < kBatchMaxK; ++a)
-                            if (a < kw) dm[1 + a] += static_cast<double>(Wv(a, row) * am);
+                            if (a < kw) dm[1 + a] = dot_acc(dm[1 + a], Wv(a, row), am);
                     }
                 }
                 __syncthreads();  // the previous chunk's lists and vals are consumed
@@ -407,12 +407,12 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                 TC wv = Ms[row];
 #pragma unroll
                 for (int a = 0; a < kBatchMaxK; ++a)
-                    if (a < kw) wv -= static_cast<TC>(h[a]) * Wv(a, row);
+                    if (a < kw) wv = madd(-static_cast<TC>(h[a]), Wv(a, row), wv);
                 Ws[row] = wv;
-                dw[0] += static_cast<double>(wv * wv);
+                dw[0] = dot_acc(dw[0], wv, wv);
 #pragma unroll
                 for (int a = 0; a < kBatchMaxK; ++a)
-                    if (a < kw) dw[1 + a] += static_cast<double>(Wv(a, row) * wv);
+                    if (a < kw) dw[1 + a] = dot_acc(dw[1 + a], Wv(a, row), wv);
             }
             block_sum<kBatchRed>(dw, kw + 1, red_tmp, red_out);
             group_sum(kw + 1, nullptr);
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
 #pragma unroll
             for (int a = 0; a < kBatchMaxK; ++a) {
                 h2[a] = (a < kw) ? red_out[1 + a] : 0.0;
-                h2sq += h2[a] * h2[a];
+                h2sq = madd(h2[a], h2[a], h2sq);
             }
             const double nu2 = red_out[0] - h2sq;
             if (!(nu2 > 16.0 * uround * uround * mm)) {  // invariant subspace: stop at this column
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void batched_cycle_kernel(BatchParams p) {
                 TC bv = Ws[row];
 #pragma unroll
                 for (int a = 0; a < kBatchMaxK; ++a)
-                    if (a < kw) bv -= static_cast<TC>(h2[a]) * Wv(a, row);
+                    if (a < kw) bv = madd(-static_cast<TC>(h2[a]), Wv(a, row), bv);
                 bn[row] = to_basis<TS>(bv / nu);
             }
             gsync();  // b_{j+1} complete before the next step gathers it

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
                 if (q < sK[r]) {
                     const int cc = c[r];
                     const TC bv = (lds_b && cc >= row_lo && cc < row_hi) ? bst[cc - row_lo] : from_basis<TC>(bj[cc]);
-                    m[r] += v[r] * bv;
+                    m[r] = madd(v[r], bv, m[r]);
                 }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-                const TS st = to_basis<TS>(a * (m[r] - cc * bcur[r]) - q * bprev[r]);
+                const TS st = to_basis<TS>(madd(a, madd(-cc, bcur[r], m[r]), -(q * bprev[r])));
                 if (row < n) bn[row] = st;
                 bnext[r] = from_basis<TC>(st);
             }
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double bc = static_cast<double>(bcur[r]);
-            nn += bc * bc;
+            nn = madd(bc, bc, nn);
             if (p.sketch_basis) vals[r * BLOCK + tid] = bc;
             vals[RB + r * BLOCK + tid] = static_cast<double>(m[r]);
         }

@@ -62,6 +62,18 @@ __device__ __forceinline__ TC from_basis(TS v) {
     }
 }
 
+// a * b + c rounded once.  The library is compiled without floating-point
+// contraction, so every fused multiply-add is written out: two instances of a
+// kernel (or two kernels) that must give the same bits do the same operations
+// whatever the compiler's scheduling.
+__device__ __forceinline__ double madd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// acc + a * b for an FP64 accumulator: fused when the product is FP64, else
+// the product rounded in the arithmetic type and added in FP64
+__device__ __forceinline__ double dot_acc(double acc, double a, double b) { return __builtin_fma(a, b, acc); }
+__device__ __forceinline__ double dot_acc(double acc, float a, float b) { return acc + static_cast<double>(a * b); }
+
 // --------------------------------------------------------------------------
 // Philox4x32-10: ten rounds of the 4x32 Philox bijection.  Each round takes the
 // 32x32->64 products of words 0 and 2 with two odd multipliers, swaps halves

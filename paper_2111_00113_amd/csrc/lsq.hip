@@ -33,7 +33,7 @@ __device__ void lsq_body(int s, int dc, double* __restrict__ C, double* __restri
     for (int p = 0; p < dc; ++p) {
         double* cp = C + static_cast<int64_t>(p) * s;
         double t = 0.0;
-        for (int i = p + 1 + tid; i < s; i += kLsqBlock) t += cp[i] * cp[i];
+        for (int i = p + 1 + tid; i < s; i += kLsqBlock) t = madd(cp[i], cp[i], t);
         const double vals[1] = {t};
         block_sum<1>(vals, 1, tmp, red);
         if (tid == 0) {
@@ -45,7 +45,7 @@ __device__ void lsq_body(int s, int dc, double* __restrict__ C, double* __restri
                 tau = 0.0;
                 sc = 1.0;
             } else {
-                const double nrm = sqrt(alpha * alpha + xn2);
+                const double nrm = sqrt(madd(alpha, alpha, xn2));
                 beta = (alpha >= 0.0) ? -nrm : nrm;
                 tau = (beta - alpha) / beta;
                 sc = 1.0 / (alpha - beta);
@@ -71,11 +71,11 @@ __device__ void lsq_body(int s, int dc, double* __restrict__ C, double* __restri
             for (int c = p + 1 + wid; c <= dc; c += kLsqWaves) {
                 double* col = (c < dc) ? C + static_cast<int64_t>(c) * s : g;
                 double sd = 0.0;
-                for (int i = p + 1 + lane; i < s; i += kWave) sd += v[i] * col[i];
+                for (int i = p + 1 + lane; i < s; i += kWave) sd = madd(v[i], col[i], sd);
                 sd = wave_sum(sd);
                 const double head = col[p];
                 sd = (head + sd) * tau;
-                for (int i = p + 1 + lane; i < s; i += kWave) col[i] -= sd * v[i];
+                for (int i = p + 1 + lane; i < s; i += kWave) col[i] = madd(-sd, v[i], col[i]);
                 if (lane == 0) col[p] = head - sd;
             }
         }
@@ -125,13 +125,13 @@ __device__ void lsq_body(int s, int dc, double* __restrict__ C, double* __restri
 #pragma unroll
             for (int c = 0; c < kZSlots; ++c) {
                 const int q = lane + c * kWave;
-                if (q < i) z[c] -= tcol[q] * yi;
+                if (q < i) z[c] = madd(-tcol[q], yi, z[c]);
             }
         }
     }
 
     double t = 0.0;
-    for (int i = d_eff + tid; i < s; i += kLsqBlock) t += g[i] * g[i];
+    for (int i = d_eff + tid; i < s; i += kLsqBlock) t = madd(g[i], g[i], t);
     const double vals[1] = {t};
     block_sum<1>(vals, 1, tmp, red);
     if (tid == 0) dout[0] = sqrt(red[0]);
@@ -252,7 +252,7 @@ __device__ __forceinline__ void apply_reflector_cols(double (&col)[CB][S], const
     for (int i = I0; i < CB; ++i) {
         double a = 0.0;
 #pragma unroll
-        for (int q = 0; q < S; ++q) a += v[q] * col[i][q];
+        for (int q = 0; q < S; ++q) a = madd(v[q], col[i][q], a);
         sd[i] = a;
     }
     // interleaved wave sums (the step order of wave_sum)
@@ -272,7 +272,7 @@ __device__ __forceinline__ void apply_reflector_cols(double (&col)[CB][S], const
     for (int i = I0; i < CB; ++i) {
         const double t = readlane_d(sd[i], kWave - 1) * tau;
 #pragma unroll
-        for (int q = 0; q < S; ++q) col[i][q] -= t * v[q];
+        for (int q = 0; q < S; ++q) col[i][q] = madd(-t, v[q], col[i][q]);
     }
 }
 
@@ -301,7 +301,7 @@ __device__ __forceinline__ void factor_held(double (&col)[CB][S], int c0, int dc
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const int r = lane + q * kWave;
-                if (r > c) xl += col[I][q] * col[I][q];
+                if (r > c) xl = madd(col[I][q], col[I][q], xl);
             }
             const double xn2 = wave_sum(xl);
             const double alpha = row_of<S>(col[I], c);
@@ -311,7 +311,7 @@ __device__ __forceinline__ void factor_held(double (&col)[CB][S], int c0, int dc
                 tc = 0.0;
                 sc = 1.0;
             } else {
-                const double nrm = sqrt(alpha * alpha + xn2);
+                const double nrm = sqrt(madd(alpha, alpha, xn2));
                 beta = (alpha >= 0.0) ? -nrm : nrm;
                 tc = (beta - alpha) / beta;
                 sc = 1.0 / (alpha - beta);
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
 #pragma unroll
     for (int q = 0; q < S; ++q) {
         const int r = lane + q * kWave;
-        if (r >= d_eff && r < s) rl += z[q] * z[q];
+        if (r >= d_eff && r < s) rl = madd(z[q], z[q], rl);
     }
     const double rest = sqrt(wave_sum(rl));
     // back substitution T y = z, column-oriented: y_i = z_i (1 / T_ii), the
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
                     const double yi = readlane_d(z[q], i & (kWave - 1)) * readlane_d(rinv[q], i & (kWave - 1));
                     if (lane == 0) y[i] = yi;
 #pragma unroll
-                    for (int qq = 0; qq <= q; ++qq) z[qq] -= tc[u][qq] * yi;
+                    for (int qq = 0; qq <= q; ++qq) z[qq] = madd(-tc[u][qq], yi, z[qq]);
                 }
                 load_tcol(i - kRing, tc[u]);
             }

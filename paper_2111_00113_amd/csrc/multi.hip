@@ -62,11 +62,11 @@ __global__ __launch_bounds__(kMBlock) void residual_multi_kernel(int64_t n, cons
         double t = F[q];
         if (X) {
             double ax = 0.0;
-            for (int e = rp[i]; e < rp[i + 1]; ++e) ax += val[e] * X[static_cast<int64_t>(ci[e]) * NR + rhs];
+            for (int e = rp[i]; e < rp[i + 1]; ++e) ax = madd(val[e], X[static_cast<int64_t>(ci[e]) * NR + rhs], ax);
             t -= ax;
         }
         R[q] = t;
-        acc += t * t;
+        acc = madd(t, t, acc);
     }
     for (int off = NR; off < kWave; off <<= 1) acc += __shfl_xor(acc, off, kWave);
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kMBlock) void combine_multi_kernel(int64_t n, int d
         const double* yr = y + static_cast<int64_t>(r) * d;
         double t = X[q];
         for (int j = 0; j < de; ++j)
-            t += to_d(B[static_cast<int64_t>(j) * ldb + q]) * yr[j];
+            t = madd(to_d(B[static_cast<int64_t>(j) * ldb + q]), yr[j], t);
         X[q] = t;
     }
 }

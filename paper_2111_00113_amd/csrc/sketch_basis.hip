@@ -241,9 +241,9 @@ __global__ __launch_bounds__(256) void relation_kernel(int nr, int d, int k, int
     const int kw = j + 1 < k ? j + 1 : k;
     const double* Hj = H + (static_cast<int64_t>(r) * d + j) * (k + 1);
     double t = 0.0;
-    for (int a = 0; a < kw; ++a) t += Hj[a] * SB[(static_cast<int64_t>(j - a) * nr + r) * s + e];
+    for (int a = 0; a < kw; ++a) t = madd(Hj[a], SB[(static_cast<int64_t>(j - a) * nr + r) * s + e], t);
     const double nu = Hj[k];
-    if (nu != 0.0) t += nu * SB[(static_cast<int64_t>(j + 1) * nr + r) * s + e];
+    if (nu != 0.0) t = madd(nu, SB[(static_cast<int64_t>(j + 1) * nr + r) * s + e], t);
     SAB[q] = t;
 }
 

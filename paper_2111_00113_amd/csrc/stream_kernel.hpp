@@ -234,17 +234,17 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                             } else {
                                 bv = ldB(bj + (static_cast<uint32_t>(c[u]) * NR + rhs));
                             }
-                            m[u] += v[u] * bv;
+                            m[u] = madd(v[u], bv, m[u]);
                         }
                 }
 #pragma unroll
                 for (int u = 0; u < PG; ++u) {
                     const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>((g0 + u) * kBlock + tid);
                     if (q < npairs) {
-                        acc[0] += static_cast<double>(m[u] * m[u]);
+                        acc[0] = dot_acc(acc[0], m[u], m[u]);
                         for (int a = 0; a < kw; ++a) {
                             const TC wa = ldW(a, q, (g0 + u) * kBlock + tid);
-                            acc[1 + a] += static_cast<double>(wa * m[u]);
+                            acc[1 + a] = dot_acc(acc[1 + a], wa, m[u]);
                         }
                     }
                     if constexpr (HST) {
@@ -280,11 +280,11 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                         if (a < kw) wa[a] = ldW(a, q, pp * kBlock + tid);
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
-                        if (a < kw) w -= static_cast<TC>(coefA[(1 + a) * NR + rhs]) * wa[a];
-                    acc[0] += static_cast<double>(w * w);
+                        if (a < kw) w = gs_sub(w, static_cast<TC>(coefA[(1 + a) * NR + rhs]), wa[a]);
+                    acc[0] = dot_acc(acc[0], w, w);
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
-                        if (a < kw) acc[1 + a] += static_cast<double>(wa[a] * w);
+                        if (a < kw) acc[1 + a] = dot_acc(acc[1 + a], wa[a], w);
                     if constexpr (HST) state[q] = w;
                     else mreg[pp] = w;
                 }
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
         tick(4);
         if (tid < NR) {
             double h2sq = 0.0;
-            for (int a = 0; a < kw; ++a) h2sq += coefB[(1 + a) * NR + tid] * coefB[(1 + a) * NR + tid];
+            for (int a = 0; a < kw; ++a) h2sq = madd(coefB[(1 + a) * NR + tid], coefB[(1 + a) * NR + tid], h2sq);
             const double nu2 = coefB[tid] - h2sq;
             const bool brk = !(nu2 > 16.0 * uround * uround * coefA[tid]);
             nus[tid] = brk ? 0.0 : sqrt(nu2);

@@ -30,11 +30,11 @@ __global__ __launch_bounds__(kVecBlock) void residual_kernel(int64_t n, const in
         double ax = 0.0;
         if (x) {
             const int q1 = rp[i + 1];
-            for (int q = rp[i]; q < q1; ++q) ax += val[q] * x[ci[q]];
+            for (int q = rp[i]; q < q1; ++q) ax = madd(val[q], x[ci[q]], ax);
         }
         const double ri = f[i] - ax;
         r[i] = ri;
-        acc += ri * ri;
+        acc = madd(ri, ri, acc);
     }
     const double v[1] = {acc};
     block_sum<1>(v, 1, tmp, out);
@@ -85,9 +85,9 @@ __global__ __launch_bounds__(kCombineBlock) void combine_kernel(int64_t n, const
         for (; c + 8 <= d_eff; c += 8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                acc[u] += from_basis<double>(B[static_cast<int64_t>(c + u) * ldb + i]) * ys[c + u];
+                acc[u] = madd(from_basis<double>(B[static_cast<int64_t>(c + u) * ldb + i]), ys[c + u], acc[u]);
         }
-        for (; c < d_eff; ++c) acc[0] += from_basis<double>(B[static_cast<int64_t>(c) * ldb + i]) * ys[c];
+        for (; c < d_eff; ++c) acc[0] = madd(from_basis<double>(B[static_cast<int64_t>(c) * ldb + i]), ys[c], acc[0]);
         const double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         x[i] += sum;
     }
@@ -164,9 +164,9 @@ __global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, cons
         const int64_t i = 4 * nq + threadIdx.x;
         double a0 = 0.0, a1 = 0.0;
         for (int c = 0; c < d_eff; ++c) {
-            const double v = from_basis<double>(B[static_cast<int64_t>(c) * ldb + i]) * ys[c];
-            if (c & 1) a1 += v;
-            else a0 += v;
+            const double b = from_basis<double>(B[static_cast<int64_t>(c) * ldb + i]);
+            if (c & 1) a1 = madd(b, ys[c], a1);
+            else a0 = madd(b, ys[c], a0);
         }
         x[i] += a0 + a1;
     }
