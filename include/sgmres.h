@@ -343,14 +343,20 @@ typedef struct {
  * them (SGMRES_PATH_STREAM; s <= 1024); opts->path = SGMRES_PATH_PART_SPLIT
  * keeps them on the per-system kernels.  Other systems of at least 2^19 rows
  * fill the chip alone: they are solved one after another by the resident
- * kernels of sgmres_solve_ex.  The rest run together, one persistent launch per cycle,
- * each split into parts of at most 16384 rows taken by workgroups from a queue;
- * each cycle's kernels are replayed from a captured hipGraph.  opts: zeta,
- * kappa_max, precision (mixed precision
- * with FP64 refinement as in sgmres_solve_ex), block_size / rows_per_thread
+ * kernels of sgmres_solve_ex.  The rest (SGMRES_PATH_MULTI, the default) run
+ * several to a resident truncated-Arnoldi launch, each on its own group of
+ * ceil(n / (1024 * rows_per_thread)) workgroups (rows_per_thread 2 or 4,
+ * default 4), packed largest first into launches that fit the chip; a system
+ * gets what sgmres_solve_ex gives it with that launch shape.  With opts->path
+ * = SGMRES_PATH_PART_SPLIT they run instead one persistent launch per cycle
+ * of the part-split kernel, each split into parts of at most 16384 rows taken
+ * by workgroups from a queue, each cycle's kernels replayed from a captured
+ * hipGraph.  opts: zeta, kappa_max, precision (mixed precision with FP64
+ * refinement as in sgmres_solve_ex), path, rows_per_thread (multi-system
+ * launches: 2 or 4); for the part-split kernel block_size / rows_per_thread
  * (0 = 512 x 4 for batches under 2^20 rows, else chosen by timing the first
- * cycle of each candidate; the choice is kept
- * per problem class), batch_eager, path; other fields are ignored.
+ * cycle of each candidate; the choice is kept per problem class) and
+ * batch_eager; other fields are ignored.
  *   nsys     number of systems (0 returns SGMRES_OK)
  *   systems  host array of nsys systems; every n >= d, 1 <= k <= 4
  *   results  host array of nsys results, may be NULL
