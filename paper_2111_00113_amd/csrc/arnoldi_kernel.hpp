@@ -70,8 +70,10 @@ __device__ __forceinline__ float gs_sub(float x, float h, float v) { return __bu
 //     words; measured slower: 9.84 -> 9.21 solves/s at n = 2^20.)
 // Chosen when few nonzeros reach outside their block (requires SKB = false).
 // One cycle of one system on the G blocks of its grid (or group of blocks);
-// blk: this block's logical index among them.
-template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO>
+// blk: this block's logical index among them.  LOOK: the three-barrier SpMV
+// loads the next slot's columns ahead (the multi-system instances, at their
+// register limit, do without: measured slower with it).
+template <int R, int KW, int BLOCK, bool SKB, typename TC, typename TS, bool HALO, bool LOOK = true>
 __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G, const int blk) {
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
@@ -381,19 +383,32 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                 }
             }
         } else {
+            // with LOOK, slot q + 1's columns are loaded while slot q's values
+            // and gathers are in flight, so each slot waits for one round trip
+            // (its gathers need its columns) instead of two (rd1m FP64:
+            // 6.77 -> 6.25 ms per launch)
+            int c[R], cn[R];
+            auto load_cols = [&](int q, int (&cd)[R]) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cd[r] = 0;
+                    if (q < sK[r]) cd[r] = p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane];
+                }
+            };
+            if constexpr (LOOK) load_cols(0, c);
             for (int q = 0; q < kmax; ++q) {
-                int c[R];
                 TC v[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    c[r] = 0;
+                    if constexpr (!LOOK) c[r] = 0;
                     v[r] = TC(0);
                     if (q < sK[r]) {
                         const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave + lane;
-                        c[r] = p.ci[e];
+                        if constexpr (!LOOK) c[r] = p.ci[e];
                         v[r] = Av[e];
                     }
                 }
+                if constexpr (LOOK) load_cols(q + 1, cn);
                 // own rows of b_j were stored by this block; other blocks' rows
                 // as described at ldB (the per-step barriers take no acquire)
 #pragma unroll
@@ -403,6 +418,10 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                         const TS bv = (cc >= row_lo && cc < row_hi) ? bj[cc] : ldB(bj + cc);
                         m[r] = madd(v[r], from_basis<TC>(bv), m[r]);
                     }
+                if constexpr (LOOK) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) c[r] = cn[r];
+                }
             }
         }
         // the first reduction of the step goes through tagged partials (tag
@@ -613,7 +632,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_multi_kernel(const ArnoldiParam
     const int g = __builtin_amdgcn_readfirstlane(grp[lb]);
     if (g < 0) return;
     const ArnoldiParams& p = ps[g];
-    arnoldi_body<R, KW, BLOCK, false, TC, TS, false>(p, p.G, lb - p.blk0);
+    arnoldi_body<R, KW, BLOCK, false, TC, TS, false, false>(p, p.G, lb - p.blk0);
 }
 
 // Kernel instance for (BLOCK, R, KW); (R, KW) = (8, 8) is never selected
