@@ -146,9 +146,9 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
         }
     }
 
-    // HALO, publishing: bit r set when own row r is gathered by another block
+    // HALO: bit r set when own row r is gathered by another block
     unsigned xmask = 0;
-    if constexpr (HALO && kPub) {
+    if constexpr (HALO) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
@@ -477,10 +477,11 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
             }
         }
         if constexpr (HALO && !kPub) {
+            // only the rows other blocks gather
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
-                if (row < n) store_stream(wbuf + row, w[r]);
+                if ((xmask >> r) & 1u) store_stream(wbuf + row, w[r]);
             }
         }
         // tagged as well: the second barrier still orders w and the basis
