@@ -104,6 +104,7 @@ typedef struct {
     int32_t launch_grid;
     double t_sketch_ms; /* streaming path: sketch of the finished basis, S A B = (S B) H
                            and g = S r (profile only; included in t_basis_ms) */
+    double cheb_box[3]; /* Chebyshev basis: the box (c, dx, dy) used, given or estimated */
 } sgmres_info_t;
 
 #define SGMRES_PATH_ARNOLDI_3BAR 1 /* resident truncated Arnoldi, three grid barriers per step */
@@ -134,7 +135,9 @@ typedef struct {
     int32_t basis;      /* SGMRES_BASIS_ARNOLDI (default) or SGMRES_BASIS_CHEBYSHEV */
     double cheb_c;      /* Chebyshev basis: the spectrum of A lies in the box */
     double cheb_dx;     /* [cheb_c - cheb_dx, cheb_c + cheb_dx] x [-cheb_dy, cheb_dy] */
-    double cheb_dy;     /* (Section 4.4); dx, dy >= 0, max(dx, dy) > 0; k is unused */
+    double cheb_dy;     /* (Section 4.4); dx, dy >= 0; k is unused.  dx = dy = 0: the box is
+                           estimated from a short Arnoldi pass on b (sgmres_chebyshev_box);
+                           not for transposed solves without a plan */
     int32_t precision;  /* SGMRES_PREC_* (0 = FP64) */
     int32_t batch_eager; /* sgmres_solve_batched: launch each cycle's kernels directly
                             instead of replaying the captured hipGraph */
@@ -370,6 +373,40 @@ int sgmres_solve_batched(int nsys, const sgmres_system_t *systems, int d, int k,
 
 /* Frees the cached workspace of every device. */
 void sgmres_release_workspace(void);
+
+/*
+ * Spectral box for the Chebyshev basis from a short Arnoldi pass (Section 4.4:
+ * a few Arnoldi iterations estimate the spectrum of A, and the shifted and
+ * scaled Chebyshev polynomials are fitted to a region containing it).  Runs
+ * m + 1 steps of Arnoldi with a full window (two classical Gram-Schmidt
+ * passes, FP64) from r on the device, takes the Ritz values (eigenvalues of
+ * the leading m x m block of the Hessenberg matrix, computed on the host; the
+ * leading dc x dc block when the Krylov space of r is invariant after dc
+ * columns) and returns their bounding rectangle with both half-widths widened
+ * by 10%.  sgmres_solve_ex does this with m = min(20, d, n - 1) and r = b when
+ * the Chebyshev basis is asked for with cheb_dx = cheb_dy = 0.
+ *   A      device CSR, n > m
+ *   r      n device vector (r = 0 gives the box (0, 1, 0) and no Ritz values)
+ *   m      1 <= m <= 64
+ *   box    host, 3 doubles out: c, dx, dy
+ *   ritz   host, 2m doubles out (nullable): real parts, then imaginary parts
+ *   nritz  host out (nullable): Ritz values returned
+ * Synchronises the stream.  Returns SGMRES_OK, SGMRES_EINVAL, SGMRES_ECSR,
+ * SGMRES_ENONFINITE (non-finite r or Hessenberg entries) or SGMRES_ETIMEOUT.
+ */
+int sgmres_chebyshev_box(const sgmres_csr_t *A, const double *r, int m, double *box, double *ritz, int *nritz,
+                         void *stream);
+
+/*
+ * Eigenvalues of an m x m upper Hessenberg matrix (host memory, column-major,
+ * leading dimension ldh; entries below the subdiagonal are ignored; H is not
+ * modified) by the implicitly double-shifted QR iteration: the step that
+ * sgmres_chebyshev_box applies to the Arnoldi Hessenberg matrix.  wr, wi: m
+ * doubles out (real and imaginary parts; a complex pair is stored
+ * consecutively).  Host code only, no device.  Returns SGMRES_OK, or
+ * SGMRES_EINVAL for bad sizes or when the iteration does not converge.
+ */
+int sgmres_hessenberg_eigenvalues(int m, const double *H, int ldh, double *wr, double *wi);
 
 /* Library version string (static storage). */
 const char *sgmres_version(void);

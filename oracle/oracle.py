@@ -17,7 +17,8 @@ __all__ = [
     "philox4x32_10", "sketch_pattern", "sketch_apply", "sketch_dense", "csr_spmv",
     "csr_transpose", "residual", "arnoldi_cycle", "sketched_lsq", "basis_combine",
     "sgmres_solve", "sgmres_solve_transposed", "dense_solve_gradient", "lib",
-    "chebyshev_cycle", "sgmres_solve_chebyshev", "set_threads", "get_threads",
+    "chebyshev_cycle", "sgmres_solve_chebyshev", "set_threads", "get_threads", "ritz_values",
+    "chebyshev_box",
 ]
 
 OK = 0
@@ -289,6 +290,37 @@ def sgmres_solve_chebyshev(A, b, box, x0=None, d=40, s=None, zeta=8, seed=0, tol
         cycles=int(info[0]), steps=int(info[1]), d_eff_last=int(info[2]), flags=int(info[3]),
         relres=float(info[4]), rest_est=float(info[5]), kappa_est=float(info[6]),
     )
+
+
+def ritz_values(A, r, m: int):
+    """Ritz values of an m-step Arnoldi process on A from r (Section 4.4: a few
+    Arnoldi iterations estimate the spectrum): m + 1 steps of the oracle's
+    Arnoldi with a full window, the leading m x m block of its Hessenberg
+    matrix (the leading dc x dc block when the basis stops at dc columns), and
+    that block's eigenvalues (numpy's dense eigenvalue routine)."""
+    d, k = m + 1, m
+    s = max(d + 1, 16)
+    out = arnoldi_cycle(A, r, d=d, k=k, s=s, zeta=8, seed=0, cycle=0)
+    H = out["H"]  # (k + 1) x d: H[a, j] = coefficient of window entry a (newest first), H[k, j] = nu_j
+    me = min(m, int(out["dc"]))
+    Hm = np.zeros((me, me))
+    for j in range(me):
+        for a in range(j + 1):
+            Hm[j - a, j] = H[a, j]
+        if j + 1 < me:
+            Hm[j + 1, j] = H[k, j]
+    return np.linalg.eigvals(Hm)
+
+
+def chebyshev_box(A, r, m: int, margin: float = 0.1):
+    """The spectral box (c, dx, dy) for the Chebyshev basis from the Ritz values
+    of ritz_values(A, r, m): their bounding rectangle [c +- dx] x [+-dy], both
+    half-widths widened by the fraction margin (a reading: the paper leaves the
+    fit of the region to the estimated spectrum open)."""
+    th = ritz_values(A, r, m)
+    xmin, xmax = float(th.real.min()), float(th.real.max())
+    ymax = float(np.abs(th.imag).max())
+    return 0.5 * (xmin + xmax), (1.0 + margin) * 0.5 * (xmax - xmin), (1.0 + margin) * ymax
 
 
 def sgmres_solve_transposed(A, b, x0=None, d=40, k=2, s=None, zeta=8, seed=0, tol=1e-10,

@@ -36,6 +36,8 @@ from .sgmres import (  # noqa: F401
     sgmres_residual,
     sgmres_arnoldi_cycle,
     sgmres_chebyshev_cycle,
+    sgmres_chebyshev_box,
+    hessenberg_eigenvalues,
     sgmres_sketched_lsq,
     sgmres_basis_combine,
     sgmres_csr_transpose,

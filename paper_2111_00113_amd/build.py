@@ -37,7 +37,7 @@ CFLAGS = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
-SOURCES = ["sell.hip", "arnoldi.hip", "arnoldi_sb.hip", "arnoldi_f32.hip", "arnoldi_bf16.hip", "arnoldi_halo_f64.hip", "arnoldi_halo_f32.hip", "arnoldi_halo_bf16.hip", "arnoldi_multi.hip", "batched.hip", "capi.hip", "chebyshev.hip", "lsq.hip", "multi.hip", "sketch.hip", "sketch_basis.hip", "stream.hip", "transpose.hip", "vec.hip"]
+SOURCES = ["sell.hip", "arnoldi.hip", "arnoldi_sb.hip", "arnoldi_f32.hip", "arnoldi_bf16.hip", "arnoldi_halo_f64.hip", "arnoldi_halo_f32.hip", "arnoldi_halo_bf16.hip", "arnoldi_multi.hip", "batched.hip", "box.hip", "capi.hip", "chebyshev.hip", "lsq.hip", "multi.hip", "sketch.hip", "sketch_basis.hip", "stream.hip", "transpose.hip", "vec.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

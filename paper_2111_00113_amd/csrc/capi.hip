@@ -802,6 +802,11 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     if (rc) return rc;
     const double nf = ws.host_sc->nf;
     sgmres_info_t rep{};
+    if (cheb) {
+        rep.cheb_box[0] = a.cheb_c;
+        rep.cheb_box[1] = a.cheb_dx;
+        rep.cheb_box[2] = a.cheb_dy;
+    }
     if (!std::isfinite(nf)) return SGMRES_ENONFINITE;
     if (nf == 0.0) {
         SG_TRY(launch_fill(a.x, n, 0.0, st));
@@ -884,6 +889,82 @@ int solve_impl(const SolveArgs& a, sgmres_info_t* info) {
     return status;
 }
 
+constexpr int kBoxSteps = 20;       // Arnoldi steps of the automatic box estimate
+constexpr double kBoxMargin = 0.1;  // widening of the Ritz values' half-widths
+
+// Spectral box (c, dx, dy) of A for the Chebyshev basis (Section 4.4: a few
+// Arnoldi iterations estimate the spectrum): m + 1 steps of Arnoldi with a
+// full window from r (the resident basis kernel, FP64, two Gram-Schmidt
+// passes), the Ritz values (eigenvalues of the leading m x m block of the
+// Hessenberg matrix; of the leading dc x dc block when the Krylov space is
+// invariant after dc columns) and their bounding rectangle, half-widths
+// widened by kBoxMargin.  ritz (nullable, 2m): real parts, then imaginary
+// parts; *mr: Ritz values found.  Caller holds g_mutex.
+int cheb_box_locked(Workspace& ws, const sgmres_csr_t& A, const double* r, int m, double box[3], double* ritz,
+                    int* mr, hipStream_t st) {
+    const int64_t n = A.n;
+    if (m < 1 || m > 64 || m >= n) return SGMRES_EINVAL;
+    const int d = m + 1, k = m, zeta = 8;
+    const int s = d + 1 > 2 * zeta ? d + 1 : 2 * zeta;
+    ArnoldiLaunch L{};
+    int rc = prepare_arnoldi(ws, n, d, k, s, zeta, 0, 0, &L, 0);
+    if (rc) return rc;
+    const int64_t ldb = (n + 127) / 128 * 128;
+    SG_TRY(ensure(ws.r, ws.r_cap, static_cast<size_t>(n)));
+    SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
+    SG_TRY(ensure(ws.B, ws.B_cap, static_cast<size_t>(ldb) * d));
+    SG_TRY(ensure(ws.SB, ws.SB_cap, static_cast<size_t>(s) * d));
+    SG_TRY(ensure(ws.SAB, ws.SAB_cap, static_cast<size_t>(s) * d));
+    SG_TRY(ensure(ws.H, ws.H_cap, static_cast<size_t>(k + 1) * d));
+    SG_TRY(ensure(ws.g, ws.g_cap, static_cast<size_t>(s)));
+    rc = check_csr(ws, A, st);
+    if (rc) return rc;
+    rc = build_sell(ws, A, SGMRES_PREC_FP64, st);
+    if (rc) return rc;
+    SG_TRY(hipMemsetAsync(&ws.sc->dc, 0, 5 * sizeof(int), st));
+    SG_TRY(launch_residual(n, nullptr, nullptr, nullptr, r, nullptr, ws.r, ws.part_vec, st));
+    SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(n), &ws.sc->beta, nullptr, st));
+    SG_TRY(launch_fill(ws.H, static_cast<int64_t>(k + 1) * d, 0.0, st));
+    rc = run_cycle(ws, A, d, k, s, zeta, 0, 0, L, ws.B, ldb, ws.SB, ws.SAB, ws.H, ws.g, st);
+    if (rc) return rc;
+    std::vector<double> Hh(static_cast<size_t>(k + 1) * d);
+    SG_TRY(hipMemcpyAsync(Hh.data(), ws.H, sizeof(double) * Hh.size(), hipMemcpyDeviceToHost, st));
+    rc = copy_scalars(ws, st);
+    if (rc) return rc;
+    if (ws.host_sc->abort) return SGMRES_ETIMEOUT;
+    if (!std::isfinite(ws.host_sc->beta)) return SGMRES_ENONFINITE;
+    if (ws.host_sc->beta == 0.0) {  // r = 0: no Krylov space; a valid box, no Ritz values
+        box[0] = 0.0;
+        box[1] = 1.0;
+        box[2] = 0.0;
+        if (mr) *mr = 0;
+        return SGMRES_OK;
+    }
+    const int me = ws.host_sc->dc < m ? ws.host_sc->dc : m;
+    if (me < 1) return SGMRES_EINVAL;
+    // leading me x me block, column-major: column j holds h_a = H[j (k+1) + a]
+    // in row j - a (window entry a, newest first) and nu_j = H[j (k+1) + k]
+    // below the diagonal
+    std::vector<double> Hm(static_cast<size_t>(me) * me, 0.0), wr(me), wi(me);
+    for (int j = 0; j < me; ++j) {
+        for (int a = 0; a <= j; ++a) Hm[(j - a) + static_cast<size_t>(j) * me] = Hh[static_cast<size_t>(j) * (k + 1) + a];
+        if (j + 1 < me) Hm[(j + 1) + static_cast<size_t>(j) * me] = Hh[static_cast<size_t>(j) * (k + 1) + k];
+    }
+    for (double v : Hm)
+        if (!std::isfinite(v)) return SGMRES_ENONFINITE;
+    if (hessenberg_eigenvalues(me, Hm.data(), me, wr.data(), wi.data()) != 0) return SGMRES_EINVAL;
+    box_from_ritz(me, wr.data(), wi.data(), kBoxMargin, box);
+    // a single point (A a multiple of I on the Krylov space): keep rho > 0
+    if (!(box[1] > 0.0) && !(box[2] > 0.0)) box[1] = std::fabs(box[0]) > 0.0 ? 1e-8 * std::fabs(box[0]) : 1e-8;
+    if (ritz)
+        for (int i = 0; i < me; ++i) {
+            ritz[i] = wr[i];
+            ritz[m + i] = wi[i];
+        }
+    if (mr) *mr = me;
+    return SGMRES_OK;
+}
+
 int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k, int s, uint64_t seed,
                 double tol, int restarts, const sgmres_options_t* opts, sgmres_info_t* info, void* stream,
                 const Plan* plan = nullptr) {
@@ -927,14 +1008,33 @@ int solve_entry(const sgmres_csr_t* A, const double* b, double* x, int d, int k,
     if (a.precision != SGMRES_PREC_FP64 && a.precision != SGMRES_PREC_FP32 && a.precision != SGMRES_PREC_BF16_BASIS)
         return SGMRES_EINVAL;
     if (a.basis != SGMRES_BASIS_ARNOLDI && a.basis != SGMRES_BASIS_CHEBYSHEV) return SGMRES_EINVAL;
+    a.stream = static_cast<hipStream_t>(stream);
     if (a.basis == SGMRES_BASIS_CHEBYSHEV) {
-        ChebCoef cf{};
-        if (!cheb_coefficients(opts->cheb_c, opts->cheb_dx, opts->cheb_dy, &cf)) return SGMRES_EINVAL;
         a.cheb_c = opts->cheb_c;
         a.cheb_dx = opts->cheb_dx;
         a.cheb_dy = opts->cheb_dy;
+        if (a.cheb_dx == 0.0 && a.cheb_dy == 0.0) {
+            // no box given: estimate it from b (transposed solves and plans
+            // estimate it for the matrix they solve with)
+            double box[3];
+            const int m = std::min<int64_t>(std::min(kBoxSteps, d), A->n - 1);
+            const bool t = opts->transposed != 0;
+            const sgmres_csr_t* M = A;
+            if (t && plan) M = &plan->At;
+            if (t && !plan) return SGMRES_EINVAL;  // the box of A^T: pass it, or use a plan with A^T
+            std::lock_guard<std::mutex> lock(g_mutex);
+            Workspace* wsp = nullptr;
+            int rc = workspace(&wsp);
+            if (rc) return rc;
+            rc = cheb_box_locked(*wsp, *M, b, m, box, nullptr, nullptr, a.stream);
+            if (rc) return rc;
+            a.cheb_c = box[0];
+            a.cheb_dx = box[1];
+            a.cheb_dy = box[2];
+        }
+        ChebCoef cf{};
+        if (!cheb_coefficients(a.cheb_c, a.cheb_dx, a.cheb_dy, &cf)) return SGMRES_EINVAL;
     }
-    a.stream = static_cast<hipStream_t>(stream);
     if (plan) {
         a.plan = plan;
         a.plan_t = (opts && opts->transposed) ? 1 : 0;
@@ -2200,6 +2300,24 @@ int sgmres_solve_batched(int nsys, const sgmres_system_t* systems, int d, int k,
     if (results)
         for (size_t q = 0; q < small.size(); ++q) results[small[q]] = sres[q];
     return all;
+}
+
+int sgmres_chebyshev_box(const sgmres_csr_t* A, const double* r, int m, double* box, double* ritz, int* nritz,
+                         void* stream) {
+    if (!csr_ok(A) || !r || !box) return SGMRES_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace* wsp = nullptr;
+    int rc = workspace(&wsp);
+    if (rc) return rc;
+    return cheb_box_locked(*wsp, *A, r, m, box, ritz, nritz, static_cast<hipStream_t>(stream));
+}
+
+int sgmres_hessenberg_eigenvalues(int m, const double* H, int ldh, double* wr, double* wi) {
+    if (m < 1 || ldh < m || !H || !wr || !wi) return SGMRES_EINVAL;
+    std::vector<double> work(static_cast<size_t>(m) * m);
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) work[i + static_cast<size_t>(j) * m] = H[i + static_cast<size_t>(j) * ldh];
+    return hessenberg_eigenvalues(m, work.data(), m, wr, wi) == 0 ? SGMRES_OK : SGMRES_EINVAL;
 }
 
 const char* sgmres_version(void) { return "sgmres-gfx950 0.1.0"; }

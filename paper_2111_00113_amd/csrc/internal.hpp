@@ -70,6 +70,10 @@ __host__ __device__ constexpr int arnoldi_vals_doubles(int RB, int zeta) {
 }
 
 size_t arnoldi_lds_bytes(int block, int R, int s, int k, int zeta);
+
+// ---- Chebyshev box from a short Arnoldi pass (box.hip, host) ---------------
+int hessenberg_eigenvalues(int m, double* H, int ldh, double* wr, double* wi);
+void box_from_ritz(int m, const double* wr, const double* wi, double margin, double box[3]);
 // ---- several systems per basis launch (arnoldi_multi.hip) ------------------
 constexpr int kMultiBlock = 1024;  // threads per workgroup
 constexpr int kMultiMaxK = 4;      // register window of the instances

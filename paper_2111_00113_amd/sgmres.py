@@ -12,6 +12,8 @@ import ctypes
 import dataclasses
 import os
 
+import numpy as np
+
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +80,7 @@ class _Info(ctypes.Structure):
         ("launch_rows", ctypes.c_int32),
         ("launch_grid", ctypes.c_int32),
         ("t_sketch_ms", ctypes.c_double),
+        ("cheb_box", ctypes.c_double * 3),
     ]
 
 
@@ -138,6 +141,8 @@ def lib():
     L.sgmres_sketch_apply.argtypes = [i64, vp, u64, u32, i32, i32, vp, vp]
     L.sgmres_sketch_apply_noalloc.argtypes = [i64, vp, u64, u32, i32, i32, vp, vp]
     L.sgmres_residual.argtypes = [P(_CSR), vp, vp, vp, P(dbl), vp]
+    L.sgmres_chebyshev_box.argtypes = [P(_CSR), vp, i32, vp, vp, P(i32), vp]
+    L.sgmres_hessenberg_eigenvalues.argtypes = [i32, vp, i32, vp, vp]
     L.sgmres_arnoldi_cycle.argtypes = [P(_CSR), vp, i32, i32, i32, i32, u64, u32, vp, i64, vp, vp, vp, vp,
                                        P(i32), P(i32), vp]
     L.sgmres_solve_batched.argtypes = [i32, P(_System), i32, i32, i32, u64, dbl, i32, P(_Options),
@@ -224,7 +229,8 @@ def _info(i: _Info) -> dict:
                 rest_est=i.rest_est, kappa_est=i.kappa_est, t_residual_ms=i.t_residual_ms,
                 t_basis_ms=i.t_basis_ms, t_lsq_ms=i.t_lsq_ms, t_combine_ms=i.t_combine_ms,
                 phase_us=list(i.phase_us), path=i.path, launch_block=i.launch_block,
-                launch_rows=i.launch_rows, launch_grid=i.launch_grid, t_sketch_ms=i.t_sketch_ms)
+                launch_rows=i.launch_rows, launch_grid=i.launch_grid, t_sketch_ms=i.t_sketch_ms,
+                cheb_box=tuple(i.cheb_box))
 
 
 def _raise(fn, rc):
@@ -240,8 +246,10 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     """Restarted sGMRES on A x = b (or A^T x = b); x is updated in place.
 
     cheb_box=(c, dx, dy) selects the Chebyshev basis for a spectrum inside
-    [c - dx, c + dx] x [-dy, dy] (k is then unused); None selects k-truncated
-    Arnoldi.  precision: "fp64", "fp32" (basis cycles in FP32) or "bf16" (FP32
+    [c - dx, c + dx] x [-dy, dy] (k is then unused), cheb_box="auto" the
+    Chebyshev basis with the box estimated from a short Arnoldi pass on b
+    (sgmres_chebyshev_box; reported in info["cheb_box"]); None selects
+    k-truncated Arnoldi.  precision: "fp64", "fp32" (basis cycles in FP32) or "bf16" (FP32
     arithmetic, basis stored in bfloat16); the residual, least squares and x stay
     FP64, so restarting refines to FP64 accuracy.  halo_off=True keeps three grid
     barriers per truncated-Arnoldi step (the default uses two when few
@@ -256,6 +264,10 @@ def sgmres_solve(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, *
     _check_dev(b, torch.float64, n)
     _check_dev(x, torch.float64, n)
     info = _Info()
+    if isinstance(cheb_box, str):
+        if cheb_box != "auto":
+            raise ValueError("cheb_box: (c, dx, dy), 'auto' or None")
+        cheb_box = (0.0, 0.0, 0.0)
     basis, (cc, cdx, cdy) = (0, (0.0, 0.0, 0.0)) if cheb_box is None else (1, tuple(float(t) for t in cheb_box))
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     opts = _Options(zeta, kappa_max, 1 if transposed else 0, block_size, rows_per_thread, 1 if profile else 0,
@@ -339,6 +351,35 @@ def sgmres_solve_batched(systems, d, k, s, seed=0, tol=1e-10, restarts=100, *, z
     out = [dict(status=r.status, cycles=r.cycles, steps=r.steps, flags=r.flags, relres=r.relres)
            for r in res[: len(systems)]]
     return rc, out
+
+
+def sgmres_chebyshev_box(A: DeviceCSR, r, m=20, stream=None):
+    """Spectral box (c, dx, dy) for the Chebyshev basis from m + 1 Arnoldi
+    steps on r (Section 4.4), and the Ritz values it is built from (a complex
+    numpy array; shorter than m when the Krylov space of r is invariant)."""
+    _check_dev(r, torch.float64, A.n)
+    box = (ctypes.c_double * 3)()
+    ritz = (ctypes.c_double * (2 * max(m, 1)))()
+    nr = ctypes.c_int(0)
+    rc = lib().sgmres_chebyshev_box(ctypes.byref(A._c()), r.data_ptr(), m, box, ritz, ctypes.byref(nr),
+                                    _stream(stream))
+    _raise("sgmres_chebyshev_box", rc)
+    k = nr.value
+    return (box[0], box[1], box[2]), np.array(ritz[:k]) + 1j * np.array(ritz[m:m + k])
+
+
+def hessenberg_eigenvalues(H):
+    """Eigenvalues of an upper Hessenberg matrix (host numpy array) by the
+    library's double-shift QR iteration (entries below the subdiagonal are
+    ignored)."""
+    H = np.asfortranarray(np.asarray(H, dtype=np.float64))
+    m = H.shape[0]
+    if H.ndim != 2 or H.shape[1] != m:
+        raise ValueError("H must be square")
+    wr, wi = np.zeros(m), np.zeros(m)
+    rc = lib().sgmres_hessenberg_eigenvalues(m, H.ctypes.data, m, wr.ctypes.data, wi.ctypes.data)
+    _raise("sgmres_hessenberg_eigenvalues", rc)
+    return wr + 1j * wi
 
 
 def sgmres_solve_transposed(A: DeviceCSR, b, x, d, k, s, seed=0, tol=1e-10, restarts=100, stream=None):

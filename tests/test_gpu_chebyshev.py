@@ -160,13 +160,99 @@ def test_chebyshev_rejects_bad_box(sg):
     A = synth.convection_diffusion(10)
     dA = sg.DeviceCSR.from_host(A)
     f = _t(synth.rhs(A.n))
+    # (dx, dy) = (0, 0) asks the solve to estimate the box (see below); the
+    # cycle entry point, which takes the box as given, rejects it
     for box in [(4.0, 0.0, 0.0), (4.0, -1.0, 0.0), (float("nan"), 1.0, 0.0), (4.0, float("inf"), 0.0)]:
-        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
-        with pytest.raises(sg.SGMRESError) as e:
-            sg.sgmres_solve(dA, f, x, 10, 1, 22, cheb_box=box)
-        assert e.value.rc == -1
+        if box[1] != 0.0:
+            x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+            with pytest.raises(sg.SGMRESError) as e:
+                sg.sgmres_solve(dA, f, x, 10, 1, 22, cheb_box=box)
+            assert e.value.rc == -1
         with pytest.raises(sg.SGMRESError):
             sg.sgmres_chebyshev_cycle(dA, f, 4, 10, *box)
+
+
+# ---------------------------------------------------------------- box estimate
+def _nearest_gap(a, b):
+    return max(min(abs(x - y) for x in a) for y in b)
+
+
+def test_box_estimate_matches_oracle(sg, orc):
+    """m + 1 Arnoldi steps on the GPU (full window, two Gram-Schmidt passes)
+    against the oracle's: the same Ritz values to rounding, the same box."""
+    for N, beta, m in [(64, (10.0, 10.0), 20), (50, (50.0, 20.0), 12), (40, (0.0, 0.0), 30)]:
+        A = synth.convection_diffusion(N, beta)
+        f = synth.rhs(A.n, 2)
+        box, ritz = sg.sgmres_chebyshev_box(sg.DeviceCSR.from_host(A), _t(f), m)
+        th = orc.ritz_values(A, f, m)
+        box_o = orc.chebyshev_box(A, f, m)
+        scale = np.abs(th).max()
+        print(f"cd{N} beta={beta} m={m}: box {box}, oracle {box_o}", flush=True)
+        assert len(ritz) == len(th) == m
+        assert _nearest_gap(ritz, th) <= 1e-8 * scale and _nearest_gap(th, ritz) <= 1e-8 * scale
+        assert np.allclose(box, box_o, rtol=1e-8, atol=1e-10 * scale)
+
+
+def test_box_estimate_invariant_subspace(sg):
+    # A = diag(A1, A2), r supported on A1's rows: the basis stops after q
+    # columns and the Ritz values are eig(A1) (numpy on the dense block)
+    import scipy.sparse as sps
+
+    rng = np.random.default_rng(3)
+    q, n = 7, 40
+    A1 = rng.standard_normal((q, q)) + 3.0 * np.eye(q)
+    Ad = np.zeros((n, n))
+    Ad[:q, :q] = A1
+    Ad[q:, q:] = rng.standard_normal((n - q, n - q))
+    M = sps.csr_matrix(Ad)
+    A = synth.CSR(n=n, row_ptr=M.indptr.astype(np.int32), col_idx=M.indices.astype(np.int32),
+                  val=M.data.astype(np.float64))
+    r = np.zeros(n)
+    r[:q] = rng.standard_normal(q)
+    box, ritz = sg.sgmres_chebyshev_box(sg.DeviceCSR.from_host(A), _t(r), 12)
+    ev = np.linalg.eigvals(A1)
+    assert len(ritz) == q
+    assert _nearest_gap(ritz, ev) <= 1e-10 * np.abs(ev).max()
+    assert np.all(np.abs(ev.real - box[0]) <= box[1]) and np.all(np.abs(ev.imag) <= box[2])
+
+
+def test_box_estimate_edge_cases(sg):
+    A = synth.convection_diffusion(12)
+    dA = sg.DeviceCSR.from_host(A)
+    z = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    box, ritz = sg.sgmres_chebyshev_box(dA, z, 5)  # r = 0: a valid box, no Ritz values
+    assert box == (0.0, 1.0, 0.0) and len(ritz) == 0
+    f = _t(synth.rhs(A.n, 1))
+    for m in (0, 65, A.n):
+        with pytest.raises(sg.SGMRESError):
+            sg.sgmres_chebyshev_box(dA, f, m)
+    bad = f.clone()
+    bad[3] = float("nan")
+    with pytest.raises(sg.SGMRESError):
+        sg.sgmres_chebyshev_box(dA, bad, 5)
+
+
+def test_chebyshev_solve_with_estimated_box(sg, orc):
+    """cheb_box="auto": the solve estimates the box from b with
+    m = min(20, d, n - 1) (the same box sgmres_chebyshev_box returns, bit for
+    bit), and converges like the oracle's Chebyshev solve with the oracle's
+    estimate of the box."""
+    A = synth.convection_diffusion(96, (50.0, 20.0))
+    f = synth.rhs(A.n, 0)
+    dA = sg.DeviceCSR.from_host(A)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    rc, info = sg.sgmres_solve(dA, _t(f), x, 60, 1, 130, 0, 1e-10, 500, cheb_box="auto")
+    box, _ = sg.sgmres_chebyshev_box(dA, _t(f), 20)
+    assert info["path"] == sg.PATH_CHEBYSHEV and tuple(info["cheb_box"]) == box
+    box_o = orc.chebyshev_box(A, f, 20)
+    rc_o, x_o, info_o = orc.sgmres_solve_chebyshev(A, f, box_o, d=60, s=130, zeta=8, seed=0, tol=1e-10,
+                                                   restarts=500)
+    _, nrm = orc.residual(A, f, _np(x))
+    print(f"estimated box {box} (oracle {box_o}); cycles {info['cycles']} (oracle {info_o['cycles']}, "
+          f"given box (4, 4, 0): see test_chebyshev_restarted_solve)", flush=True)
+    assert rc == sg.OK and rc_o == orc.OK
+    assert nrm / np.linalg.norm(f) <= 1e-10
+    assert abs(info["cycles"] - info_o["cycles"]) <= max(1, info_o["cycles"] // 10)
 
 
 def test_chebyshev_full_size_first_steps_parity(sg, orc):
