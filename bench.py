@@ -37,8 +37,8 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "arnoldi": {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "00d593068470b914",
                 "bytes_per_launch": 1.9679e+10},
-    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "10f1d1704267a106",
-                  "bytes_per_launch": 1.5471e+10},
+    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "89b649c8bc2a4748",
+                  "bytes_per_launch": 1.5474e+10},
 }
 
 
