@@ -132,6 +132,8 @@ struct Workspace {
     size_t wv_sys_cap = 0;
     BatchState* wv_st = nullptr;
     size_t wv_st_cap = 0;
+    LsqJob* wv_jobs = nullptr;
+    size_t wv_jobs_cap = 0;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
@@ -1405,7 +1407,7 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         const size_t tot = static_cast<size_t>(sp[i][nsl] > 0 ? sp[i][nsl] : 1);
         size_t b = align_up(8 * (nsl + 1)) + align_up(4 * tot) + align_up(ev * tot) + align_up(8 * static_cast<size_t>(n));
         b += align_up(8 * static_cast<size_t>(s) * d) + align_up(8 * static_cast<size_t>(kk + 1) * d) +
-             align_up(8 * static_cast<size_t>(s)) + align_up(8 * static_cast<size_t>(d));
+             align_up(8 * static_cast<size_t>(s)) + 2 * align_up(8 * static_cast<size_t>(d));
         off[i + 1] = off[i] + b;
     }
     SG_TRY(ensure(ws.wv_sys_arena, ws.wv_sys_arena_cap, off[nsys]));
@@ -1416,7 +1418,7 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         int64_t* sp;
         int32_t* col;
         void* val;
-        double *r, *SAB, *H, *g, *y;
+        double *r, *SAB, *H, *g, *y, *tau;
     };
     std::vector<SysBufs> sb(nsys);
     std::vector<BatchSys> desc(nsys);
@@ -1441,6 +1443,8 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         B.g = reinterpret_cast<double*>(q);
         q += align_up(8 * static_cast<size_t>(s));
         B.y = reinterpret_cast<double*>(q);
+        q += align_up(8 * static_cast<size_t>(d));
+        B.tau = reinterpret_cast<double*>(q);
         SG_TRY(hipMemcpyAsync(B.sp, sp[i].data(), sizeof(int64_t) * (nsl + 1), hipMemcpyHostToDevice, st));
         SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, B.sp, B.col, B.val, prec, st));
         BatchSys& D = desc[i];
@@ -1499,12 +1503,16 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
     const size_t psk_dbl = static_cast<size_t>(2 * s * d + s) * cap;
     // B of one wave: at most cap groups, each column padded to 128 entries
     const size_t b_bytes = align_up(static_cast<size_t>(cap * L.rows + 128 * static_cast<int64_t>(cap)) * d * eb);
-    const size_t wave_bytes = align_up(sync_u32 * 4 * cap) + align_up(8 * pab_u64) + align_up(8 * psk_dbl) + b_bytes;
+    const size_t lsq_bytes = align_up(lsq_sync_bytes() * cap);
+    const size_t wave_bytes =
+        align_up(sync_u32 * 4 * cap) + align_up(8 * pab_u64) + align_up(8 * psk_dbl) + b_bytes + lsq_bytes;
     SG_TRY(ensure(ws.wv_wave_arena, ws.wv_wave_arena_cap, wave_bytes));
     unsigned* w_sync = reinterpret_cast<unsigned*>(ws.wv_wave_arena);
     unsigned long long* w_pab = reinterpret_cast<unsigned long long*>(ws.wv_wave_arena + align_up(sync_u32 * 4 * cap));
     double* w_psk = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(w_pab) + align_up(8 * pab_u64));
     unsigned char* w_B = reinterpret_cast<unsigned char*>(w_psk) + align_up(8 * psk_dbl);
+    void* w_lsq = w_B + b_bytes;  // publication counters of the pipelined least squares
+    const bool pipe = s <= kLsqPipeMaxS;
 
     std::vector<int> order(nsys);
     for (int i = 0; i < nsys; ++i) order[i] = i;
@@ -1541,7 +1549,9 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         const size_t nw = waves.size();
         SG_TRY(ensure(ws.wv_ps, ws.wv_ps_cap, nw * cap));
         SG_TRY(ensure(ws.wv_idx, ws.wv_idx_cap, nw * 2 * cap));
+        SG_TRY(ensure(ws.wv_jobs, ws.wv_jobs_cap, nw * cap));
         std::vector<ArnoldiParams> ps(nw * cap);
+        std::vector<LsqJob> jobs(nw * cap);
         std::vector<int> idx(nw * 2 * cap, -1);
         std::vector<int> grids(nw);
         struct Slot {
@@ -1597,6 +1607,15 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
                 p.blk0 = blk0;
                 for (int b = 0; b < G; ++b) idx[w * 2 * cap + blk0 + b] = static_cast<int>(g);
                 idx[w * 2 * cap + cap + g] = i;
+                LsqJob& J = jobs[w * cap + g];
+                J.dc = &ws.wv_st[i].dc;
+                J.C = sb[i].SAB;
+                J.g = sb[i].g;
+                J.tau = sb[i].tau;
+                J.y = sb[i].y;
+                J.dout = &ws.wv_st[i].rest;
+                J.iout = &ws.wv_st[i].d_eff;
+                J.sync = static_cast<unsigned char*>(w_lsq) + lsq_sync_bytes() * g;
                 slots[w].push_back(Slot{i, ldb, B});
                 blk0 += G;
             }
@@ -1604,12 +1623,17 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         }
         SG_TRY(hipMemcpyAsync(ws.wv_ps, ps.data(), sizeof(ArnoldiParams) * ps.size(), hipMemcpyHostToDevice, st));
         SG_TRY(hipMemcpyAsync(ws.wv_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
+        SG_TRY(hipMemcpyAsync(ws.wv_jobs, jobs.data(), sizeof(LsqJob) * jobs.size(), hipMemcpyHostToDevice, st));
         for (size_t w = 0; w < nw; ++w) {
             const int ng = static_cast<int>(waves[w].size());
             SG_TRY(launch_fill_u32(w_sync, static_cast<int64_t>(sync_u32) * ng, 0u, st));
             SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(w_pab), static_cast<int64_t>(2 * pab_u64), 0u, st));
             SG_TRY(arnoldi_multi_launch(L, grids[w], ws.wv_ps + w * cap, ws.wv_idx + w * 2 * cap, st));
-            SG_TRY(launch_lsq_batched(ng, s, ws.wv_sys, ws.wv_st, kappa_max, st, ws.wv_idx + w * 2 * cap + cap));
+            if (pipe)
+                SG_TRY(launch_lsq_pipeline_batched(ng, s, d, ws.wv_jobs + w * cap, w_lsq, kappa_max, &ws.sc->abort,
+                                                   kSpinLimitTicks, st));
+            else
+                SG_TRY(launch_lsq_batched(ng, s, ws.wv_sys, ws.wv_st, kappa_max, st, ws.wv_idx + w * 2 * cap + cap));
             for (const Slot& sl : slots[w]) {
                 const int i = sl.sys;
                 const sgmres_csr_t& A = systems[i].A;
@@ -2156,7 +2180,7 @@ void sgmres_release_workspace(void) {
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
                         w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr, w.wv_sys_arena, w.wv_wave_arena, w.wv_K,
-                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st};
+                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st, w.wv_jobs};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);

@@ -304,6 +304,24 @@ hipError_t batch_launch(const BatchLaunch& L, const BatchParams& p, hipStream_t 
 // reset: start of a solve (clears every BatchState and counter).
 hipError_t launch_batch_advance(int* ctr, BatchState* st, unsigned* gcnt, int nsys, hipStream_t stream);
 hipError_t launch_batch_reset(BatchState* st, unsigned* gcnt, int nsys, int* ctr, hipStream_t stream);
+// One system of a batched pipelined least squares: its dc (device), C = S A B
+// (s x d, overwritten), g (s, overwritten), tau (d scratch), y (d out),
+// dout (rest, kappa), iout (d_eff, flags |=), sync (lsq_sync_bytes(), per job)
+struct LsqJob {
+    const int* dc;
+    double* C;
+    double* g;
+    double* tau;
+    double* y;
+    double* dout;
+    int* iout;
+    void* sync;
+};
+// jobs (device array of njobs) run concurrently, each on the workgroups of
+// launch_lsq_pipeline; syncs: njobs consecutive sync blocks (cleared here);
+// s <= 512
+hipError_t launch_lsq_pipeline_batched(int njobs, int s, int d_max, const LsqJob* jobs, void* syncs,
+                                       double kappa_max, int* abort, uint64_t limit, hipStream_t stream);
 hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* st, double kappa_max,
                               hipStream_t stream, const int* idx = nullptr);
 

@@ -343,19 +343,20 @@ __device__ __forceinline__ void factor_held(double (&col)[CB][S], int c0, int dc
     }
 }
 
+// One system's factorisation; blk: this workgroup's index among the system's.
 template <int S>
-__global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const int* __restrict__ dc_dev, int dc_host,
-                                                                  double* __restrict__ C, double* __restrict__ g,
-                                                                  double* __restrict__ tau, double kappa_max,
-                                                                  double* __restrict__ y, double* __restrict__ dout,
-                                                                  int* __restrict__ iout, LsqSync* sync, int* abort,
-                                                                  uint64_t limit) {
+__device__ __forceinline__ void lsq_pipeline_body(int blk, int s, const int* __restrict__ dc_dev, int dc_host,
+                                                  double* __restrict__ C, double* __restrict__ g,
+                                                  double* __restrict__ tau, double kappa_max,
+                                                  double* __restrict__ y, double* __restrict__ dout,
+                                                  int* __restrict__ iout, LsqSync* sync, int* abort,
+                                                  uint64_t limit) {
     constexpr int CB = kPipeCols;
     extern __shared__ double lds[];
     __shared__ unsigned lpub;
     const int dc = dc_dev ? *dc_dev : dc_host;
     const int lane = threadIdx.x & (kWave - 1);
-    const int bstart = blockIdx.x * kPipeBC;
+    const int bstart = blk * kPipeBC;
     const int c0 = bstart + (threadIdx.x / kWave) * CB;
     if (threadIdx.x == 0) lpub = static_cast<unsigned>(bstart);
     __syncthreads();
@@ -567,6 +568,29 @@ __global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const i
     }
 }
 
+template <int S>
+__global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_kernel(int s, const int* __restrict__ dc_dev, int dc_host,
+                                                                  double* __restrict__ C, double* __restrict__ g,
+                                                                  double* __restrict__ tau, double kappa_max,
+                                                                  double* __restrict__ y, double* __restrict__ dout,
+                                                                  int* __restrict__ iout, LsqSync* sync, int* abort,
+                                                                  uint64_t limit) {
+    lsq_pipeline_body<S>(blockIdx.x, s, dc_dev, dc_host, C, g, tau, kappa_max, y, dout, iout, sync, abort, limit);
+}
+
+// Several systems' factorisations in one launch: workgroups [j nblk, (j+1)
+// nblk) factor system jobs[j]; each system has its own publication counter.
+template <int S>
+__global__ __launch_bounds__(kPipeBlock) void lsq_pipeline_batched_kernel(int s, int nblk,
+                                                                          const LsqJob* __restrict__ jobs,
+                                                                          double kappa_max, int* abort,
+                                                                          uint64_t limit) {
+    const int j = blockIdx.x / nblk;
+    const LsqJob& J = jobs[j];
+    lsq_pipeline_body<S>(blockIdx.x - j * nblk, s, J.dc, 0, J.C, J.g, J.tau, kappa_max, J.y, J.dout, J.iout,
+                         static_cast<LsqSync*>(J.sync), abort, limit);
+}
+
 }  // namespace
 
 hipError_t launch_lsq(int s, const int* dc_dev, int dc_host, double* C, double* g, double kappa_max,
@@ -604,6 +628,31 @@ hipError_t launch_lsq_pipeline(int s, int d_max, const int* dc_dev, int dc_host,
     LsqSync* sp = static_cast<LsqSync*>(sync);
     void* args[] = {&s, &dc_dev, &dc_host, &C, &g, &tau, &kappa_max, &y, &dout, &iout, &sp, &abort, &limit};
     return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kPipeBlock), args, static_cast<unsigned>(lds), stream);
+}
+
+hipError_t launch_lsq_pipeline_batched(int njobs, int s, int d_max, const LsqJob* jobs, void* syncs, double kappa_max,
+                                       int* abort, uint64_t limit, hipStream_t stream) {
+    if (njobs <= 0) return hipSuccess;
+    const int slots = (s + kWave - 1) / kWave;
+    const void* fn = nullptr;
+    int S = 0;
+    if (slots <= 1) fn = reinterpret_cast<const void*>(lsq_pipeline_batched_kernel<1>), S = 1;
+    else if (slots <= 2) fn = reinterpret_cast<const void*>(lsq_pipeline_batched_kernel<2>), S = 2;
+    else if (slots <= 4) fn = reinterpret_cast<const void*>(lsq_pipeline_batched_kernel<4>), S = 4;
+    else if (slots <= 8) fn = reinterpret_cast<const void*>(lsq_pipeline_batched_kernel<8>), S = 8;
+    else return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * static_cast<size_t>(kPipeBC) * (S * kWave + 1);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (err != hipSuccess) return err;
+    // the publication counters start at zero (a fill kernel: capture-safe)
+    err = launch_fill_u32(static_cast<unsigned*>(syncs),
+                          static_cast<int64_t>(njobs) * static_cast<int64_t>(sizeof(LsqSync) / sizeof(unsigned)), 0u,
+                          stream);
+    if (err != hipSuccess) return err;
+    int nblk = (d_max + 1 + kPipeBC - 1) / kPipeBC;
+    void* args[] = {&s, &nblk, &jobs, &kappa_max, &abort, &limit};
+    return hipLaunchCooperativeKernel(fn, dim3(njobs * nblk), dim3(kPipeBlock), args, static_cast<unsigned>(lds),
+                                      stream);
 }
 
 }  // namespace sg
