@@ -86,6 +86,23 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
     // together; wider groups measured slower: 64 -> 73 us per step at
     // n = 2^22 in FP32 with all 16 pairs of a tile)
     constexpr int PG = P < 4 ? P : 4;
+    // window entries read from HBM (those not in the LDS ring)
+    constexpr int NH = kStreamMaxK - NL;
+    // FP32 arithmetic, one right-hand side, register state: the newest KH of
+    // them stay in registers (at most 32 a lane) and move down the window
+    // there, so no phase reads them from HBM (FP64 and several right-hand
+    // sides: the registers spill)
+    constexpr int KH0 = 32 / (P * static_cast<int>(sizeof(TC)) / 4);
+    constexpr int KH = (sizeof(TC) == 4 && NR == 1 && !HST && NL > 0) ? (NH < KH0 ? NH : KH0) : 0;
+    // otherwise the SpMV group's HBM window entries are loaded with its first
+    // slot when they take at most 8 registers a lane
+    constexpr bool PRE = KH == 0 && NH > 0 && NH * PG * static_cast<int>(sizeof(TC)) <= 32;
+    // FP32 arithmetic, one right-hand side: the next slot's column indices
+    // and values are loaded while the current slot's gathers are in flight
+    constexpr bool LA = sizeof(TC) == 4 && NR == 1;
+    // pairs whose window loads are in flight together in the Gram-Schmidt
+    // phases
+    constexpr int WP = P < 4 ? P : 4;
     __shared__ double red[kNW * kNV * NR];
     __shared__ double coefA[kNV * NR];  // [v * NR + rhs]: v = 0 <m,m>, 1 + a: h_a
     __shared__ double coefB[kNV * NR];  // v = 0 <w,w>, 1 + a: h2_a
@@ -162,6 +179,12 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
     bar.sync();  // b_1 complete everywhere
 
     TC mreg[HST ? 1 : P];
+    // kept window entries: wk[h][pp] is entry NL + h of pair pp
+    TC wk[KH > 0 ? KH : 1][KH > 0 ? P : 1];
+#pragma unroll
+    for (int h = 0; h < (KH > 0 ? KH : 1); ++h)
+#pragma unroll
+        for (int pp = 0; pp < (KH > 0 ? P : 1); ++pp) wk[h][pp] = TC(0);
     int flags = 0;
     int dc = d;
     for (int j = 0; j < d; ++j) {
@@ -170,12 +193,19 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
         const unsigned tag = static_cast<unsigned>(j + 1);
         // window entry a (0 = newest; a < min(j + 1, k)) of the thread's pair
         // at local index loc: ring slot (j - a) % NL when a < NL, else B
-        int soff[NL > 0 ? NL : 1];
+        int soff[NL > 0 ? NL : 1] = {};
+        if constexpr (NL > 0) {
 #pragma unroll
-        for (int a = 0; a < (NL > 0 ? NL : 1); ++a) soff[a] = (((j - a) % NL + NL) % NL) * T;
+            for (int a = 0; a < NL; ++a) soff[a] = (((j - a) % NL + NL) % NL) * T;
+        }
         auto ldW = [&](int a, uint32_t q, int loc) -> TC {
             if (a < NL) return ring[soff[a] + loc];
             return from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q]);
+        };
+        // window entry a of register-state pair pp (compile-time a and pp)
+        auto wwin = [&](int a, int pp, uint32_t q) -> TC {
+            if (a >= NL && a < NL + KH) return wk[a - NL][pp];
+            return ldW(a, q, pp * kBlock + tid);
         };
         tick(0);
 
@@ -210,9 +240,8 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                 TC m[PG];
 #pragma unroll
                 for (int u = 0; u < PG; ++u) m[u] = TC(0);
-                for (int e = 0; e < kmax; ++e) {
-                    int c[PG];
-                    TC v[PG];
+                // slot e's column indices and values of the PG pairs
+                auto ld_slot = [&](int e, int (&c)[PG], TC (&v)[PG]) {
 #pragma unroll
                     for (int u = 0; u < PG; ++u) {
                         c[u] = 0;
@@ -223,6 +252,10 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                             v[u] = (Av + spos[u])[a];
                         }
                     }
+                };
+                // gathers of slot e and the products' sums (each row in slot
+                // order)
+                auto spmv_slot = [&](int e, const int (&c)[PG], const TC (&v)[PG], TC (&m)[PG]) {
 #pragma unroll
                     for (int u = 0; u < PG; ++u)
                         if (e < sK[u]) {
@@ -236,16 +269,61 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                             }
                             m[u] = madd(v[u], bv, m[u]);
                         }
+                };
+                int c[PG];
+                TC v[PG];
+                if constexpr (LA) ld_slot(0, c, v);
+                // the group's window entries that live in HBM, in flight
+                // with the first slot
+                TC wpre[PRE ? PG : 1][NH > 0 ? NH : 1];
+                if constexpr (PRE) {
+#pragma unroll
+                    for (int u = 0; u < PG; ++u) {
+                        const uint32_t q =
+                            static_cast<uint32_t>(tl * T) + static_cast<uint32_t>((g0 + u) * kBlock + tid);
+#pragma unroll
+                        for (int h = 0; h < NH; ++h) {
+                            const int a = kStreamMaxK - NH + h;
+                            wpre[u][h] = (q < npairs && a < kw)
+                                             ? from_basis<TC>((Bs + static_cast<int64_t>(j - a) * ldb)[q])
+                                             : TC(0);
+                        }
+                    }
+                }
+                for (int e = 0; e < kmax; ++e) {
+                    if constexpr (LA) {
+                        // next slot's loads in flight during this slot's gathers
+                        int cn[PG];
+                        TC vn[PG];
+                        ld_slot(e + 1, cn, vn);
+                        spmv_slot(e, c, v, m);
+#pragma unroll
+                        for (int u = 0; u < PG; ++u) {
+                            c[u] = cn[u];
+                            v[u] = vn[u];
+                        }
+                    } else {
+                        ld_slot(e, c, v);
+                        spmv_slot(e, c, v, m);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < PG; ++u) {
                     const uint32_t q = static_cast<uint32_t>(tl * T) + static_cast<uint32_t>((g0 + u) * kBlock + tid);
-                    if (q < npairs) {
+                    if (KH == 0 && q < npairs) {
                         acc[0] = dot_acc(acc[0], m[u], m[u]);
-                        for (int a = 0; a < kw; ++a) {
-                            const TC wa = ldW(a, q, (g0 + u) * kBlock + tid);
-                            acc[1 + a] = dot_acc(acc[1 + a], wa, m[u]);
-                        }
+#pragma unroll
+                        for (int a = 0; a < kStreamMaxK; ++a)
+                            if (a < kw) {
+                                TC wa;
+                                if constexpr (PRE) {
+                                    wa = a >= kStreamMaxK - NH ? wpre[u][a - (kStreamMaxK - NH)]
+                                                               : ldW(a, q, (g0 + u) * kBlock + tid);
+                                } else {
+                                    wa = ldW(a, q, (g0 + u) * kBlock + tid);
+                                }
+                                acc[1 + a] = dot_acc(acc[1 + a], wa, m[u]);
+                            }
                     }
                     if constexpr (HST) {
                         if (q < npairs) state[q] = m[u];
@@ -254,6 +332,20 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if constexpr (KH > 0) {
+            // the window dots of the tile's pairs, pairs in order
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t q = static_cast<uint32_t>(tbase) + static_cast<uint32_t>(pp * kBlock + tid);
+                if (q < npairs) {
+                    acc[0] = dot_acc(acc[0], mreg[pp], mreg[pp]);
+#pragma unroll
+                    for (int a = 0; a < kStreamMaxK; ++a)
+                        if (a < kw) acc[1 + a] = dot_acc(acc[1 + a], wwin(a, pp, q), mreg[pp]);
+                }
+                if ((pp + 1) % WP == 0) __builtin_amdgcn_sched_barrier(0);
             }
         }
         block_sum_rhs<NR>(acc, kw + 1, red, [&](int v, int r, double val) {
@@ -277,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                     TC wa[kStreamMaxK];
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
-                        if (a < kw) wa[a] = ldW(a, q, pp * kBlock + tid);
+                        if (a < kw) wa[a] = HST ? ldW(a, q, pp * kBlock + tid) : wwin(a, pp, q);
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
                         if (a < kw) w = gs_sub(w, static_cast<TC>(coefA[(1 + a) * NR + rhs]), wa[a]);
@@ -288,9 +380,9 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                     if constexpr (HST) state[q] = w;
                     else mreg[pp] = w;
                 }
-                // one pair's window loads in flight at a time: keeps the
+                // WP pairs' window loads in flight at a time: keeps the
                 // register state of many pairs from spilling
-                __builtin_amdgcn_sched_barrier(0);
+                if ((pp + 1) % WP == 0) __builtin_amdgcn_sched_barrier(0);
             }
         }
         block_sum_rhs<NR>(acc, kw + 1, red, [&](int v, int r, double val) {
@@ -345,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                         TC wa[kStreamMaxK];
 #pragma unroll
                         for (int a = 0; a < kStreamMaxK; ++a)
-                            if (a < kw) wa[a] = ldW(a, q, pp * kBlock + tid);
+                            wa[a] = a < kw ? (HST ? ldW(a, q, pp * kBlock + tid) : wwin(a, pp, q)) : TC(0);
 #pragma unroll
                         for (int a = 0; a < kStreamMaxK; ++a)
                             if (a < kw) w = gs_sub(w, static_cast<TC>(coefB[(1 + a) * NR + rhs]), wa[a]);
@@ -354,8 +446,16 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                         // (the slot of column j + 1 - nl: window entry nl at the next
                         // step, which then reads it from B)
                         if constexpr (NL > 0) ring[((j + 1) % NL) * T + pp * kBlock + tid] = from_basis<TC>(st);
+                        if constexpr (KH > 0) {
+                            // the next step's kept entries: entry NL - 1 of
+                            // this step (the ring slot just overwritten) and
+                            // the kept entries moved one place down
+#pragma unroll
+                            for (int h = KH - 1; h > 0; --h) wk[h][pp] = wk[h - 1][pp];
+                            wk[0][pp] = wa[NL - 1];
+                        }
                     }
-                    __builtin_amdgcn_sched_barrier(0);
+                    if ((pp + 1) % WP == 0) __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
