@@ -35,21 +35,34 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # in profiles/<kernel>_cd1024_hbm_counters.md).  Valid only for the kernel
 # source it was measured on; any change to it makes the figure stale (null).
 MEASURED_TRAFFIC = {
-    "arnoldi": {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "00d593068470b914",
-                "bytes_per_launch": 1.9679e+10},
-    "chebyshev": {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "89b649c8bc2a4748",
-                  "bytes_per_launch": 1.5474e+10},
+    # (kernel, workload, precision) -> sources the figure is tied to, their
+    # hash, and FETCH_SIZE x 2 + WRITE_SIZE per launch
+    ("arnoldi", "cd1024", "fp64"): {"files": ("arnoldi_kernel.hpp", "common.hpp"), "source_hash": "00d593068470b914",
+                                    "bytes_per_launch": 1.9679e+10},
+    ("chebyshev", "cd1024", "fp64"): {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "89b649c8bc2a4748",
+                                      "bytes_per_launch": 1.5474e+10},
+    ("stream", "cd2048", "fp32"): {"files": ("stream_kernel.hpp", "common.hpp"), "source_hash": "819f8a8506306796",
+                                   "bytes_per_launch": 3.8233e+10},
 }
 
 
-def kernel_source_hash(basis: str) -> str:
+def kernel_source_hash(files) -> str:
     import hashlib
 
     m = hashlib.sha256()
-    for f in MEASURED_TRAFFIC[basis]["files"]:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2111_00113_amd", "csrc", f), "rb") as fh:
             m.update(fh.read())
     return m.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """Counter-measured bytes per launch of this kernel at this workload, or
+    None when none were taken or the kernel's source has changed since."""
+    e = MEASURED_TRAFFIC.get((kernel, workload, precision))
+    if e is None or kernel_source_hash(e["files"]) != e["source_hash"]:
+        return None
+    return e["bytes_per_launch"]
 
 
 def log(msg: str) -> None:
@@ -487,9 +500,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": (MEASURED_TRAFFIC[args.basis]["bytes_per_launch"]
-                        if kernel_source_hash(args.basis) == MEASURED_TRAFFIC[args.basis]["source_hash"]
-                        and args.workload == "cd1024" and args.precision == "fp64" and not streaming else None),
+            "traffic": (measured_traffic("stream" if streaming else args.basis, args.workload, args.precision)
+                        if resident else None),
             "traffic_unit": "bytes per launch",
             "kernel": ("stream_kernel (streaming truncated Arnoldi)" if streaming else
                        ("chebyshev_kernel" if cheb else "arnoldi_kernel (spmv_truncarnoldi)")) if resident
