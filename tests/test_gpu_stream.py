@@ -237,6 +237,36 @@ def test_stream_full_size_one_cycle_reduced_precision(sg, cd2048, cd2048_oracle_
         assert err < 0.1 and ratio < 10.0
 
 
+@pytest.fixture(scope="module")
+def cd2040_with_oracle_cycle(orc):
+    A = synth.convection_diffusion(2040, (50.0, 20.0))
+    f = synth.rhs(A.n, 0)
+    orc.set_threads(_host_threads())
+    try:
+        _, x_o, info_o = orc.sgmres_solve(A, f, d=200, k=4, s=400, zeta=8, seed=0, tol=0.0, restarts=0)
+    finally:
+        orc.set_threads(1)
+    return A, f, x_o, info_o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stream_ragged_last_tile_one_cycle(sg, cd2040_with_oracle_cycle, prec):
+    """n = 4,161,600 (2040 x 2040 grid): 16 rows per thread in registers over
+    255 tiles of 16,384 rows, the last holding 64 rows, so most of its pairs
+    lie past n; one cycle against the oracle's (bounds as at n = 4,194,304)."""
+    A, f, x_o, info_o = cd2040_with_oracle_cycle
+    rc, x, info = _gpu(sg, A, f, 200, 4, 400, 0, 0.0, 0, precision=prec)
+    assert info["path"] == sg.PATH_STREAM and info["launch_rows"] == 16 and info["launch_grid"] == 255
+    err = np.linalg.norm(x - x_o) / np.linalg.norm(x_o)
+    print(f"cd2040 {prec} one cycle: x error {err:.3e}, relres gpu {info['relres']:.9e} "
+          f"oracle {info_o['relres']:.9e}", flush=True)
+    if prec == "fp64":
+        assert err < 1e-8 and abs(info["relres"] - info_o["relres"]) < 1e-10
+        assert np.isclose(info["rest_est"], info_o["rest_est"], rtol=1e-8)
+    else:
+        assert err < 1e-4 and abs(info["relres"] / info_o["relres"] - 1.0) < 1e-4
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_stream_full_size_converges(sg, orc, cd2048, prec):
     A, f = cd2048
