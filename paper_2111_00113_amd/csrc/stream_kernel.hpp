@@ -10,8 +10,10 @@
 // one contiguous run and the NR right-hand sides share every read of A.  A
 // tile is P * BLOCK consecutive pairs; thread t of a block takes pairs
 // tile * P * BLOCK + p * BLOCK + t, p < P, so its right-hand side is t % NR.
-// The window (the last k basis vectors) is read back from B; A is read through
-// its sliced ELL copy (entry e of row i at sp[i / 64] + 64 e + i % 64).
+// The window (the last k basis vectors) comes from an LDS ring of the newest
+// columns of the block's tile, then from registers (FP32 arithmetic, one
+// right-hand side), then from B; A is read through its sliced ELL copy (entry
+// e of row i at sp[i / 64] + 64 e + i % 64).
 //
 // Per step j (two tagged reductions and one grid barrier):
 //   phase 1  m = A b_j; per right-hand side partials <m,m>, W^T m  (tagged)
