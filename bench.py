@@ -344,7 +344,7 @@ def cheb_launch_bytes(n: int, nnz: int, dc: float, prec: str = "fp64") -> float:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed solves")
+    ap.add_argument("--steps", type=int, default=5, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--workload", default="cd1024")
     ap.add_argument("--cpu-sample-cols", type=int, default=40)
@@ -432,9 +432,14 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
+    per_solve = []
     for i in range(args.steps):
+        ti = time.perf_counter()
         infos.append(solve(True))
-        log(f"step {i}: cycles={infos[-1]['cycles']} relres={infos[-1]['relres']:.3e}")
+        torch.cuda.synchronize()
+        per_solve.append(time.perf_counter() - ti)
+        log(f"step {i}: cycles={infos[-1]['cycles']} relres={infos[-1]['relres']:.3e} "
+            f"{per_solve[-1] * 1e3:.2f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -470,6 +475,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": elapsed * 1e3 / args.steps,
+        "median_ms_per_solve": float(np.median(per_solve)) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
