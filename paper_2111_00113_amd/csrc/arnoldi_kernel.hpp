@@ -626,14 +626,16 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_kernel(ArnoldiParams p) {
 // logical blocks [ps[g].blk0, ps[g].blk0 + ps[g].G), which the XCD-aware
 // numbering keeps on as few XCDs as possible.  Each group has its own grid
 // barrier words, partial sums and status; groups never wait for each other.
-template <int R, int KW, int BLOCK, typename TC, typename TS>
+// LOOK: the SpMV loads the next slot's columns ahead (where it fits in the
+// registers without a spill).
+template <int R, int KW, int BLOCK, typename TC, typename TS, bool LOOK>
 __global__ __launch_bounds__(BLOCK) void arnoldi_multi_kernel(const ArnoldiParams* __restrict__ ps,
                                                               const int* __restrict__ grp) {
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int g = __builtin_amdgcn_readfirstlane(grp[lb]);
     if (g < 0) return;
     const ArnoldiParams& p = ps[g];
-    arnoldi_body<R, KW, BLOCK, false, TC, TS, false, false>(p, p.G, lb - p.blk0);
+    arnoldi_body<R, KW, BLOCK, false, TC, TS, false, LOOK>(p, p.G, lb - p.blk0);
 }
 
 // Kernel instance for (BLOCK, R, KW); (R, KW) = (8, 8) is never selected

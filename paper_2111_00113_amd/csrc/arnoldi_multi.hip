@@ -8,19 +8,29 @@ namespace sg {
 
 namespace {
 
-template <typename TC, typename TS>
+// Window registers: two columns for k <= 2, else four.  The SpMV's column
+// look-ahead is on wherever it costs no register spill: every instance but
+// FP64 arithmetic with a four-column window (which spilled 24 VGPRs with it
+// at four rows per thread and measured slower).
+template <typename TC, typename TS, int KW>
 const void* pick_rows_multi(int R) {
+    constexpr bool look = KW <= 2 || sizeof(TC) == 4;
     switch (R) {
-        case 2: return reinterpret_cast<const void*>(arnoldi_detail::arnoldi_multi_kernel<2, 4, 1024, TC, TS>);
-        case 4: return reinterpret_cast<const void*>(arnoldi_detail::arnoldi_multi_kernel<4, 4, 1024, TC, TS>);
+        case 2: return reinterpret_cast<const void*>(arnoldi_detail::arnoldi_multi_kernel<2, KW, 1024, TC, TS, look>);
+        case 4: return reinterpret_cast<const void*>(arnoldi_detail::arnoldi_multi_kernel<4, KW, 1024, TC, TS, look>);
         default: return nullptr;
     }
 }
 
-const void* pick_multi(int R, int precision) {
-    if (precision == SGMRES_PREC_FP64) return pick_rows_multi<double, double>(R);
-    if (precision == SGMRES_PREC_FP32) return pick_rows_multi<float, float>(R);
-    if (precision == SGMRES_PREC_BF16_BASIS) return pick_rows_multi<float, bf16_t>(R);
+template <typename TC, typename TS>
+const void* pick_window_multi(int R, int k) {
+    return k <= 2 ? pick_rows_multi<TC, TS, 2>(R) : pick_rows_multi<TC, TS, 4>(R);
+}
+
+const void* pick_multi(int R, int k, int precision) {
+    if (precision == SGMRES_PREC_FP64) return pick_window_multi<double, double>(R, k);
+    if (precision == SGMRES_PREC_FP32) return pick_window_multi<float, float>(R, k);
+    if (precision == SGMRES_PREC_BF16_BASIS) return pick_window_multi<float, bf16_t>(R, k);
     return nullptr;
 }
 
@@ -28,7 +38,7 @@ const void* pick_multi(int R, int precision) {
 
 hipError_t arnoldi_multi_configure(int R, int k, int s, int zeta, int precision, MultiLaunch* out) {
     if (k < 1 || k > kMultiMaxK) return hipErrorInvalidValue;
-    const void* fn = pick_multi(R, precision);
+    const void* fn = pick_multi(R, k, precision);
     if (!fn) return hipErrorInvalidValue;
     int device = 0;
     hipError_t err = hipGetDevice(&device);

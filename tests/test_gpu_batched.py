@@ -275,6 +275,39 @@ def test_multi_rows_per_thread(sg, orc, R):
         assert abs(r["relres"] - info_o["relres"]) <= 1e-10
 
 
+@pytest.mark.parametrize("k", [1, 3, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_window_lengths(sg, orc, k, prec):
+    """The multi-system instances for other window lengths (two window columns
+    in registers for k <= 2, four for k = 3, 4; FP64 with four columns and
+    four rows per thread without the column look-ahead), one cycle.  Each
+    system's x equals, bit for bit, that of sgmres_solve with the same launch
+    shape (1024 x 4, three barriers).  Against the oracle for k = 3, 4 (FP32:
+    to the basis precision); at k = 1 the basis is far from orthogonal here
+    (the oracle's kappa estimate of S A B is 2.8e9 for the 900-row system),
+    so only the bits against sgmres_solve are compared."""
+    d, s = 40, 90
+    batch = _mixed_batch(d)
+    rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, path=sg.PATH_MULTI, precision=prec)
+    for (A, b), r, x in zip(batch, res, xs):
+        x1 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc1, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(b), x1, d, k, s, 3, 0.0, 0, block_size=1024,
+                                    rows_per_thread=4, halo_off=True, precision=prec)
+        assert r["cycles"] == 1 and info["cycles"] == 1 and r["steps"] == info["steps"]
+        assert np.array_equal(_np(x1), x) and r["relres"] == info["relres"], A.n
+        if k == 1:
+            continue
+        rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=8, seed=3, tol=0.0, restarts=0)
+        err = np.linalg.norm(x - x_o) / np.linalg.norm(x_o)
+        if prec == "fp64":
+            assert r["steps"] == info_o["steps"]
+            assert err <= 1e-8, A.n
+            assert abs(r["relres"] - info_o["relres"]) <= 1e-10
+        else:
+            assert err <= 1e-4, (A.n, err)
+            assert r["relres"] <= info_o["relres"] + 1e-4, (A.n, r["relres"], info_o["relres"])
+
+
 def test_multi_waves(sg, orc):
     """More groups than fit one launch: 40 systems of 40,000-70,000 rows (10 to
     18 workgroups of 4096 rows each, about 560 in all) run in several waves;
