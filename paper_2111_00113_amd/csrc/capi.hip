@@ -134,6 +134,10 @@ struct Workspace {
     size_t wv_st_cap = 0;
     LsqJob* wv_jobs = nullptr;
     size_t wv_jobs_cap = 0;
+    TailJob* wv_tail = nullptr;  // per wave: the systems' combine, residual and norm
+    size_t wv_tail_cap = 0;
+    double* wv_tpart = nullptr;  // their residual block partials (one wave at a time)
+    size_t wv_tpart_cap = 0;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
     DevScalars* sc = nullptr;
     DevScalars* host_sc = nullptr;  // pinned
@@ -1550,8 +1554,12 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         SG_TRY(ensure(ws.wv_ps, ws.wv_ps_cap, nw * cap));
         SG_TRY(ensure(ws.wv_idx, ws.wv_idx_cap, nw * 2 * cap));
         SG_TRY(ensure(ws.wv_jobs, ws.wv_jobs_cap, nw * cap));
+        SG_TRY(ensure(ws.wv_tail, ws.wv_tail_cap, nw * cap));
+        SG_TRY(ensure(ws.wv_tpart, ws.wv_tpart_cap, static_cast<size_t>(cap) * kMaxVecGrid));
         std::vector<ArnoldiParams> ps(nw * cap);
         std::vector<LsqJob> jobs(nw * cap);
+        std::vector<TailJob> tails(nw * cap);
+        std::vector<int> cblocks(nw, 0), rblocks(nw, 0);
         std::vector<int> idx(nw * 2 * cap, -1);
         std::vector<int> grids(nw);
         struct Slot {
@@ -1616,6 +1624,27 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
                 J.dout = &ws.wv_st[i].rest;
                 J.iout = &ws.wv_st[i].d_eff;
                 J.sync = static_cast<unsigned char*>(w_lsq) + lsq_sync_bytes() * g;
+                TailJob& T = tails[w * cap + g];
+                T.n = A.n;
+                T.d_eff = &ws.wv_st[i].d_eff;
+                T.B = B;
+                T.ldb = ldb;
+                T.y = sb[i].y;
+                T.x = systems[i].x;
+                T.rp = A.row_ptr;
+                T.ci = A.col_idx;
+                T.val = A.val;
+                T.f = systems[i].b;
+                T.r = sb[i].r;
+                T.beta = &ws.wv_st[i].beta;
+                T.nf = &ws.wv_st[i].nf;
+                T.cblk0 = cblocks[w];
+                T.cnblk = A.n >= 4 ? combine4_grid(A.n) : 0;  // fewer rows: combined on its own
+                cblocks[w] += T.cnblk;
+                T.rblk0 = rblocks[w];
+                T.rnblk = vec_grid(A.n);
+                T.part = ws.wv_tpart + rblocks[w];
+                rblocks[w] += T.rnblk;
                 slots[w].push_back(Slot{i, ldb, B});
                 blk0 += G;
             }
@@ -1624,6 +1653,7 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         SG_TRY(hipMemcpyAsync(ws.wv_ps, ps.data(), sizeof(ArnoldiParams) * ps.size(), hipMemcpyHostToDevice, st));
         SG_TRY(hipMemcpyAsync(ws.wv_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
         SG_TRY(hipMemcpyAsync(ws.wv_jobs, jobs.data(), sizeof(LsqJob) * jobs.size(), hipMemcpyHostToDevice, st));
+        SG_TRY(hipMemcpyAsync(ws.wv_tail, tails.data(), sizeof(TailJob) * tails.size(), hipMemcpyHostToDevice, st));
         for (size_t w = 0; w < nw; ++w) {
             const int ng = static_cast<int>(waves[w].size());
             SG_TRY(launch_fill_u32(w_sync, static_cast<int64_t>(sync_u32) * ng, 0u, st));
@@ -1634,15 +1664,17 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
                                                    kSpinLimitTicks, st));
             else
                 SG_TRY(launch_lsq_batched(ng, s, ws.wv_sys, ws.wv_st, kappa_max, st, ws.wv_idx + w * 2 * cap + cap));
+            // the wave's systems' combines, residuals and norms: one launch
+            // each (a system of fewer than four rows is combined on its own)
             for (const Slot& sl : slots[w]) {
                 const int i = sl.sys;
                 const sgmres_csr_t& A = systems[i].A;
-                BatchState* t = ws.wv_st + i;
-                SG_TRY(launch_combine(A.n, &t->d_eff, d, sl.B, sl.ldb, sb[i].y, systems[i].x, st, nullptr, prec));
-                SG_TRY(launch_residual(A.n, A.row_ptr, A.col_idx, A.val, systems[i].b, systems[i].x, sb[i].r,
-                                       ws.part_vec, st));
-                SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(A.n), &t->beta, &t->nf, st));
+                if (A.n < 4)
+                    SG_TRY(launch_combine(A.n, &ws.wv_st[i].d_eff, d, sl.B, sl.ldb, sb[i].y, systems[i].x, st,
+                                          nullptr, prec));
             }
+            SG_TRY(launch_tail_jobs(ws.wv_tail + w * cap, static_cast<int>(slots[w].size()), cblocks[w],
+                                    rblocks[w], d, prec, st));
         }
         rc = read_states();  // also orders the host vectors' copies above
         if (rc) return rc;
@@ -2180,7 +2212,7 @@ void sgmres_release_workspace(void) {
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
                         w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr, w.wv_sys_arena, w.wv_wave_arena, w.wv_K,
-                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st, w.wv_jobs};
+                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st, w.wv_jobs, w.wv_tail, w.wv_tpart};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);

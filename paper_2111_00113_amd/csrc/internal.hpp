@@ -363,6 +363,33 @@ hipError_t launch_fill_u32(unsigned* x, int64_t n, unsigned v, hipStream_t strea
 hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B, int64_t ldb,
                           const double* y, double* x, hipStream_t stream, const double* colnorm = nullptr,
                           int precision = 0);
+// The tail of one system's cycle in a multi-system wave: x += B y (blocks
+// [cblk0, cblk0 + cnblk) of the combine launch; cnblk = 0: not in it), then
+// r = f - A x with block partials of |r|^2 (blocks [rblk0, rblk0 + rnblk),
+// rnblk = vec_grid(n)), then beta[0] = |r|, beta[1] = |r| / *nf.  Jobs are in
+// block order in both launches.
+struct TailJob {
+    int64_t n;
+    const int* d_eff;
+    const void* B;  // aligned to four entries, as is ldb
+    int64_t ldb;
+    const double* y;
+    double* x;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+    const double* f;
+    double* r;
+    double* part;  // rnblk partials
+    double* beta;
+    const double* nf;
+    int cblk0, cnblk;
+    int rblk0, rnblk;
+};
+// blocks of the four-rows-per-thread combine for n rows
+int combine4_grid(int64_t n);
+hipError_t launch_tail_jobs(const TailJob* jobs, int njobs, int cblocks, int rblocks, int d_max, int precision,
+                            hipStream_t stream);
 // out[i] = (float) in[i]
 hipError_t launch_to_f32(int64_t count, const double* in, float* out, hipStream_t stream);
 

@@ -15,18 +15,17 @@ int vec_grid(int64_t n) {
 
 namespace {
 
-__global__ __launch_bounds__(kVecBlock) void residual_kernel(int64_t n, const int32_t* __restrict__ rp,
-                                                             const int32_t* __restrict__ ci,
-                                                             const double* __restrict__ val,
-                                                             const double* __restrict__ f,
-                                                             const double* __restrict__ x,
-                                                             double* __restrict__ r,
-                                                             double* __restrict__ part) {
+// Block blk of nblk: rows blk * kVecBlock + t + k * nblk * kVecBlock; its
+// partial |r|^2 into part[blk].
+__device__ __forceinline__ void residual_body(int blk, int nblk, int64_t n, const int32_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                              const double* __restrict__ f, const double* __restrict__ x,
+                                              double* __restrict__ r, double* __restrict__ part) {
     __shared__ double tmp[kVecBlock / kWave];
     __shared__ double out[1];
     double acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kVecBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kVecBlock + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = static_cast<int64_t>(nblk) * kVecBlock;
+    for (int64_t i = static_cast<int64_t>(blk) * kVecBlock + threadIdx.x; i < n; i += stride) {
         double ax = 0.0;
         if (x) {
             const int q1 = rp[i + 1];
@@ -38,12 +37,21 @@ __global__ __launch_bounds__(kVecBlock) void residual_kernel(int64_t n, const in
     }
     const double v[1] = {acc};
     block_sum<1>(v, 1, tmp, out);
-    if (threadIdx.x == 0) part[blockIdx.x] = out[0];
+    if (threadIdx.x == 0) part[blk] = out[0];
 }
 
-__global__ __launch_bounds__(kVecBlock) void norm_finish_kernel(const double* __restrict__ part, int G,
-                                                                double* __restrict__ out,
-                                                                const double* __restrict__ nf) {
+__global__ __launch_bounds__(kVecBlock) void residual_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ ci,
+                                                             const double* __restrict__ val,
+                                                             const double* __restrict__ f,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ r,
+                                                             double* __restrict__ part) {
+    residual_body(blockIdx.x, gridDim.x, n, rp, ci, val, f, x, r, part);
+}
+
+__device__ __forceinline__ void norm_finish_body(const double* __restrict__ part, int G, double* __restrict__ out,
+                                                 const double* __restrict__ nf) {
     __shared__ double res[1];
     grid_sum(part, G, 1, res);
     if (threadIdx.x == 0) {
@@ -51,6 +59,12 @@ __global__ __launch_bounds__(kVecBlock) void norm_finish_kernel(const double* __
         out[0] = nrm;
         if (nf) out[1] = nrm / *nf;
     }
+}
+
+__global__ __launch_bounds__(kVecBlock) void norm_finish_kernel(const double* __restrict__ part, int G,
+                                                                double* __restrict__ out,
+                                                                const double* __restrict__ nf) {
+    norm_finish_body(part, G, out, nf);
 }
 
 __global__ void fill_kernel(double* x, int64_t n, double v) {
@@ -124,12 +138,11 @@ __device__ __forceinline__ void load_quad(const bf16_t* p, double (&o)[4]) {
 // keeps two interleaved sums (even and odd columns).  Needs B and ldb aligned
 // to four entries; the n % 4 last rows are done by block 0 one per thread.
 constexpr int kCombineCols = 16;
+// Block blk of nblk; the n % 4 last rows by block 0.
 template <typename TS>
-__global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, const int* __restrict__ d_eff_p,
-                                                                 const TS* __restrict__ B, int64_t ldb,
-                                                                 const double* __restrict__ y,
-                                                                 double* __restrict__ x,
-                                                                 const double* __restrict__ cn) {
+__device__ __forceinline__ void combine4_body(int blk, int nblk, int64_t n, const int* __restrict__ d_eff_p,
+                                              const TS* __restrict__ B, int64_t ldb, const double* __restrict__ y,
+                                              double* __restrict__ x, const double* __restrict__ cn) {
     extern __shared__ double ys[];
     const int d_eff = *d_eff_p;
     for (int c = threadIdx.x; c < d_eff; c += kCombineBlock)
@@ -137,8 +150,8 @@ __global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, cons
     __syncthreads();
     if (d_eff <= 0) return;
     const int64_t nq = n / 4;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kCombineBlock;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kCombineBlock + threadIdx.x; t < nq; t += stride) {
+    const int64_t stride = static_cast<int64_t>(nblk) * kCombineBlock;
+    for (int64_t t = static_cast<int64_t>(blk) * kCombineBlock + threadIdx.x; t < nq; t += stride) {
         const int64_t i0 = 4 * t;
         double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
         int c = 0;
@@ -160,7 +173,7 @@ __global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, cons
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[i0 + r] += acc[r][0] + acc[r][1];
     }
-    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    if (blk == 0 && threadIdx.x < (n & 3)) {
         const int64_t i = 4 * nq + threadIdx.x;
         double a0 = 0.0, a1 = 0.0;
         for (int c = 0; c < d_eff; ++c) {
@@ -170,6 +183,55 @@ __global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, cons
         }
         x[i] += a0 + a1;
     }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(kCombineBlock) void combine4_kernel(int64_t n, const int* __restrict__ d_eff_p,
+                                                                 const TS* __restrict__ B, int64_t ldb,
+                                                                 const double* __restrict__ y,
+                                                                 double* __restrict__ x,
+                                                                 const double* __restrict__ cn) {
+    combine4_body<TS>(blockIdx.x, gridDim.x, n, d_eff_p, B, ldb, y, x, cn);
+}
+
+// ---- the tails of several systems' cycles, one launch per kernel ----------
+// Each job's blocks run as the single-system launch would with its own grid
+// (combine4_grid / vec_grid of its n), so every system gets the bits of
+// launch_combine, launch_residual and launch_norm_finish.
+
+// the job whose blocks [first, first + count) hold block b (jobs in block order)
+__device__ __forceinline__ int tail_job_of(const TailJob* __restrict__ jobs, int njobs, int b, bool combine) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if ((combine ? jobs[mid].cblk0 : jobs[mid].rblk0) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename TS>
+__global__ __launch_bounds__(kCombineBlock) void combine4_jobs_kernel(const TailJob* __restrict__ jobs, int njobs) {
+    __shared__ int sj;
+    if (threadIdx.x == 0) sj = tail_job_of(jobs, njobs, blockIdx.x, true);
+    __syncthreads();
+    const TailJob& J = jobs[sj];
+    if (J.cnblk == 0) return;  // this system's combine is launched on its own
+    combine4_body<TS>(blockIdx.x - J.cblk0, J.cnblk, J.n, J.d_eff, static_cast<const TS*>(J.B), J.ldb, J.y, J.x,
+                      nullptr);
+}
+
+__global__ __launch_bounds__(kVecBlock) void residual_jobs_kernel(const TailJob* __restrict__ jobs, int njobs) {
+    __shared__ int sj;
+    if (threadIdx.x == 0) sj = tail_job_of(jobs, njobs, blockIdx.x, false);
+    __syncthreads();
+    const TailJob& J = jobs[sj];
+    residual_body(blockIdx.x - J.rblk0, J.rnblk, J.n, J.rp, J.ci, J.val, J.f, J.x, J.r, J.part);
+}
+
+__global__ __launch_bounds__(kVecBlock) void norm_jobs_kernel(const TailJob* __restrict__ jobs) {
+    const TailJob& J = jobs[blockIdx.x];
+    norm_finish_body(J.part, J.rnblk, J.beta, J.nf);
 }
 
 // bad[0] = 1 if row_ptr is not a valid prefix array for nnz entries or a
@@ -231,6 +293,34 @@ hipError_t launch_norm_finish(const double* part, int G, double* out, const doub
     return hipGetLastError();
 }
 
+int combine4_grid(int64_t n) {
+    int64_t g4 = (n / 4 + kCombineBlock - 1) / kCombineBlock;
+    if (g4 > 2048) g4 = 2048;
+    if (g4 < 1) g4 = 1;
+    return static_cast<int>(g4);
+}
+
+hipError_t launch_tail_jobs(const TailJob* jobs, int njobs, int cblocks, int rblocks, int d_max, int precision,
+                            hipStream_t stream) {
+    if (njobs <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (d_max > 0 ? d_max : 1);
+    if (cblocks > 0) {
+        if (precision == SGMRES_PREC_FP32)
+            combine4_jobs_kernel<float><<<cblocks, kCombineBlock, lds, stream>>>(jobs, njobs);
+        else if (precision == SGMRES_PREC_BF16_BASIS)
+            combine4_jobs_kernel<bf16_t><<<cblocks, kCombineBlock, lds, stream>>>(jobs, njobs);
+        else
+            combine4_jobs_kernel<double><<<cblocks, kCombineBlock, lds, stream>>>(jobs, njobs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    residual_jobs_kernel<<<rblocks, kVecBlock, 0, stream>>>(jobs, njobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    norm_jobs_kernel<<<njobs, kVecBlock, 0, stream>>>(jobs);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     int64_t g = (n + 255) / 256;
@@ -257,9 +347,7 @@ hipError_t launch_combine(int64_t n, const int* d_eff, int d_max, const void* B,
     const size_t esz = precision == SGMRES_PREC_FP32 ? 4 : precision == SGMRES_PREC_BF16_BASIS ? 2 : 8;
     const size_t qa = esz == 8 ? 16 : 4 * esz;
     if (((reinterpret_cast<uintptr_t>(B) | static_cast<uintptr_t>(ldb) * esz) % qa) == 0 && n >= 4) {
-        int64_t g4 = (n / 4 + kCombineBlock - 1) / kCombineBlock;
-        if (g4 > 2048) g4 = 2048;
-        if (g4 < 1) g4 = 1;
+        const int g4 = combine4_grid(n);
         if (precision == SGMRES_PREC_FP32)
             combine4_kernel<float><<<static_cast<int>(g4), kCombineBlock, lds, stream>>>(
                 n, d_eff, static_cast<const float*>(B), ldb, y, x, colnorm);

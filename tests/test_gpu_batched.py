@@ -308,6 +308,27 @@ def test_multi_window_lengths(sg, orc, k, prec):
             assert r["relres"] <= info_o["relres"] + 1e-4, (A.n, r["relres"], info_o["relres"])
 
 
+def test_multi_tiny_systems(sg, orc):
+    """Systems of 1, 2, 3 and 5 rows next to a larger one in one multi-system
+    launch (d = 1; fewer than four rows: combined on their own, the rest in
+    the wave's combine launch); each against the oracle and, bit for bit,
+    against sgmres_solve at the same launch shape."""
+    d, k, s = 1, 1, 4
+    mats = [synth.random_dominant(n, offdiag=n - 1, seed=[7, n]) for n in (1, 2, 3, 5)]
+    mats.append(synth.random_dominant(3000, offdiag=6, seed=[7, 0]))
+    batch = [(A, synth.rhs(A.n, [5, i])) for i, A in enumerate(mats)]
+    rc, res, xs = _run(sg, batch, d, k, s, 0.0, 0, path=sg.PATH_MULTI, zeta=4)
+    for (A, b), r, x in zip(batch, res, xs):
+        rc_o, x_o, info_o = orc.sgmres_solve(A, b, d=d, k=k, s=s, zeta=4, seed=3, tol=0.0, restarts=0)
+        assert r["cycles"] == 1
+        assert np.linalg.norm(x - x_o) <= 1e-12 * np.linalg.norm(x_o), A.n
+        assert abs(r["relres"] - info_o["relres"]) <= 1e-12, A.n
+        x1 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc1, info = sg.sgmres_solve(sg.DeviceCSR.from_host(A), _t(b), x1, d, k, s, 3, 0.0, 0, zeta=4,
+                                    block_size=1024, rows_per_thread=4, halo_off=True)
+        assert np.array_equal(_np(x1), x) and r["relres"] == info["relres"], A.n
+
+
 def test_multi_waves(sg, orc):
     """More groups than fit one launch: 40 systems of 40,000-70,000 rows (10 to
     18 workgroups of 4096 rows each, about 560 in all) run in several waves;
