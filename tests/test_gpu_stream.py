@@ -237,6 +237,26 @@ def test_stream_full_size_one_cycle_reduced_precision(sg, cd2048, cd2048_oracle_
         assert err < 0.1 and ratio < 10.0
 
 
+def test_stream_full_size_lucky_breakdown(sg, orc):
+    """A = diag(1..n) at n = 4,194,304 (the 16-rows-per-thread launch) and b
+    with three nonzeros: the Krylov space is invariant after three columns;
+    every workgroup stops at the same step and the solution is exact."""
+    n = 1 << 22
+    A = synth.diagonal(np.arange(1.0, n + 1.0))
+    f = np.zeros(n)
+    f[[0, 5000, n - 1]] = (1.0, -2.0, 3.0)
+    rc, x, info = _gpu(sg, A, f, 200, 4, 400, 0, 0.0, 0)
+    assert info["path"] == sg.PATH_STREAM and info["launch_rows"] == 16
+    rc_o, x_o, info_o = orc.sgmres_solve(A, f, d=200, k=4, s=400, zeta=8, seed=0, tol=0.0, restarts=0)
+    assert info["flags"] & sg.FLAG_BREAKDOWN and info_o["flags"] & sg.FLAG_BREAKDOWN
+    assert info["steps"] == info_o["steps"] == 3
+    assert np.count_nonzero(x) == 3
+    # the three-column least squares has kappa ~ 4e6 (the oracle's x is off
+    # the exact f / diag(A) by 8e-11 in its smallest entry)
+    assert np.allclose(x, x_o, rtol=1e-8, atol=0.0)
+    assert np.allclose(x[[0, 5000, n - 1]], f[[0, 5000, n - 1]] / np.array([1.0, 5001.0, float(n)]), rtol=1e-8)
+
+
 @pytest.fixture(scope="module")
 def cd2040_with_oracle_cycle(orc):
     A = synth.convection_diffusion(2040, (50.0, 20.0))
