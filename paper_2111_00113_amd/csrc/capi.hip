@@ -136,6 +136,10 @@ struct Workspace {
     size_t wv_jobs_cap = 0;
     TailJob* wv_tail = nullptr;  // per wave: the systems' combine, residual and norm
     size_t wv_tail_cap = 0;
+    TailJob* wv_tail0 = nullptr;  // the systems' |b| and first residual
+    size_t wv_tail0_cap = 0;
+    int64_t* wv_sp = nullptr;  // the systems' sliced ELL slice starts, one after another
+    size_t wv_sp_cap = 0;
     double* wv_tpart = nullptr;  // their residual block partials (one wave at a time)
     size_t wv_tpart_cap = 0;
     unsigned* sync = nullptr;  // grid-barrier words of the basis kernel
@@ -1401,20 +1405,23 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
     std::vector<int> K(static_cast<size_t>(koff[nsys]));
     SG_TRY(hipMemcpyAsync(K.data(), ws.wv_K, sizeof(int) * K.size(), hipMemcpyDeviceToHost, st));
     SG_TRY(hipStreamSynchronize(st));
-    // per-system arena: sp, col, val, r, SAB, H, g, y
-    std::vector<std::vector<int64_t>> sp(nsys);
+    // slice starts of all systems in one array (one copy); per-system arena:
+    // col, val, r, SAB, H, g, y
+    std::vector<int64_t> sp(static_cast<size_t>(koff[nsys] + nsys), 0);
     std::vector<size_t> off(nsys + 1, 0);
     for (int i = 0; i < nsys; ++i) {
         const int64_t n = systems[i].A.n, nsl = (n + 63) / 64;
-        sp[i].assign(static_cast<size_t>(nsl + 1), 0);
-        for (int64_t q = 0; q < nsl; ++q) sp[i][q + 1] = sp[i][q] + 64 * static_cast<int64_t>(K[koff[i] + q]);
-        const size_t tot = static_cast<size_t>(sp[i][nsl] > 0 ? sp[i][nsl] : 1);
-        size_t b = align_up(8 * (nsl + 1)) + align_up(4 * tot) + align_up(ev * tot) + align_up(8 * static_cast<size_t>(n));
+        int64_t* spi = sp.data() + koff[i] + i;
+        for (int64_t q = 0; q < nsl; ++q) spi[q + 1] = spi[q] + 64 * static_cast<int64_t>(K[koff[i] + q]);
+        const size_t tot = static_cast<size_t>(spi[nsl] > 0 ? spi[nsl] : 1);
+        size_t b = align_up(4 * tot) + align_up(ev * tot) + align_up(8 * static_cast<size_t>(n));
         b += align_up(8 * static_cast<size_t>(s) * d) + align_up(8 * static_cast<size_t>(kk + 1) * d) +
              align_up(8 * static_cast<size_t>(s)) + 2 * align_up(8 * static_cast<size_t>(d));
         off[i + 1] = off[i] + b;
     }
     SG_TRY(ensure(ws.wv_sys_arena, ws.wv_sys_arena_cap, off[nsys]));
+    SG_TRY(ensure(ws.wv_sp, ws.wv_sp_cap, sp.size()));
+    SG_TRY(hipMemcpyAsync(ws.wv_sp, sp.data(), sizeof(int64_t) * sp.size(), hipMemcpyHostToDevice, st));
     SG_TRY(ensure(ws.wv_sys, ws.wv_sys_cap, static_cast<size_t>(nsys)));
     SG_TRY(ensure(ws.wv_st, ws.wv_st_cap, static_cast<size_t>(nsys)));
     SG_TRY(ensure(ws.part_vec, ws.part_vec_cap, static_cast<size_t>(kMaxVecGrid)));
@@ -1429,11 +1436,11 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
     for (int i = 0; i < nsys; ++i) {
         const sgmres_csr_t& A = systems[i].A;
         const int64_t n = A.n, nsl = (n + 63) / 64;
-        const size_t tot = static_cast<size_t>(sp[i][nsl] > 0 ? sp[i][nsl] : 1);
+        const int64_t* spi = sp.data() + koff[i] + i;
+        const size_t tot = static_cast<size_t>(spi[nsl] > 0 ? spi[nsl] : 1);
         unsigned char* q = ws.wv_sys_arena + off[i];
         SysBufs& B = sb[i];
-        B.sp = reinterpret_cast<int64_t*>(q);
-        q += align_up(8 * (nsl + 1));
+        B.sp = ws.wv_sp + koff[i] + i;
         B.col = reinterpret_cast<int32_t*>(q);
         q += align_up(4 * tot);
         B.val = q;
@@ -1449,7 +1456,6 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         B.y = reinterpret_cast<double*>(q);
         q += align_up(8 * static_cast<size_t>(d));
         B.tau = reinterpret_cast<double*>(q);
-        SG_TRY(hipMemcpyAsync(B.sp, sp[i].data(), sizeof(int64_t) * (nsl + 1), hipMemcpyHostToDevice, st));
         SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, B.sp, B.col, B.val, prec, st));
         BatchSys& D = desc[i];
         D = BatchSys{};
@@ -1470,14 +1476,40 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
                            0u, st));
     SG_TRY(hipMemsetAsync(&ws.sc->abort, 0, sizeof(int), st));
 
-    // ---- |b| and the first residual --------------------------------------
-    for (int i = 0; i < nsys; ++i) {
-        const sgmres_csr_t& A = systems[i].A;
-        BatchState* t = ws.wv_st + i;
-        SG_TRY(launch_residual(A.n, nullptr, nullptr, nullptr, systems[i].b, nullptr, sb[i].r, ws.part_vec, st));
-        SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(A.n), &t->nf, nullptr, st));
-        SG_TRY(launch_residual(A.n, A.row_ptr, A.col_idx, A.val, systems[i].b, systems[i].x, sb[i].r, ws.part_vec, st));
-        SG_TRY(launch_norm_finish(ws.part_vec, vec_grid(A.n), &t->beta, &t->nf, st));
+    // ---- |b| and the first residual of every system: two passes of the
+    // tail jobs without a combine (the bits of launch_residual and
+    // launch_norm_finish per system) ----------------------------------------
+    std::vector<TailJob> t0(2 * static_cast<size_t>(nsys));  // read by a copy: kept to the next synchronisation
+    {
+        int rb = 0;
+        for (int i = 0; i < nsys; ++i) {
+            const sgmres_csr_t& A = systems[i].A;
+            TailJob& a = t0[i];
+            a = TailJob{};
+            a.n = A.n;
+            a.f = systems[i].b;
+            a.r = sb[i].r;
+            a.rblk0 = rb;
+            a.rnblk = vec_grid(A.n);
+            a.part = nullptr;  // set below, once the partial buffer is sized
+            a.beta = &ws.wv_st[i].nf;  // pass 1: r = b, out[0] = |b|
+            rb += a.rnblk;
+            TailJob& c = t0[nsys + i];
+            c = a;
+            c.rp = A.row_ptr;
+            c.ci = A.col_idx;
+            c.val = A.val;
+            c.x = systems[i].x;
+            c.beta = &ws.wv_st[i].beta;  // pass 2: r = b - A x0, beta and rho
+            c.nf = &ws.wv_st[i].nf;
+        }
+        SG_TRY(ensure(ws.wv_tpart, ws.wv_tpart_cap,
+                      std::max(static_cast<size_t>(rb), static_cast<size_t>(L.capacity) * kMaxVecGrid)));
+        for (auto& j : t0) j.part = ws.wv_tpart + j.rblk0;
+        SG_TRY(ensure(ws.wv_tail0, ws.wv_tail0_cap, t0.size()));
+        SG_TRY(hipMemcpyAsync(ws.wv_tail0, t0.data(), sizeof(TailJob) * t0.size(), hipMemcpyHostToDevice, st));
+        SG_TRY(launch_tail_jobs(ws.wv_tail0, nsys, 0, rb, d, prec, st));
+        SG_TRY(launch_tail_jobs(ws.wv_tail0 + nsys, nsys, 0, rb, d, prec, st));
     }
     std::vector<BatchState> hs(nsys);
     auto read_states = [&]() -> int {
@@ -2212,7 +2244,8 @@ void sgmres_release_workspace(void) {
                         w.sell_val, w.sync, w.sc, w.t_rp, w.t_ci, w.t_val,
                         w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
                         w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr, w.wv_sys_arena, w.wv_wave_arena, w.wv_K,
-                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st, w.wv_jobs, w.wv_tail, w.wv_tpart};
+                        w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st, w.wv_jobs, w.wv_tail, w.wv_tpart, w.wv_tail0,
+                        w.wv_sp};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);
