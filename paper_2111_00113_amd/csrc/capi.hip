@@ -138,6 +138,8 @@ struct Workspace {
     size_t wv_tail_cap = 0;
     TailJob* wv_tail0 = nullptr;  // the systems' |b| and first residual
     size_t wv_tail0_cap = 0;
+    SellJob* wv_sell = nullptr;  // the systems' sliced ELL builds
+    size_t wv_sell_cap = 0;
     int64_t* wv_sp = nullptr;  // the systems' sliced ELL slice starts, one after another
     size_t wv_sp_cap = 0;
     double* wv_tpart = nullptr;  // their residual block partials (one wave at a time)
@@ -1401,7 +1403,24 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
     std::vector<int64_t> koff(nsys + 1, 0);
     for (int i = 0; i < nsys; ++i) koff[i + 1] = koff[i] + (systems[i].A.n + 63) / 64;
     SG_TRY(ensure(ws.wv_K, ws.wv_K_cap, static_cast<size_t>(koff[nsys])));
-    for (int i = 0; i < nsys; ++i) SG_TRY(launch_sell_width(systems[i].A.n, systems[i].A.row_ptr, ws.wv_K + koff[i], st));
+    // one launch for all systems' widths, one for all fills (below)
+    std::vector<SellJob> sj(nsys);  // read by copies: kept to the synchronisations below
+    int wblocks = 0;
+    for (int i = 0; i < nsys; ++i) {
+        SellJob& J = sj[i];
+        J = SellJob{};
+        J.n = systems[i].A.n;
+        J.rp = systems[i].A.row_ptr;
+        J.ci = systems[i].A.col_idx;
+        J.val = systems[i].A.val;
+        J.K = ws.wv_K + koff[i];
+        J.wblk0 = wblocks;
+        J.wnblk = sell_width_blocks(J.n);
+        wblocks += J.wnblk;
+    }
+    SG_TRY(ensure(ws.wv_sell, ws.wv_sell_cap, static_cast<size_t>(nsys)));
+    SG_TRY(hipMemcpyAsync(ws.wv_sell, sj.data(), sizeof(SellJob) * nsys, hipMemcpyHostToDevice, st));
+    SG_TRY(launch_sell_jobs(ws.wv_sell, nsys, wblocks, false, prec, st));
     std::vector<int> K(static_cast<size_t>(koff[nsys]));
     SG_TRY(hipMemcpyAsync(K.data(), ws.wv_K, sizeof(int) * K.size(), hipMemcpyDeviceToHost, st));
     SG_TRY(hipStreamSynchronize(st));
@@ -1433,6 +1452,7 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
     };
     std::vector<SysBufs> sb(nsys);
     std::vector<BatchSys> desc(nsys);
+    int fblocks = 0;
     for (int i = 0; i < nsys; ++i) {
         const sgmres_csr_t& A = systems[i].A;
         const int64_t n = A.n, nsl = (n + 63) / 64;
@@ -1456,7 +1476,13 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         B.y = reinterpret_cast<double*>(q);
         q += align_up(8 * static_cast<size_t>(d));
         B.tau = reinterpret_cast<double*>(q);
-        SG_TRY(launch_sell_fill(n, A.row_ptr, A.col_idx, A.val, B.sp, B.col, B.val, prec, st));
+        SellJob& J = sj[i];
+        J.sp = B.sp;
+        J.scol = B.col;
+        J.sval = B.val;
+        J.fblk0 = fblocks;
+        J.fnblk = sell_fill_blocks(n);
+        fblocks += J.fnblk;
         BatchSys& D = desc[i];
         D = BatchSys{};
         D.n = n;
@@ -1470,6 +1496,8 @@ int wave_solve_locked(int nsys, const sgmres_system_t* systems, int d, int k, in
         D.g = B.g;
         D.y = B.y;
     }
+    SG_TRY(hipMemcpyAsync(ws.wv_sell, sj.data(), sizeof(SellJob) * nsys, hipMemcpyHostToDevice, st));
+    SG_TRY(launch_sell_jobs(ws.wv_sell, nsys, fblocks, true, prec, st));
     SG_TRY(hipMemcpyAsync(ws.wv_sys, desc.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
     SG_TRY(hipStreamSynchronize(st));  // the host vectors above are read by the copies
     SG_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(ws.wv_st), static_cast<int64_t>(sizeof(BatchState) / 4) * nsys,
@@ -2245,7 +2273,7 @@ void sgmres_release_workspace(void) {
                         w.t_scratch, w.st_lists, w.st_part, w.st_state, w.mr_F, w.mr_X, w.mr_R,
                         w.mr_part, w.mr_scal, w.mr_int, w.mr_ptr, w.wv_sys_arena, w.wv_wave_arena, w.wv_K,
                         w.wv_ps, w.wv_idx, w.wv_sys, w.wv_st, w.wv_jobs, w.wv_tail, w.wv_tpart, w.wv_tail0,
-                        w.wv_sp};
+                        w.wv_sp, w.wv_sell};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (w.host_sc) (void)hipHostFree(w.host_sc);

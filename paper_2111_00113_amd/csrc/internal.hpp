@@ -330,6 +330,25 @@ hipError_t launch_lsq_batched(int nsys, int s, const BatchSys* sys, BatchState* 
 // of 64 K; scol / sval (sval in the basis arithmetic type: double for
 // SGMRES_PREC_FP64, float otherwise) hold sp[nslices] entries.
 hipError_t launch_sell_width(int64_t n, const int32_t* rp, int* K, hipStream_t stream);
+// Several matrices' width or fill passes in one launch (the batched solve):
+// each job's blocks [wblk0, wblk0 + wnblk) / [fblk0, fblk0 + fnblk) do what
+// launch_sell_width / launch_sell_fill do for that matrix; jobs in block order.
+struct SellJob {
+    int64_t n;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+    int* K;             // width pass output, (n + 63) / 64 entries
+    const int64_t* sp;  // fill pass input
+    int32_t* scol;
+    void* sval;
+    int wblk0, wnblk;
+    int fblk0, fnblk;
+};
+int sell_width_blocks(int64_t n);
+int sell_fill_blocks(int64_t n);
+hipError_t launch_sell_jobs(const SellJob* jobs, int njobs, int blocks, bool fill, int precision,
+                            hipStream_t stream);
 hipError_t launch_sell_fill(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const int64_t* sp,
                             int32_t* scol, void* sval, int precision, hipStream_t stream);
 

@@ -12,9 +12,11 @@ namespace sg {
 
 namespace {
 
-__global__ void sell_width_kernel(int64_t n, const int32_t* __restrict__ rp, int64_t nsl, int* __restrict__ K) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t sl = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; sl < nsl; sl += stride) {
+// block blk of nblk of one matrix's width pass: slice widths into K
+__device__ __forceinline__ void sell_width_body(int blk, int nblk, int64_t n, const int32_t* __restrict__ rp,
+                                                int64_t nsl, int* __restrict__ K) {
+    const int64_t stride = static_cast<int64_t>(nblk) * blockDim.x;
+    for (int64_t sl = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x; sl < nsl; sl += stride) {
         int k = 0;
         for (int l = 0; l < kWave; ++l) {
             const int64_t row = sl * kWave + l;
@@ -24,12 +26,18 @@ __global__ void sell_width_kernel(int64_t n, const int32_t* __restrict__ rp, int
     }
 }
 
+__global__ void sell_width_kernel(int64_t n, const int32_t* __restrict__ rp, int64_t nsl, int* __restrict__ K) {
+    sell_width_body(blockIdx.x, gridDim.x, n, rp, nsl, K);
+}
+
+// block blk of nblk of one matrix's fill pass
 template <typename TC>
-__global__ void sell_fill_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                 const double* __restrict__ val, int64_t nsl, const int64_t* __restrict__ sp,
-                                 int32_t* __restrict__ scol, TC* __restrict__ sval) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t row = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; row < nsl * kWave; row += stride) {
+__device__ __forceinline__ void sell_fill_body(int blk, int nblk, int64_t n, const int32_t* __restrict__ rp,
+                                               const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                               int64_t nsl, const int64_t* __restrict__ sp, int32_t* __restrict__ scol,
+                                               TC* __restrict__ sval) {
+    const int64_t stride = static_cast<int64_t>(nblk) * blockDim.x;
+    for (int64_t row = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x; row < nsl * kWave; row += stride) {
         const int64_t sl = row / kWave;
         const int64_t base = sp[sl] + (row - sl * kWave);
         const int K = static_cast<int>((sp[sl + 1] - sp[sl]) / kWave);
@@ -44,6 +52,43 @@ __global__ void sell_fill_kernel(int64_t n, const int32_t* __restrict__ rp, cons
     }
 }
 
+template <typename TC>
+__global__ void sell_fill_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const double* __restrict__ val, int64_t nsl, const int64_t* __restrict__ sp,
+                                 int32_t* __restrict__ scol, TC* __restrict__ sval) {
+    sell_fill_body<TC>(blockIdx.x, gridDim.x, n, rp, ci, val, nsl, sp, scol, sval);
+}
+
+// several matrices per launch: the job whose blocks hold block b (jobs in
+// block order; first block blk0 of each pass)
+__device__ __forceinline__ int sell_job_of(const SellJob* __restrict__ jobs, int njobs, int b, bool fill) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if ((fill ? jobs[mid].fblk0 : jobs[mid].wblk0) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void sell_width_jobs_kernel(const SellJob* __restrict__ jobs, int njobs) {
+    __shared__ int sj;
+    if (threadIdx.x == 0) sj = sell_job_of(jobs, njobs, blockIdx.x, false);
+    __syncthreads();
+    const SellJob& J = jobs[sj];
+    sell_width_body(blockIdx.x - J.wblk0, J.wnblk, J.n, J.rp, (J.n + kWave - 1) / kWave, J.K);
+}
+
+template <typename TC>
+__global__ void sell_fill_jobs_kernel(const SellJob* __restrict__ jobs, int njobs) {
+    __shared__ int sj;
+    if (threadIdx.x == 0) sj = sell_job_of(jobs, njobs, blockIdx.x, true);
+    __syncthreads();
+    const SellJob& J = jobs[sj];
+    sell_fill_body<TC>(blockIdx.x - J.fblk0, J.fnblk, J.n, J.rp, J.ci, J.val, (J.n + kWave - 1) / kWave, J.sp,
+                       J.scol, static_cast<TC*>(J.sval));
+}
+
 int grid_for(int64_t items) {
     int64_t g = (items + 255) / 256;
     if (g < 1) g = 1;
@@ -52,6 +97,21 @@ int grid_for(int64_t items) {
 }
 
 }  // namespace
+
+int sell_width_blocks(int64_t n) { return grid_for((n + kWave - 1) / kWave); }
+int sell_fill_blocks(int64_t n) { return grid_for((n + kWave - 1) / kWave * kWave); }
+
+hipError_t launch_sell_jobs(const SellJob* jobs, int njobs, int blocks, bool fill, int precision,
+                            hipStream_t stream) {
+    if (njobs <= 0 || blocks <= 0) return hipSuccess;
+    if (!fill)
+        sell_width_jobs_kernel<<<blocks, 256, 0, stream>>>(jobs, njobs);
+    else if (precision == SGMRES_PREC_FP64)
+        sell_fill_jobs_kernel<double><<<blocks, 256, 0, stream>>>(jobs, njobs);
+    else
+        sell_fill_jobs_kernel<float><<<blocks, 256, 0, stream>>>(jobs, njobs);
+    return hipGetLastError();
+}
 
 hipError_t launch_sell_width(int64_t n, const int32_t* rp, int* K, hipStream_t stream) {
     const int64_t nsl = (n + kWave - 1) / kWave;
