@@ -41,7 +41,7 @@ MEASURED_TRAFFIC = {
                                     "bytes_per_launch": 1.9677e+10},
     ("chebyshev", "cd1024", "fp64"): {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "89b649c8bc2a4748",
                                       "bytes_per_launch": 1.5474e+10},
-    ("stream", "cd2048", "fp32"): {"files": ("stream_kernel.hpp", "common.hpp"), "source_hash": "f22cecf34dd3c542",
+    ("stream", "cd2048", "fp32"): {"files": ("stream_kernel.hpp", "common.hpp"), "source_hash": "1f6c18b28c8d7639",
                                    "bytes_per_launch": 3.8233e+10},
 }
 

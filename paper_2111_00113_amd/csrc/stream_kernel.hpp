@@ -18,6 +18,7 @@
 // Per step j (two tagged reductions and one grid barrier):
 //   phase 1  m = A b_j; per right-hand side partials <m,m>, W^T m  (tagged)
 //   phase 2  h = W^T m; w = m - W h; partials <w,w>, W^T w           (tagged)
+//            (HBM state: w is not stored; phase 3 forms it again from m)
 //   phase 3  h2 = W^T w; nu^2 = <w,w> - |h2|^2 (window orthonormal to
 //            rounding); b_{j+1} = (w - W h2) / nu; H column j   -- barrier --
 // With REG state (one tile per block) m and w stay in registers for the whole
@@ -379,8 +380,9 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
 #pragma unroll
                     for (int a = 0; a < kStreamMaxK; ++a)
                         if (a < kw) acc[1 + a] = dot_acc(acc[1 + a], wa[a], w);
-                    if constexpr (HST) state[q] = w;
-                    else mreg[pp] = w;
+                    // HBM state keeps m: phase 3 forms w again from it (the
+                    // same operations), which saves writing w back
+                    if constexpr (!HST) mreg[pp] = w;
                 }
                 // WP pairs' window loads in flight at a time: keeps the
                 // register state of many pairs from spilling
@@ -440,6 +442,12 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
 #pragma unroll
                         for (int a = 0; a < kStreamMaxK; ++a)
                             wa[a] = a < kw ? (HST ? ldW(a, q, pp * kBlock + tid) : wwin(a, pp, q)) : TC(0);
+                        if constexpr (HST) {
+                            // w = m - W h, as in phase 2
+#pragma unroll
+                            for (int a = 0; a < kStreamMaxK; ++a)
+                                if (a < kw) w = gs_sub(w, static_cast<TC>(coefA[(1 + a) * NR + rhs]), wa[a]);
+                        }
 #pragma unroll
                         for (int a = 0; a < kStreamMaxK; ++a)
                             if (a < kw) w = gs_sub(w, static_cast<TC>(coefB[(1 + a) * NR + rhs]), wa[a]);
