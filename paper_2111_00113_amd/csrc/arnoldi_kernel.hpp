@@ -156,6 +156,31 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
         }
     }
 
+    // Halo mode: nonzero slot q of the wavefront's 64 rows of chunk r whose
+    // column is the row plus the same offset in every lane (a diagonal of A
+    // across the slice, as in banded and grid operators) keeps that offset in
+    // LDS, and the SpMV forms those columns instead of loading them; other
+    // slots (and q >= 16) read the column index array.  Found once per cycle
+    // from the column indices themselves.
+    constexpr int kOffSlots = 16;
+    constexpr int kIrregular = INT_MIN;
+    __shared__ int hoff[HALO ? NW * R * kOffSlots : 1];
+    if constexpr (HALO) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+            for (int q = 0; q < kOffSlots; ++q) {
+                int o = kIrregular;
+                if (q < sK[r]) {
+                    const int d = p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane] - static_cast<int>(row);
+                    const int d0 = __builtin_amdgcn_readfirstlane(d);
+                    if (__all(d == d0)) o = d0;
+                }
+                if (lane == 0) hoff[(wid * R + r) * kOffSlots + q] = o;
+            }
+        }
+    }
+
     // ---- sketch lists of the block's rows, sorted by sketch row --------------
     sketch_lists_build<R, BLOCK, true>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
                                  lcount, lists);
@@ -308,6 +333,14 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
             // step at cd1024 in FP32)
             int c[R], cn[R];
             TC v[R], vn[R];
+            // column of slot q of chunk r: the row plus the slot's offset, or
+            // loaded (the offset is wavefront-uniform)
+            auto col_of = [&](int r, int q, int64_t e) -> int {
+                const int o =
+                    q < kOffSlots ? __builtin_amdgcn_readfirstlane(hoff[(wid * R + r) * kOffSlots + q]) : kIrregular;
+                if (o != kIrregular) return static_cast<int>(base + static_cast<int64_t>(r) * BLOCK) + o;
+                return p.ci[e];
+            };
             auto load_slot = [&](int q, int (&cd)[R], TC (&vd)[R]) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -315,7 +348,7 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
                     vd[r] = TC(0);
                     if (q < sK[r]) {
                         const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave + lane;
-                        cd[r] = p.ci[e];
+                        cd[r] = col_of(r, q, e);
                         vd[r] = Av[e];
                     }
                 }
@@ -329,7 +362,7 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     cd[r] = -1;
-                    if (q < sK[r]) cd[r] = p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane];
+                    if (q < sK[r]) cd[r] = col_of(r, q, spos[r] + static_cast<int64_t>(q) * kWave + lane);
                 }
             };
             if constexpr (kLook) load_slot(0, c, v);
