@@ -86,6 +86,25 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
             }
         }
     }
+    // nonzero slot q of the wavefront's 64 rows of chunk r whose column is the
+    // row plus the same offset in every lane keeps that offset in LDS; the
+    // SpMV forms those columns instead of loading them (found once per cycle)
+    constexpr int kOffSlots = 16;
+    constexpr int kIrregular = INT_MIN;
+    __shared__ int soff[NW * R * kOffSlots];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+        for (int q = 0; q < kOffSlots; ++q) {
+            int o = kIrregular;
+            if (q < sK[r]) {
+                const int d = p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane] - static_cast<int>(row);
+                const int d0 = __builtin_amdgcn_readfirstlane(d);
+                if (__all(d == d0)) o = d0;
+            }
+            if (lane == 0) soff[(wid * R + r) * kOffSlots + q] = o;
+        }
+    }
     sketch_lists_build<R, BLOCK, true>(p.seed, p.cycle, base, n, s, zeta, reinterpret_cast<uint16_t*>(vals), lstart,
                                  lcount, lists);
 
@@ -162,7 +181,9 @@ __global__ __launch_bounds__(BLOCK) void chebyshev_kernel(ChebParams p) {
                 vd[r] = TC(0);
                 if (q < sK[r]) {
                     const int64_t e = spos[r] + static_cast<int64_t>(q) * kWave + lane;
-                    cd[r] = p.ci[e];
+                    const int o = q < kOffSlots ? __builtin_amdgcn_readfirstlane(soff[(wid * R + r) * kOffSlots + q])
+                                                : kIrregular;
+                    cd[r] = o != kIrregular ? static_cast<int>(base + static_cast<int64_t>(r) * BLOCK) + o : p.ci[e];
                     vd[r] = Av[e];
                 }
             }
