@@ -181,6 +181,39 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
     }
     bar.sync();  // b_1 complete everywhere
 
+    // register state, one right-hand side: slot e of the wavefront's slice for
+    // pair pp whose column is the row plus the same offset in every lane (a
+    // diagonal of A across the slice) keeps that offset in LDS, and the SpMV
+    // forms those columns instead of loading them; found once per launch
+    constexpr bool kOff = !HST && NR == 1;
+    constexpr int kOffSlots = 16;
+    constexpr int kIrregular = INT_MIN;
+    __shared__ int doff[kOff ? kNW * P * kOffSlots : 1];
+    if constexpr (kOff) {
+        const int64_t nsl = (n + kWave - 1) / kWave;
+#pragma unroll
+        for (int pp = 0; pp < P; ++pp) {
+            const int64_t row0 = tbase + static_cast<int64_t>(pp) * kBlock + wid_s * kWave;  // the slice's first row
+            const int64_t sl = row0 / kWave;
+            int64_t a = 0;
+            int K = 0;
+            if (sl < nsl) {
+                a = p.sp[sl];
+                K = static_cast<int>((p.sp[sl + 1] - a) / kWave);
+            }
+            for (int e = 0; e < kOffSlots; ++e) {
+                int o = kIrregular;
+                if (e < K) {
+                    const int d = (p.ci + a)[e * kWave + (tid & (kWave - 1))] - static_cast<int>(row0 + (tid & (kWave - 1)));
+                    const int d0 = __builtin_amdgcn_readfirstlane(d);
+                    if (__all(d == d0)) o = d0;
+                }
+                if ((tid & (kWave - 1)) == 0) doff[(wid_s * P + pp) * kOffSlots + e] = o;
+            }
+        }
+        __syncthreads();
+    }
+
     TC mreg[HST ? 1 : P];
     // kept window entries: wk[h][pp] is entry NL + h of pair pp
     TC wk[KH > 0 ? KH : 1][KH > 0 ? P : 1];
@@ -244,6 +277,8 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
 #pragma unroll
                 for (int u = 0; u < PG; ++u) m[u] = TC(0);
                 // slot e's column indices and values of the PG pairs
+                const int doff0 = wid_s * P * kOffSlots;
+                const int row0 = static_cast<int>(tbase) + tid;  // (n < 2^31 in this path)
                 auto ld_slot = [&](int e, int (&c)[PG], TC (&v)[PG]) {
 #pragma unroll
                     for (int u = 0; u < PG; ++u) {
@@ -251,7 +286,10 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                         v[u] = TC(0);
                         if (e < sK[u]) {
                             const uint32_t a = static_cast<uint32_t>(e * kWave + lrow[u]);
-                            c[u] = (p.ci + spos[u])[a];
+                            int o = kIrregular;
+                            if constexpr (kOff)
+                                if (e < kOffSlots) o = __builtin_amdgcn_readfirstlane(doff[doff0 + (g0 + u) * kOffSlots + e]);
+                            c[u] = o != kIrregular ? row0 + (g0 + u) * kBlock + o : (p.ci + spos[u])[a];
                             v[u] = (Av + spos[u])[a];
                         }
                     }
