@@ -41,8 +41,8 @@ MEASURED_TRAFFIC = {
                                     "bytes_per_launch": 1.5813e+10},
     ("chebyshev", "cd1024", "fp64"): {"files": ("chebyshev.hip", "common.hpp"), "source_hash": "eb5be861a9705acd",
                                       "bytes_per_launch": 1.2882e+10},
-    ("stream", "cd2048", "fp32"): {"files": ("stream_kernel.hpp", "common.hpp"), "source_hash": "1f6c18b28c8d7639",
-                                   "bytes_per_launch": 3.8233e+10},
+    ("stream", "cd2048", "fp32"): {"files": ("stream_kernel.hpp", "common.hpp"), "source_hash": "4ece445a24a0ac75",
+                                   "bytes_per_launch": 2.2217e+10},
 }
 
 
