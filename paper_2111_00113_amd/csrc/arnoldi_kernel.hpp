@@ -169,10 +169,16 @@ __device__ __forceinline__ void arnoldi_body(const ArnoldiParams& p, const int G
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t row = base + static_cast<int64_t>(r) * BLOCK;
+            // the slots' column loads all in flight, then one vote per slot
+            int cs[kOffSlots];
+#pragma unroll
+            for (int q = 0; q < kOffSlots; ++q)
+                cs[q] = q < sK[r] ? p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane] : 0;
+#pragma unroll
             for (int q = 0; q < kOffSlots; ++q) {
                 int o = kIrregular;
                 if (q < sK[r]) {
-                    const int d = p.ci[spos[r] + static_cast<int64_t>(q) * kWave + lane] - static_cast<int>(row);
+                    const int d = cs[q] - static_cast<int>(row);
                     const int d0 = __builtin_amdgcn_readfirstlane(d);
                     if (__all(d == d0)) o = d0;
                 }

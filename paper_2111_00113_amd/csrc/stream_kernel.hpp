@@ -201,10 +201,15 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(StreamParams p) {
                 a = p.sp[sl];
                 K = static_cast<int>((p.sp[sl + 1] - a) / kWave);
             }
+            // the slots' column loads all in flight, then one vote per slot
+            int cs[kOffSlots];
+#pragma unroll
+            for (int e = 0; e < kOffSlots; ++e) cs[e] = e < K ? (p.ci + a)[e * kWave + (tid & (kWave - 1))] : 0;
+#pragma unroll
             for (int e = 0; e < kOffSlots; ++e) {
                 int o = kIrregular;
                 if (e < K) {
-                    const int d = (p.ci + a)[e * kWave + (tid & (kWave - 1))] - static_cast<int>(row0 + (tid & (kWave - 1)));
+                    const int d = cs[e] - static_cast<int>(row0 + (tid & (kWave - 1)));
                     const int d0 = __builtin_amdgcn_readfirstlane(d);
                     if (__all(d == d0)) o = d0;
                 }
