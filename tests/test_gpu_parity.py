@@ -322,6 +322,53 @@ def test_two_barrier_mode_bit_identical(sg, orc, prec):
     assert nrm / np.linalg.norm(_np(f)) <= 1e-10
 
 
+def _band_matrix(n, half, seed):
+    """Diagonally dominant band matrix, 2 half + 1 diagonals (fewer at the
+    ends), columns in ascending order."""
+    rng = np.random.default_rng(seed)
+    offs = np.arange(-half, half + 1)
+    rows, cols, vals = [], [], []
+    i = np.arange(n)
+    off_abs = np.zeros(n)
+    for o in offs:
+        if o == 0:
+            continue
+        keep = (i + o >= 0) & (i + o < n)
+        v = rng.standard_normal(int(keep.sum()))
+        rows.append(i[keep]), cols.append(i[keep] + o), vals.append(v)
+        np.add.at(off_abs, i[keep], np.abs(v))
+    rows.append(i), cols.append(i), vals.append(1.5 * off_abs + 1.0)
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, r + 1, 1)
+    return synth.CSR(n=n, row_ptr=np.cumsum(rp).astype(np.int32), col_idx=c.astype(np.int32), val=v)
+
+
+def test_two_barrier_wide_band_bit_identical(sg, orc):
+    """A band matrix with 25 nonzeros per row at four rows per thread: slots
+    up to 15 whose columns are a diagonal across the wavefront's slice are
+    formed from their offset, slots 16 to 24 and the end slices read the
+    column indices; the two-barrier solve must still give the three-barrier
+    bits, and reach the tolerance."""
+    A = _band_matrix(65536, 12, seed=5)
+    f = _t(synth.rhs(A.n, 0))
+    dA = sg.DeviceCSR.from_host(A)
+    outs = []
+    for halo_off in (False, True):
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        rc, info = sg.sgmres_solve(dA, f, x, 60, 4, 120, 3, 1e-10, 20, halo_off=halo_off, block_size=1024,
+                                   rows_per_thread=4)
+        assert info["launch_rows"] == 4
+        assert info["path"] == (sg.PATH_ARNOLDI_3BAR if halo_off else sg.PATH_ARNOLDI_HALO)
+        outs.append((_np(x), info["relres"], info["cycles"]))
+    assert np.array_equal(outs[1][0], outs[0][0])
+    assert outs[1][1] == outs[0][1] and outs[1][2] == outs[0][2]
+    _, nrm = orc.residual(A, _np(f), outs[0][0])
+    assert nrm / np.linalg.norm(_np(f)) <= 1e-10
+
+
 def test_solve_edge_cases(sg, orc):
     A = synth.convection_diffusion(12)
     dA = sg.DeviceCSR.from_host(A)
