@@ -71,7 +71,7 @@ def test_autograd_finite_differences(sg):
         L = ((x - xtt) ** 2).sum()
         if grad:
             L.backward()
-            return float(L), val.grad.cpu().numpy(), bt.grad.cpu().numpy()
+            return float(L.detach()), val.grad.cpu().numpy(), bt.grad.cpu().numpy()
         return float(L)
 
     L0, gv, gb = loss(A.val, b, grad=True)
